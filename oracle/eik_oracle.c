@@ -1,0 +1,608 @@
+/*
+ * CPU oracle for the first-order upwind Eikonal solve and its adjoint.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may link, load or call
+ * this file; only the tests, the smoke check and the benchmark's CPU-baseline
+ * leg use it.  It shares no code with the HIP path.
+ *
+ * Everything is plain, sequential binary64 arithmetic.  Build it with
+ * `-O2 -ffp-contract=off` and no fast-math: the operator is defined by
+ * separately rounded subtract / multiply / add, so no contraction to FMA is
+ * allowed anywhere.
+ *
+ * Grid layout: C-order [nz][ny][nx], x fastest; 2D grids have nz == 1.
+ *
+ * Operator (the paper's "true monotonicity" rounding, section "Achieving Exact
+ * Monotonicity with Finite Precision Arithmetic", extended to the one-sided
+ * case and to 3D):
+ *   a_k   = min of the two axis-k neighbours of the point (+inf off the grid),
+ *   q     = fl(h / v)  (speed field) or fl(h * s) (slowness field),
+ *   c     = fl(q * q),
+ *   T_k(r)= fl(d * d) with d = fl(r - a_k) when d > 0, else +0,
+ *   S(r)  = the T_k summed largest-first, i.e. in ascending order of a_k:
+ *           fl(fl(T_(0) + T_(1)) + T_(2)),
+ *   dbar  = the smallest binary64 r >= min_k a_k with S(r) >= c.
+ * S(r) >= c is the sign test of the paper's root function alpha evaluated in
+ * floating point; S is non-decreasing in r and non-increasing in every a_k, so
+ * dbar is monotone and causal in floating point (Theorem 1 then gives one fixed
+ * point for every schedule).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_SPEED 0
+#define ORC_SLOWNESS 1
+
+#define OP_DBAR 0   /* exact monotone rounding */
+#define OP_DHAT 1   /* reordered explicit formula (2D only) */
+#define OP_DTILDE 2 /* textbook explicit formula (2D only) */
+
+static uint64_t bits_of(double x) { uint64_t u; memcpy(&u, &x, 8); return u; }
+static double double_of(uint64_t u) { double x; memcpy(&x, &u, 8); return x; }
+
+/* ------------------------------------------------------------------------- */
+/* the operator                                                               */
+/* ------------------------------------------------------------------------- */
+
+static void sort3(double a[3]) {
+    double t;
+    if (a[1] < a[0]) { t = a[0]; a[0] = a[1]; a[1] = t; }
+    if (a[2] < a[1]) { t = a[1]; a[1] = a[2]; a[2] = t; }
+    if (a[1] < a[0]) { t = a[0]; a[0] = a[1]; a[1] = t; }
+}
+
+/* S(r) >= c for neighbour minima already sorted ascending. */
+static int reaches(double r, const double as[3], double c) {
+    double T[3];
+    for (int k = 0; k < 3; ++k) {
+        double d = r - as[k];
+        T[k] = (d > 0.0) ? d * d : 0.0;
+    }
+    double s = T[0] + T[1];
+    s = s + T[2];
+    return s >= c;
+}
+
+/* Any starting point for the search: the exact-arithmetic Godunov solution,
+ * trying one, two, then three upwind axes.  Its accuracy affects only how many
+ * predicate evaluations the search below needs, never its result. */
+static double textbook_guess(const double as[3], double c) {
+    double q = sqrt(c);
+    double g = as[0] + q;
+    if (g <= as[1]) return g;
+    double b1 = as[1] - as[0];
+    double disc = 2.0 * c - b1 * b1;
+    g = as[0] + 0.5 * (b1 + sqrt(disc > 0.0 ? disc : 0.0));
+    if (g <= as[2]) return g;
+    double b2 = as[2] - as[0];
+    double sb = b1 + b2;
+    disc = sb * sb - 3.0 * (b1 * b1 + b2 * b2 - c);
+    g = as[0] + (sb + sqrt(disc > 0.0 ? disc : 0.0)) / 3.0;
+    return g;
+}
+
+/* dbar: smallest r >= a_min with S(r) >= c.  Found by an exponential search
+ * from a guess on the integer image of positive doubles (which orders them),
+ * then bisection; the invariant reaches(L) == 0, reaches(H) == 1 makes the
+ * result the smallest such r whatever the guess was. */
+double orc_dbar(const double a_in[3], double c) {
+    double as[3] = {a_in[0], a_in[1], a_in[2]};
+    sort3(as);
+    if (!(as[0] < INFINITY)) return INFINITY;
+    const uint64_t A0 = bits_of(as[0]);             /* reaches(a_min) == 0 */
+    const uint64_t INF = bits_of(INFINITY);         /* reaches(+inf) == 1  */
+    double g = textbook_guess(as, c);
+    uint64_t G;
+    if (!(g > as[0])) G = A0 + 1;
+    else if (!(g < INFINITY)) G = INF;
+    else G = bits_of(g);
+    uint64_t L, H;
+    if (reaches(double_of(G), as, c)) {
+        H = G;
+        uint64_t step = 1;
+        for (;;) {
+            L = (H - A0 > step) ? G - step : A0;
+            if (L == A0 || !reaches(double_of(L), as, c)) break;
+            H = L;
+            step <<= 1;
+        }
+    } else {
+        L = G;
+        uint64_t step = 1;
+        for (;;) {
+            H = (INF - G > step) ? G + step : INF;
+            if (H == INF || reaches(double_of(H), as, c)) break;
+            L = H;
+            step <<= 1;
+        }
+    }
+    while (H - L > 1) {
+        uint64_t M = L + (H - L) / 2;
+        if (reaches(double_of(M), as, c)) H = M; else L = M;
+    }
+    return double_of(H);
+}
+
+/* Exported single predicate evaluation, for tests. */
+int orc_reaches(double r, const double a_in[3], double c) {
+    double as[3] = {a_in[0], a_in[1], a_in[2]};
+    sort3(as);
+    return reaches(r, as, c);
+}
+
+/* The two explicit 2D formulas the paper analyses, with q = fl(h/v), c = fl(q*q).
+ * Two-sided branch when |tH - tV| < q, else min(tH, tV) + q. */
+double orc_dtilde(double tH, double tV, double c, double q) {
+    if (fabs(tH - tV) >= q) return (tH < tV ? tH : tV) + q;
+    double s = tH + tV;
+    double inner = s * s - 2.0 * ((tH * tH + tV * tV) - c);
+    return 0.5 * (s + sqrt(inner));
+}
+
+double orc_dhat(double tH, double tV, double c, double q) {
+    if (fabs(tH - tV) >= q) return (tH < tV ? tH : tV) + q;
+    double d = tH - tV;
+    double inner = 2.0 * c - d * d;
+    return 0.5 * ((tH + tV) + sqrt(inner));
+}
+
+/* ------------------------------------------------------------------------- */
+/* grid helpers                                                               */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    int ndim;
+    int64_t nx, ny, nz, n;
+    double h;
+} grid_t;
+
+static grid_t mkgrid(int ndim, int64_t nx, int64_t ny, int64_t nz, double h) {
+    grid_t g = {ndim, nx, ny, nz, nx * ny * nz, h};
+    return g;
+}
+
+/* Per-point constant q (speed: h/v, slowness: h*s).  Returns -1 when a field
+ * value is not a positive finite number or c = q*q is not in (0, inf). */
+static int make_q(const grid_t *g, const double *field, int kind, double *q) {
+    for (int64_t i = 0; i < g->n; ++i) {
+        double f = field[i];
+        if (!(f > 0.0) || !(f < INFINITY)) return -1;
+        double qq = (kind == ORC_SPEED) ? g->h / f : g->h * f;
+        double cc = qq * qq;
+        if (!(cc > 0.0) || !(cc < INFINITY)) return -1;
+        q[i] = qq;
+    }
+    return 0;
+}
+
+/* a_k for point i: min of the two axis neighbours, +inf off the grid. */
+static void neighbour_minima(const grid_t *g, const double *t, int64_t i, double a[3]) {
+    int64_t ix = i % g->nx, iy = (i / g->nx) % g->ny, iz = i / (g->nx * g->ny);
+    double lo, hi;
+    lo = ix > 0 ? t[i - 1] : INFINITY;
+    hi = ix < g->nx - 1 ? t[i + 1] : INFINITY;
+    a[0] = lo < hi ? lo : hi;
+    lo = iy > 0 ? t[i - g->nx] : INFINITY;
+    hi = iy < g->ny - 1 ? t[i + g->nx] : INFINITY;
+    a[1] = lo < hi ? lo : hi;
+    if (g->ndim == 3) {
+        int64_t s = g->nx * g->ny;
+        lo = iz > 0 ? t[i - s] : INFINITY;
+        hi = iz < g->nz - 1 ? t[i + s] : INFINITY;
+        a[2] = lo < hi ? lo : hi;
+    } else {
+        a[2] = INFINITY;
+    }
+}
+
+/* Apply the chosen operator at point i; returns the candidate value. */
+static double apply_op(const grid_t *g, const double *t, const double *q, int64_t i, int op) {
+    double a[3];
+    neighbour_minima(g, t, i, a);
+    double qi = q[i];
+    double c = qi * qi;
+    if (op == OP_DBAR) return orc_dbar(a, c);
+    double tH = a[0], tV = a[1];
+    if (!(tH < INFINITY) && !(tV < INFINITY)) return INFINITY;
+    if (op == OP_DHAT) return orc_dhat(tH, tV, c, qi);
+    return orc_dtilde(tH, tV, c, qi);
+}
+
+static int nbrs(const grid_t *g, int64_t i, int64_t out[6]) {
+    int64_t ix = i % g->nx, iy = (i / g->nx) % g->ny, iz = i / (g->nx * g->ny);
+    int k = 0;
+    if (ix > 0) out[k++] = i - 1;
+    if (ix < g->nx - 1) out[k++] = i + 1;
+    if (iy > 0) out[k++] = i - g->nx;
+    if (iy < g->ny - 1) out[k++] = i + g->nx;
+    if (g->ndim == 3) {
+        int64_t s = g->nx * g->ny;
+        if (iz > 0) out[k++] = i - s;
+        if (iz < g->nz - 1) out[k++] = i + s;
+    }
+    return k;
+}
+
+/* Common set-up: q array, fixed (source) mask, t = +inf with the sources set to
+ * their start times (duplicates: the smallest wins). */
+static int setup(const grid_t *g, const double *field, int kind, int64_t nsrc,
+                 const int64_t *src, const double *t0, double *t, double **q_out,
+                 uint8_t **fixed_out) {
+    double *q = (double *)malloc(sizeof(double) * (size_t)g->n);
+    uint8_t *fixed = (uint8_t *)calloc((size_t)g->n, 1);
+    if (!q || !fixed) { free(q); free(fixed); return -2; }
+    if (make_q(g, field, kind, q) != 0) { free(q); free(fixed); return -1; }
+    for (int64_t i = 0; i < g->n; ++i) t[i] = INFINITY;
+    for (int64_t s = 0; s < nsrc; ++s) {
+        int64_t i = src[s];
+        if (i < 0 || i >= g->n) { free(q); free(fixed); return -3; }
+        double v = t0 ? t0[s] : 0.0;
+        if (!(v >= 0.0) || !(v < INFINITY) || signbit(v)) { free(q); free(fixed); return -3; }
+        if (!fixed[i] || v < t[i]) t[i] = v;
+        fixed[i] = 1;
+    }
+    *q_out = q;
+    *fixed_out = fixed;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* binary heap of (t, index) with lazy deletion                               */
+/* ------------------------------------------------------------------------- */
+
+typedef struct { double t; int64_t i; } item_t;
+typedef struct { item_t *a; int64_t n, cap; } heap_t;
+
+static int item_less(item_t x, item_t y) { return x.t < y.t || (x.t == y.t && x.i < y.i); }
+
+static int heap_push(heap_t *h, double t, int64_t i) {
+    if (h->n == h->cap) {
+        int64_t nc = h->cap ? 2 * h->cap : 1024;
+        item_t *na = (item_t *)realloc(h->a, sizeof(item_t) * (size_t)nc);
+        if (!na) return -2;
+        h->a = na;
+        h->cap = nc;
+    }
+    int64_t k = h->n++;
+    item_t it = {t, i};
+    while (k > 0) {
+        int64_t p = (k - 1) / 2;
+        if (!item_less(it, h->a[p])) break;
+        h->a[k] = h->a[p];
+        k = p;
+    }
+    h->a[k] = it;
+    return 0;
+}
+
+static item_t heap_pop(heap_t *h) {
+    item_t top = h->a[0];
+    item_t last = h->a[--h->n];
+    int64_t k = 0;
+    for (;;) {
+        int64_t l = 2 * k + 1;
+        if (l >= h->n) break;
+        int64_t m = (l + 1 < h->n && item_less(h->a[l + 1], h->a[l])) ? l + 1 : l;
+        if (!item_less(h->a[m], last)) break;
+        h->a[k] = h->a[m];
+        k = m;
+    }
+    if (h->n > 0) h->a[k] = last;
+    return top;
+}
+
+/* ------------------------------------------------------------------------- */
+/* schedules                                                                  */
+/* ------------------------------------------------------------------------- */
+
+/* stats[0] = pops (non-stale), stats[1] = operator applications,
+ * stats[2] = accepted (decreasing) updates. */
+
+/* Fast marching (Algorithm "Fast Marching Method"): pop the smallest entry,
+ * apply the operator at every non-source neighbour, push each one that
+ * decreased.  Stale heap entries (tagged with an old t) are skipped. */
+int orc_fmm(int ndim, int64_t nx, int64_t ny, int64_t nz, double h, const double *field,
+            int kind, int64_t nsrc, const int64_t *src, const double *t0, int op,
+            double *t, int64_t *stats) {
+    grid_t g = mkgrid(ndim, nx, ny, nz, h);
+    double *q;
+    uint8_t *fixed;
+    int rc = setup(&g, field, kind, nsrc, src, t0, t, &q, &fixed);
+    if (rc) return rc;
+    heap_t hp = {0, 0, 0};
+    int64_t pops = 0, applies = 0, accepts = 0;
+    for (int64_t s = 0; s < nsrc; ++s)
+        if (heap_push(&hp, t[src[s]], src[s])) { rc = -2; goto done; }
+    while (hp.n > 0) {
+        item_t it = heap_pop(&hp);
+        if (it.t != t[it.i]) continue;
+        ++pops;
+        int64_t nb[6];
+        int k = nbrs(&g, it.i, nb);
+        for (int j = 0; j < k; ++j) {
+            int64_t m = nb[j];
+            if (fixed[m]) continue;
+            double r = apply_op(&g, t, q, m, op);
+            ++applies;
+            if (r < t[m]) {
+                t[m] = r;
+                ++accepts;
+                if (heap_push(&hp, r, m)) { rc = -2; goto done; }
+            }
+        }
+    }
+done:
+    if (stats) { stats[0] = pops; stats[1] = applies; stats[2] = accepts; }
+    free(hp.a);
+    free(q);
+    free(fixed);
+    return rc;
+}
+
+/* Topology-driven schedule (Algorithm "topology-driven"): apply the operator at
+ * every point, in index order, until a whole round changes nothing. */
+int orc_sweep_all(int ndim, int64_t nx, int64_t ny, int64_t nz, double h, const double *field,
+                  int kind, int64_t nsrc, const int64_t *src, const double *t0, int op,
+                  double *t, int64_t *stats) {
+    grid_t g = mkgrid(ndim, nx, ny, nz, h);
+    double *q;
+    uint8_t *fixed;
+    int rc = setup(&g, field, kind, nsrc, src, t0, t, &q, &fixed);
+    if (rc) return rc;
+    int64_t rounds = 0, accepts = 0;
+    int changed = 1;
+    while (changed) {
+        changed = 0;
+        ++rounds;
+        for (int64_t i = 0; i < g.n; ++i) {
+            if (fixed[i]) continue;
+            double r = apply_op(&g, t, q, i, op);
+            if (r < t[i]) { t[i] = r; changed = 1; ++accepts; }
+        }
+    }
+    if (stats) { stats[0] = rounds; stats[1] = rounds * g.n; stats[2] = accepts; }
+    free(q);
+    free(fixed);
+    return 0;
+}
+
+/* Fast sweeping (Algorithm "Fast Sweeping Method"): Gauss-Seidel sweeps in the
+ * 2^ndim alternating axis directions, repeated until a full cycle of sweeps
+ * changes nothing. */
+int orc_fsm(int ndim, int64_t nx, int64_t ny, int64_t nz, double h, const double *field,
+            int kind, int64_t nsrc, const int64_t *src, const double *t0, int op,
+            double *t, int64_t *stats) {
+    grid_t g = mkgrid(ndim, nx, ny, nz, h);
+    double *q;
+    uint8_t *fixed;
+    int rc = setup(&g, field, kind, nsrc, src, t0, t, &q, &fixed);
+    if (rc) return rc;
+    int ndir = 1 << ndim;
+    int64_t cycles = 0, accepts = 0;
+    int changed = 1;
+    while (changed) {
+        changed = 0;
+        ++cycles;
+        for (int dir = 0; dir < ndir; ++dir) {
+            int fx = !(dir & 1), fy = !(dir & 2), fz = !(dir & 4);
+            for (int64_t kz = 0; kz < g.nz; ++kz) {
+                int64_t iz = fz ? kz : g.nz - 1 - kz;
+                for (int64_t ky = 0; ky < g.ny; ++ky) {
+                    int64_t iy = fy ? ky : g.ny - 1 - ky;
+                    for (int64_t kx = 0; kx < g.nx; ++kx) {
+                        int64_t ix = fx ? kx : g.nx - 1 - kx;
+                        int64_t i = (iz * g.ny + iy) * g.nx + ix;
+                        if (fixed[i]) continue;
+                        double r = apply_op(&g, t, q, i, op);
+                        if (r < t[i]) { t[i] = r; changed = 1; ++accepts; }
+                    }
+                }
+            }
+        }
+    }
+    if (stats) { stats[0] = cycles; stats[1] = cycles * ndir * g.n; stats[2] = accepts; }
+    free(q);
+    free(fixed);
+    return 0;
+}
+
+/* xorshift64* for the random schedule below */
+static uint64_t rng_next(uint64_t *s) {
+    uint64_t x = *s;
+    x ^= x >> 12;
+    x ^= x << 25;
+    x ^= x >> 27;
+    *s = x;
+    return x * 0x2545F4914F6CDD1DULL;
+}
+
+/* Unordered data-driven schedule: the worklist is a bag from which a uniformly
+ * random item is taken each step (arbitrary priority inversions, the extreme of
+ * soft priorities).  A neighbour is pushed whenever it decreased
+ * (mode 0) or whenever it changed at all (mode 1, the paper's conservative work
+ * tracking; only differs from mode 0 with a non-monotone operator). */
+int orc_async_random(int ndim, int64_t nx, int64_t ny, int64_t nz, double h,
+                     const double *field, int kind, int64_t nsrc, const int64_t *src,
+                     const double *t0, int op, uint64_t seed, int mode, double *t,
+                     int64_t *stats) {
+    grid_t g = mkgrid(ndim, nx, ny, nz, h);
+    double *q;
+    uint8_t *fixed;
+    int rc = setup(&g, field, kind, nsrc, src, t0, t, &q, &fixed);
+    if (rc) return rc;
+    int64_t cap = 1024, n = 0;
+    int64_t *bag = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+    uint64_t st = seed * 0x9E3779B97F4A7C15ULL + 0x632BE59BD9B4E019ULL;
+    if (st == 0) st = 1;
+    int64_t pops = 0, applies = 0, accepts = 0;
+    if (!bag) { rc = -2; goto done; }
+    for (int64_t s = 0; s < nsrc; ++s) bag[n++] = src[s];
+    while (n > 0) {
+        int64_t j = (int64_t)(rng_next(&st) % (uint64_t)n);
+        int64_t p = bag[j];
+        bag[j] = bag[--n];
+        ++pops;
+        int64_t nb[6];
+        int k = nbrs(&g, p, nb);
+        for (int jj = 0; jj < k; ++jj) {
+            int64_t m = nb[jj];
+            if (fixed[m]) continue;
+            double r = apply_op(&g, t, q, m, op);
+            ++applies;
+            int push = mode ? (r != t[m]) : (r < t[m]);
+            if (op == OP_DBAR || mode == 0) {
+                if (r < t[m]) { t[m] = r; ++accepts; } else push = 0;
+            } else if (push) {
+                t[m] = r;
+                ++accepts;
+            }
+            if (push) {
+                if (n == cap) {
+                    cap *= 2;
+                    int64_t *nb2 = (int64_t *)realloc(bag, sizeof(int64_t) * (size_t)cap);
+                    if (!nb2) { rc = -2; goto done; }
+                    bag = nb2;
+                }
+                bag[n++] = m;
+                if (accepts > 4096 * g.n + 65536) { rc = -4; goto done; }  /* runaway guard */
+            }
+        }
+    }
+done:
+    if (stats) { stats[0] = pops; stats[1] = applies; stats[2] = accepts; }
+    free(bag);
+    free(q);
+    free(fixed);
+    return rc;
+}
+
+/* Residual metric (Table "tab:error"): re-apply the operator at every non-source
+ * point with the final neighbour values; returns the number of points whose
+ * value would change and writes the largest |r - t| / t to *maxrel. */
+int64_t orc_residual(int ndim, int64_t nx, int64_t ny, int64_t nz, double h,
+                     const double *field, int kind, int64_t nsrc, const int64_t *src,
+                     const double *t, int op, double *maxrel) {
+    grid_t g = mkgrid(ndim, nx, ny, nz, h);
+    double *q = (double *)malloc(sizeof(double) * (size_t)g.n);
+    uint8_t *fixed = (uint8_t *)calloc((size_t)g.n, 1);
+    int64_t bad = 0;
+    double worst = 0.0;
+    if (!q || !fixed || make_q(&g, field, kind, q) != 0) { bad = -1; goto done; }
+    for (int64_t s = 0; s < nsrc; ++s) fixed[src[s]] = 1;
+    for (int64_t i = 0; i < g.n; ++i) {
+        if (fixed[i]) continue;
+        double r = apply_op(&g, t, q, i, op);
+        if (r != t[i]) {
+            ++bad;
+            double rel = fabs(r - t[i]) / fabs(t[i]);
+            if (!(rel <= worst)) worst = rel;
+        }
+    }
+done:
+    if (maxrel) *maxrel = worst;
+    free(q);
+    free(fixed);
+    return bad;
+}
+
+/* ------------------------------------------------------------------------- */
+/* parents and adjoint                                                        */
+/* ------------------------------------------------------------------------- */
+
+/* Upwind parent record from final times.  Per axis k (bits 2k..2k+1):
+ * 0 = axis not upwind (min neighbour >= t), 1 = the minus-side neighbour,
+ * 2 = the plus-side neighbour (equal neighbours: minus side).  Bit 7 marks a
+ * source point (its other bits are zero). */
+void orc_parents(int ndim, int64_t nx, int64_t ny, int64_t nz, const double *t,
+                 int64_t nsrc, const int64_t *src, uint8_t *par) {
+    grid_t g = mkgrid(ndim, nx, ny, nz, 1.0);
+    int64_t stride[3] = {1, g.nx, g.nx * g.ny};
+    int64_t dim[3] = {g.nx, g.ny, g.nz};
+    for (int64_t i = 0; i < g.n; ++i) {
+        int64_t coord[3] = {i % g.nx, (i / g.nx) % g.ny, i / (g.nx * g.ny)};
+        uint8_t b = 0;
+        for (int k = 0; k < ndim; ++k) {
+            double lo = coord[k] > 0 ? t[i - stride[k]] : INFINITY;
+            double hi = coord[k] < dim[k] - 1 ? t[i + stride[k]] : INFINITY;
+            double m = lo <= hi ? lo : hi;
+            if (m < t[i]) b |= (uint8_t)((lo <= hi ? 1 : 2) << (2 * k));
+        }
+        par[i] = b;
+    }
+    for (int64_t s = 0; s < nsrc; ++s) par[src[s]] = 0x80;
+}
+
+typedef struct { double t; int64_t i; } key_t;
+static int key_desc(const void *x, const void *y) {
+    const key_t *a = (const key_t *)x, *b = (const key_t *)y;
+    if (a->t > b->t) return -1;
+    if (a->t < b->t) return 1;
+    return (a->i > b->i) - (a->i < b->i);
+}
+
+/* Adjoint of the discrete equations sum_k (t_n - t_{p_k})^2 = (h s_n)^2 over the
+ * recorded upwind parents p_k (paper silent; implicit differentiation).  With
+ * w_{n,k} = fl(t_n - t_{p_k}) and W_n = fl(fl(w_x + w_y) + w_z) (inactive axes
+ * +0), processing non-source points in decreasing t:
+ *   lambda_n = g_n, then += fl(mu_m * w_{m,k}) for each child m of n, children
+ *              taken in the neighbour order x-, x+, y-, y+, z-, z+,
+ *   mu_n     = fl(lambda_n / W_n),
+ *   grad_n   = fl(fl(mu_n * q_n) * h)   (d loss / d slowness_n),
+ * where q_n is the forward constant (h/v or h*s) and sources get mu = grad = 0.
+ * mu_out (optional) receives mu. Returns 0, or -1 on a field domain error. */
+int orc_adjoint(int ndim, int64_t nx, int64_t ny, int64_t nz, double h, const double *field,
+                int kind, const double *t, const uint8_t *par, const double *gin,
+                double *grad, double *mu_out) {
+    grid_t g = mkgrid(ndim, nx, ny, nz, h);
+    int64_t stride[3] = {1, g.nx, g.nx * g.ny};
+    int64_t dim[3] = {g.nx, g.ny, g.nz};
+    double *mu = (double *)calloc((size_t)g.n, sizeof(double));
+    key_t *ord = (key_t *)malloc(sizeof(key_t) * (size_t)g.n);
+    int rc = 0;
+    if (!mu || !ord) { rc = -2; goto done; }
+    int64_t m = 0;
+    for (int64_t i = 0; i < g.n; ++i) {
+        double f = field[i];
+        if (!(f > 0.0) || !(f < INFINITY)) { rc = -1; goto done; }
+        grad[i] = 0.0;
+        if (!(par[i] & 0x80)) { ord[m].t = t[i]; ord[m].i = i; ++m; }
+    }
+    qsort(ord, (size_t)m, sizeof(key_t), key_desc);
+    for (int64_t j = 0; j < m; ++j) {
+        int64_t n = ord[j].i;
+        int64_t coord[3] = {n % g.nx, (n / g.nx) % g.ny, n / (g.nx * g.ny)};
+        double lam = gin[n];
+        for (int k = 0; k < ndim; ++k) {
+            /* minus-side neighbour is a child if its plus-side parent is n */
+            if (coord[k] > 0) {
+                int64_t ch = n - stride[k];
+                if (!(par[ch] & 0x80) && ((par[ch] >> (2 * k)) & 3) == 2)
+                    lam = lam + mu[ch] * (t[ch] - t[n]);
+            }
+            if (coord[k] < dim[k] - 1) {
+                int64_t ch = n + stride[k];
+                if (!(par[ch] & 0x80) && ((par[ch] >> (2 * k)) & 3) == 1)
+                    lam = lam + mu[ch] * (t[ch] - t[n]);
+            }
+        }
+        double w[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < ndim; ++k) {
+            int code = (par[n] >> (2 * k)) & 3;
+            if (code == 1) w[k] = t[n] - t[n - stride[k]];
+            else if (code == 2) w[k] = t[n] - t[n + stride[k]];
+        }
+        double W = (w[0] + w[1]) + w[2];
+        double mun = lam / W;
+        mu[n] = mun;
+        double f = field[n];
+        double q = (kind == ORC_SPEED) ? h / f : h * f;
+        grad[n] = (mun * q) * h;
+    }
+    if (mu_out) memcpy(mu_out, mu, sizeof(double) * (size_t)g.n);
+done:
+    free(mu);
+    free(ord);
+    return rc;
+}
