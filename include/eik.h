@@ -1,0 +1,178 @@
+/*
+ * eik.h -- C ABI of the MI355X (gfx950) Eikonal travel-time library.
+ *
+ * What is computed
+ * ----------------
+ * First-arrival times t on a structured 2D or 3D grid with spacing h and a
+ * positive speed (or slowness) field, from point sources with given start
+ * times.  The discrete equations are the first-order upwind scheme of the
+ * paper's Eq. (finite_difference): at every non-source point the upwind
+ * differences per axis, taken from the smaller neighbour on that axis, have a
+ * 2-norm equal to the local slowness (Eq. difference_as_root, and the one-sided
+ * case of Algorithm "Eikonal Update Operator").  Rounding follows the paper's
+ * exactly monotone semantics (section "Achieving Exact Monotonicity with Finite
+ * Precision Arithmetic"): with a_k the smaller axis-k neighbour (+inf off the
+ * grid), q = fl(h/v) or fl(h*s), c = fl(q*q), T_k(r) = fl(fl(r-a_k)^2) when
+ * r > a_k else +0, and S(r) the T_k summed largest first, each point's value is
+ * the smallest binary64 r >= min_k a_k with S(r) >= c.  That operator is
+ * monotone and causal in floating point, so by the paper's Theorem 1 every
+ * update order reaches the same fixed point: results are bit-identical to a
+ * sequential fast-marching solve and across runs.
+ *
+ * Conventions
+ * -----------
+ *  - Layout: C-order [nz][ny][nx] float64, x fastest; 2D grids use nz = 1.
+ *  - All array arguments are DEVICE pointers on the current HIP device unless
+ *    their name ends in _host.  The caller owns every input and output buffer;
+ *    the library only reads/writes them inside work enqueued on `stream`.
+ *  - All work is enqueued on `stream` (a hipStream_t, NULL = default stream);
+ *    no call synchronises the host except eik_status().
+ *  - The library owns a workspace per (device, stream) (tile states, priority
+ *    queues, counters), allocated on first use, grown on demand and freed by
+ *    eik_release().  Two calls on the same stream are ordered; calls on
+ *    different streams use different workspaces.
+ *  - Return codes: EIK_OK (0) or a negative EIK_E* code.  Errors detectable on
+ *    the host return immediately without enqueuing work.  Errors found on the
+ *    device (bad field values, bad sources, the visit cap) are reported by
+ *    eik_status() for the last call on that stream.  eik_last_error() gives a
+ *    thread-local message for the last failing call.
+ */
+#ifndef EIK_H
+#define EIK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EIK_OK 0
+#define EIK_EINVAL (-1)   /* bad argument (dims, h, pointers, options) */
+#define EIK_EDOMAIN (-2)  /* a field value is <= 0, NaN or Inf, or c over/underflows */
+#define EIK_ENOMEM (-3)   /* workspace allocation failed */
+#define EIK_EHIP (-4)     /* HIP runtime error; eik_last_error() has the text */
+#define EIK_ELIMIT (-5)   /* max_tile_visits reached: output is an upper bound */
+#define EIK_ENOTSUP (-6)  /* shape / tile / size combination not supported */
+#define EIK_EBADSRC (-7)  /* a source index was out of range or a t0 invalid */
+#define EIK_EHANG (-8)    /* a device-side watchdog expired (internal error) */
+
+#define EIK_SPEED 0       /* field holds speed v:    q = h / v */
+#define EIK_SLOWNESS 1    /* field holds slowness s: q = h * s */
+
+typedef struct {
+    int32_t ndim;        /* 2 or 3 */
+    int32_t nx, ny, nz;  /* points per axis; nz must be 1 when ndim == 2 */
+    double h;            /* grid spacing, > 0 and finite */
+    int32_t field_kind;  /* EIK_SPEED or EIK_SLOWNESS */
+} eik_grid;
+
+typedef struct {
+    double delta;            /* priority bucket width in time units; 0 => one bucket (FIFO) */
+    int32_t tile[3];         /* tile shape (x, y, z); zeros => default for ndim.  Supported:
+                                3D 32x8x4, 16x8x8, 8x8x8, 64x4x4; 2D 32x32, 64x16, 128x8, 16x16 */
+    int32_t grid_blocks;     /* persistent workgroups; 0 => fill the device */
+    int64_t max_tile_visits; /* 0 => unlimited; else stop after this many tile visits (ELIMIT) */
+    uint32_t flags;          /* reserved, must be 0 */
+} eik_opts;
+
+typedef struct {
+    int64_t tile_visits;     /* tiles claimed and processed by the persistent solve */
+    int64_t point_updates;   /* points whose value decreased, summed over visits */
+    int64_t ntiles;          /* tiles in the problem(s) */
+    int64_t relax_passes;    /* in-tile relaxation passes, summed over visits */
+    uint32_t flags;          /* raw device flags (bit0 domain, bit1 limit, bit2 bad source, bit3 watchdog) */
+    int32_t status;          /* the EIK_* code these flags map to */
+} eik_stats;
+
+/* Forward solve.
+ *   g        grid description (host struct).
+ *   field    [nz][ny][nx] speed or slowness (device).
+ *   nsrc     number of point sources, >= 1.
+ *   src_idx  nsrc flat indices (iz*ny+iy)*nx+ix (device int64).  Duplicates are
+ *            allowed (the smallest start time wins).
+ *   src_t0   nsrc start times >= +0.0 and finite (device), or NULL for all +0.0.
+ *   t_out    [nz][ny][nx] arrival times (device, written entirely).
+ *   parents_out  NULL, or [nz][ny][nx] uint8 upwind-parent record computed from
+ *            the final times: per axis k (bits 2k..2k+1) 0 = axis not upwind,
+ *            1 = minus-side neighbour, 2 = plus-side neighbour (ties: minus);
+ *            bit 7 set (other bits 0) marks a source point.
+ *   opts     NULL for defaults.
+ *   stream   hipStream_t or NULL.
+ * Returns EIK_OK when the work was enqueued. */
+int eik_solve(const eik_grid* g, const double* field, int64_t nsrc, const int64_t* src_idx,
+              const double* src_t0, double* t_out, uint8_t* parents_out,
+              const eik_opts* opts, void* stream);
+
+/* Upwind-parent record (same encoding as parents_out above) from final times t
+ * of a finished solve.  src_idx as for eik_solve. */
+int eik_parents(const eik_grid* g, const double* t, int64_t nsrc, const int64_t* src_idx,
+                uint8_t* parents_out, void* stream);
+
+/* Adjoint: gradient of a loss L(t) with respect to slowness, given dL/dt.
+ * Linearises the discrete equations sum_k (t_n - t_{p_k})^2 = (q_n)^2 over the
+ * recorded upwind parents p_k (implicit differentiation; the paper is silent on
+ * gradients).  With w_{n,k} = fl(t_n - t_{p_k}), W_n = fl(fl(w_x + w_y) + w_z):
+ *   lambda_n = dL/dt_n + sum over children m (neighbour order x-,x+,y-,y+,z-,z+)
+ *              of fl(mu_m * w_{m,k}),   mu_n = fl(lambda_n / W_n),
+ *   dL/ds_n  = fl(fl(mu_n * q_n) * h),  0 at sources,
+ * evaluated children-first (decreasing t), so results are deterministic.
+ *   t, parents   outputs of a finished eik_solve on the same grid and field.
+ *   dL_dt        [nz][ny][nx] (device).
+ *   dL_dslowness [nz][ny][nx] output (device).  For a speed field the gradient
+ *                is still with respect to slowness s = 1/v.
+ *   mu_out       NULL or [nz][ny][nx] scratch output receiving mu (device);
+ *                when NULL the library uses workspace memory. */
+int eik_adjoint(const eik_grid* g, const double* field, const double* t, const uint8_t* parents,
+                const double* dL_dt, double* dL_dslowness, double* mu_out,
+                const eik_opts* opts, void* stream);
+
+/* Batched forward solve of nprob independent problems in ONE persistent launch.
+ *   grids_host    nprob grid descriptions (all the same ndim).
+ *   offsets_host  nprob+1 point offsets into the packed arrays (offsets_host[0] == 0,
+ *                 offsets_host[i+1] - offsets_host[i] == nx*ny*nz of problem i).
+ *   field_packed, t_packed, parents_packed (NULL ok): concatenated per-problem arrays.
+ *   src_off_host  nprob+1 offsets into src_idx / src_t0 (sources of problem i are
+ *                 src_off_host[i] .. src_off_host[i+1]-1, each problem >= 1 source).
+ *   src_idx       local flat indices within each problem (device int64).
+ *   src_t0        device start times or NULL (all +0.0).
+ * The call enqueues a fixed sequence of kernels with no host synchronisation and
+ * no allocation once the workspace has grown to this size, so it may be captured
+ * into a HIP graph after one warm-up call with the same sizes. */
+int eik_solve_batched(int32_t nprob, const eik_grid* grids_host, const int64_t* offsets_host,
+                      const double* field_packed, const int64_t* src_off_host,
+                      const int64_t* src_idx, const double* src_t0, double* t_packed,
+                      uint8_t* parents_packed, const eik_opts* opts, void* stream);
+
+/* Batched adjoint with the same packing (mu_packed NULL => workspace). */
+int eik_adjoint_batched(int32_t nprob, const eik_grid* grids_host, const int64_t* offsets_host,
+                        const double* field_packed, const double* t_packed,
+                        const uint8_t* parents_packed, const double* dL_dt_packed,
+                        double* dL_ds_packed, double* mu_packed, const eik_opts* opts,
+                        void* stream);
+
+/* Pre-grow the workspace of `stream` for up to `ntiles` tiles and `npts`
+ * points so that later calls of that size allocate nothing (e.g. before HIP
+ * graph capture). */
+int eik_reserve(int64_t ntiles, int64_t npts, void* stream);
+
+/* Number of tiles a problem of this grid uses with these options (host only). */
+int64_t eik_num_tiles(const eik_grid* g, const eik_opts* opts);
+
+/* Synchronises `stream`, copies the device status of the last call on it into
+ * *out_host (may be NULL) and returns its EIK_* code. */
+int eik_status(void* stream, eik_stats* out_host);
+
+const char* eik_strerror(int code);
+const char* eik_last_error(void);
+
+/* Frees every cached workspace on every device. */
+void eik_release(void);
+
+/* Library version string. */
+const char* eik_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EIK_H */

@@ -1,0 +1,370 @@
+// Adjoint (reverse) sweep: gradient of a travel-time loss with respect to
+// slowness through the recorded upwind dependency graph.
+//
+// The paper gives no gradient; it is the implicit derivative of the discrete
+// equations of Eq. (difference_as_root) -- sum over upwind axes of
+// (t_n - t_{p_k})^2 = q_n^2 with q_n = h * s_n -- over the upwind parents p_k
+// the forward pass recorded.  Writing w_{n,k} = fl(t_n - t_{p_k}) and
+// W_n = fl(fl(w_x + w_y) + w_z):
+//   lambda_n = g_n + sum over children m (n is m's axis-k parent) of
+//              fl(mu_m * w_{m,k}), summed in neighbour order x-,x+,y-,y+,z-,z+,
+//   mu_n     = fl(lambda_n / W_n),
+//   dL/ds_n  = fl(fl(mu_n * q_n) * h),  sources: 0.
+// A child always has a strictly larger time than its parent, so the graph is
+// acyclic and mu can be evaluated children-first.
+//
+// The sweep reuses the forward scheduler with tiles as work items, but is
+// readiness-driven: a point is evaluated exactly once, when every child (in the
+// tile or in the halo) is done, so each mu is a fixed function of final values
+// and the result is deterministic whatever the visit order.  "Not done" is a
+// NaN in mu.  Tiles are prioritised by decreasing time (key tref - t), a finished
+// face point activates the neighbour tile holding its parent, and a tile whose
+// interior was never written (V bit clear) reads as all not-done.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "eik_kernels.hpp"
+
+namespace eik {
+
+__device__ __forceinline__ double qnan64() { return as_f64(0x7FF8000000000000ull); }
+
+// Per tile: largest time (key source) and the problem-wide largest time.
+template <int TX, int TY, int TZ>
+__global__ void k_adj_prep(const Prob* probs, int nprob, int ntiles, const double* t,
+                           uint64_t* tile_tmax, unsigned long long* tref_bits) {
+    __shared__ unsigned long long s_m;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const Prob P = probs[nprob == 1 ? 0 : find_prob(probs, nprob, tile)];
+        int tl = tile - P.tile_off;
+        int tx = tl % P.ntx, ty = (tl / P.ntx) % P.nty, tz = tl / (P.ntx * P.nty);
+        if (threadIdx.x == 0) s_m = 0ull;
+        __syncthreads();
+        unsigned long long m = 0ull;
+        for (int i = threadIdx.x; i < TX * TY * TZ; i += blockDim.x) {
+            int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
+            int x = tx * TX + lx, y = ty * TY + ly, z = tz * TZ + lz;
+            if (x < P.nx && y < P.ny && z < P.nz) {
+                double v = t[P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x];
+                if (v < inf64()) {
+                    unsigned long long b = as_u64(fabs(v));
+                    m = b > m ? b : m;
+                }
+            }
+        }
+        if (m) atomicMax(&s_m, m);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            tile_tmax[tile] = s_m;
+            __hip_atomic_fetch_max(tref_bits, s_m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+    }
+}
+
+// Queue every tile, latest first.
+__global__ void k_adj_push_all(int ntiles, const uint64_t* tile_tmax,
+                               const unsigned long long* tref_bits, Sched s) {
+    const double tref = as_f64(*tref_bits);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *s.poisoned = 0;  // rings were wiped by the reset
+    for (int tile = blockIdx.x * blockDim.x + threadIdx.x; tile < ntiles; tile += gridDim.x * blockDim.x) {
+        s.tstate[tile] = kQ;
+        __hip_atomic_fetch_add(s.pending, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        push_tile(s, (uint32_t)tile, tref - as_f64(tile_tmax[tile]));
+    }
+}
+
+struct AdjArgs {
+    const Prob* probs;
+    int nprob;
+    const double* field;
+    const double* t;
+    const uint8_t* par;
+    const double* g;
+    double* mu;
+    double* grad;
+    uint64_t* tkey;
+    const unsigned long long* tref_bits;
+    Sched s;
+};
+
+template <int TX, int TY, int TZ, int NT>
+__global__ void __launch_bounds__(NT) k_adjoint(AdjArgs A) {
+    using C = TileCfg<TX, TY, TZ, NT>;
+    constexpr int NPT = C::NPT;
+    __shared__ double sT[C::NLDS];
+    __shared__ double sM[C::NLDS];
+    __shared__ uint8_t sP[C::NLDS];
+    __shared__ uint8_t sDirty[2][C::NP];
+    __shared__ int s_tile;
+    __shared__ uint32_t s_state;
+    __shared__ uint32_t s_nb[6];
+    __shared__ unsigned long long s_face[6];
+    __shared__ unsigned int s_done;
+
+    const int tid = threadIdx.x;
+    const Sched& S = A.s;
+    const double tref = as_f64(*A.tref_bits);
+    constexpr int PSTEP[3] = {1, TX, TX * TY};
+    constexpr int LSTEP[3] = {1, C::SY, C::SZ};
+    constexpr int NAX = C::D3 ? 3 : 2;
+
+    for (;;) {
+        if (tid < 64) {
+            int tile = claim(S);
+            if (tid == 0) {
+                s_tile = tile;
+                if (tile >= 0) {
+                    __hip_atomic_fetch_add(S.counters, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    uint32_t st = __hip_atomic_fetch_xor(S.tstate + tile, kQ | kR, __ATOMIC_ACQUIRE,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                    if ((st & (kQ | kR)) != kQ) set_flag(S, kFlagWatchdog);
+                    s_state = st;
+                }
+            }
+        }
+        __syncthreads();
+        const int tile = s_tile;
+        if (tile < 0) break;
+        const uint32_t st = s_state;
+        const bool visited = (st & kV) != 0;
+        const Prob P = A.probs[A.nprob == 1 ? 0 : find_prob(A.probs, A.nprob, tile)];
+        const int tl = tile - P.tile_off;
+        const int tx = tl % P.ntx, ty = (tl / P.ntx) % P.nty, tz = tl / (P.ntx * P.nty);
+        const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+
+        if (tid < 6) {
+            int d = tid >> 1, side = tid & 1;
+            int nt[3] = {tx, ty, tz};
+            int lim[3] = {P.ntx, P.nty, P.ntz};
+            nt[d] += side ? 1 : -1;
+            uint32_t w = 0;
+            if (nt[d] >= 0 && nt[d] < lim[d]) {
+                int nid = P.tile_off + (nt[2] * P.nty + nt[1]) * P.ntx + nt[0];
+                w = ld_rlx(S.tstate + nid) | 0x40000000u;
+            }
+            s_nb[tid] = w;
+            s_face[tid] = kInfBits;
+        }
+        if (tid == 0) s_done = 0u;
+
+        // stage own points
+        double gq[NPT];   // q_n, 0 when not an interior point
+        double gg[NPT];   // dL/dt
+        bool was_done[NPT];
+#pragma unroll
+        for (int j = 0; j < NPT; ++j) {
+            const int p = tid + j * NT;
+            const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+            const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+            const int L = C::lds(lx, ly, lz);
+            double tv = inf64(), mv = 0.0, q = 0.0, gv = 0.0;
+            uint8_t pv = 0x80;  // outside points act as done sources
+            if (x < P.nx && y < P.ny && z < P.nz) {
+                const int64_t gi = P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x;
+                tv = A.t[gi];
+                pv = A.par[gi];
+                bool ok;
+                q = field_q(A.field[gi], P.h, P.kind, ok);
+                if (!ok) {
+                    set_flag(S, kFlagDomain);
+                    q = 0.0;
+                }
+                gv = A.g[gi];
+                if (pv & 0x80) mv = 0.0;
+                else mv = visited ? A.mu[gi] : qnan64();
+            }
+            sT[L] = tv;
+            sP[L] = pv;
+            sM[L] = mv;
+            gq[j] = q;
+            gg[j] = gv;
+            was_done[j] = !(mv != mv);
+            sDirty[0][p] = 1;
+            sDirty[1][p] = 0;
+        }
+        __syncthreads();
+        // halo
+        {
+            constexpr int NXF = 2 * TY * TZ, NYF = 2 * TX * TZ, NZF = C::D3 ? 2 * TX * TY : 0;
+            for (int i = tid; i < NXF + NYF + NZF; i += NT) {
+                int lx, ly, lz, f;
+                if (i < NXF) {
+                    int side = i / (TY * TZ), r = i % (TY * TZ);
+                    ly = r % TY; lz = r / TY; lx = side ? TX : -1; f = side;
+                } else if (i < NXF + NYF) {
+                    int k = i - NXF, side = k / (TX * TZ), r = k % (TX * TZ);
+                    lx = r % TX; lz = r / TX; ly = side ? TY : -1; f = 2 + side;
+                } else {
+                    int k = i - NXF - NYF, side = k / (TX * TY), r = k % (TX * TY);
+                    lx = r % TX; ly = r / TX; lz = side ? TZ : -1; f = 4 + side;
+                }
+                const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+                const int L = C::lds(lx, ly, lz);
+                double tv = inf64(), mv = 0.0;
+                uint8_t pv = 0x80;
+                if (x >= 0 && x < P.nx && y >= 0 && y < P.ny && z >= 0 && z < P.nz) {
+                    const int64_t gi = P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x;
+                    tv = A.t[gi];
+                    pv = A.par[gi];
+                    if (pv & 0x80) {
+                        mv = 0.0;
+                    } else if (s_nb[f] & kV) {
+                        mv = as_f64(__hip_atomic_load((const uint64_t*)(A.mu + gi), __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT));
+                    } else {
+                        mv = qnan64();
+                    }
+                }
+                sT[L] = tv;
+                sP[L] = pv;
+                sM[L] = mv;
+            }
+        }
+        __syncthreads();
+
+        // evaluate points whose children are all done, until nothing changes
+        int cb = 0;
+        for (int pass = 0;; ++pass) {
+            bool any = false;
+#pragma unroll
+            for (int j = 0; j < NPT; ++j) {
+                const int p = tid + j * NT;
+                if (!sDirty[cb][p]) continue;
+                sDirty[cb][p] = 0;
+                const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+                const int L = C::lds(lx, ly, lz);
+                const uint8_t pn = sP[L];
+                if (pn & 0x80) continue;
+                if (!(sM[L] != sM[L])) continue;  // already done
+                const double tn = sT[L];
+                bool ready = true;
+                double lam = gg[j];
+                // children in neighbour order x-, x+, y-, y+, z-, z+
+#pragma unroll
+                for (int k = 0; k < NAX; ++k) {
+#pragma unroll
+                    for (int side = 0; side < 2; ++side) {
+                        const int Lm = side ? L + LSTEP[k] : L - LSTEP[k];
+                        const uint8_t pm = sP[Lm];
+                        // the minus-side neighbour is a child if its plus-side parent is n
+                        const uint32_t want = side ? 1u : 2u;
+                        if (!(pm & 0x80) && ((pm >> (2 * k)) & 3u) == want) {
+                            const double mm = sM[Lm];
+                            if (mm != mm) {
+                                ready = false;
+                            } else {
+                                double w = sT[Lm] - tn;
+                                lam = lam + mm * w;
+                            }
+                        }
+                    }
+                }
+                if (!ready) continue;
+                double wk[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int k = 0; k < NAX; ++k) {
+                    const uint32_t code = (pn >> (2 * k)) & 3u;
+                    if (code == 1u) wk[k] = tn - sT[L - LSTEP[k]];
+                    else if (code == 2u) wk[k] = tn - sT[L + LSTEP[k]];
+                }
+                double W = wk[0] + wk[1];
+                W = W + wk[2];
+                const double mun = lam / W;
+                sM[L] = mun;
+                any = true;
+                // parents inside the tile may now be ready
+                uint8_t* nd = sDirty[cb ^ 1];
+#pragma unroll
+                for (int k = 0; k < NAX; ++k) {
+                    const uint32_t code = (pn >> (2 * k)) & 3u;
+                    const int c = k == 0 ? lx : (k == 1 ? ly : lz);
+                    const int lim = k == 0 ? TX : (k == 1 ? TY : TZ);
+                    if (code == 1u && c > 0) nd[p - PSTEP[k]] = 1;
+                    if (code == 2u && c < lim - 1) nd[p + PSTEP[k]] = 1;
+                }
+            }
+            if (!__syncthreads_or(any)) break;
+            cb ^= 1;
+            if (pass > (1 << 20)) {
+                if (tid == 0) set_flag(S, kFlagWatchdog);
+                break;
+            }
+        }
+
+        // write back newly done points (first visit: every point, NaN = not done)
+        unsigned int ndone = 0;
+        double fkey[6] = {inf64(), inf64(), inf64(), inf64(), inf64(), inf64()};
+#pragma unroll
+        for (int j = 0; j < NPT; ++j) {
+            const int p = tid + j * NT;
+            const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+            const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+            if (!(x < P.nx && y < P.ny && z < P.nz)) continue;
+            const int L = C::lds(lx, ly, lz);
+            const int64_t gi = P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x;
+            const double mv = sM[L];
+            const bool done_now = !(mv != mv) && !was_done[j];
+            const uint8_t pn = sP[L];
+            if (done_now || !visited) {
+                __hip_atomic_store((uint64_t*)(A.mu + gi), as_u64(mv), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (done_now || (!visited && (pn & 0x80))) {
+                A.grad[gi] = (pn & 0x80) ? 0.0 : (mv * gq[j]) * P.h;
+            }
+            if (done_now && !(pn & 0x80)) {
+                ++ndone;
+                const double kt = tref - sT[L];
+                // a face point whose parent lies across that face unblocks the neighbour
+                if (lx == 0 && ((pn >> 0) & 3u) == 1u) fkey[0] = fmin(fkey[0], kt);
+                if (lx == TX - 1 && ((pn >> 0) & 3u) == 2u) fkey[1] = fmin(fkey[1], kt);
+                if (ly == 0 && ((pn >> 2) & 3u) == 1u) fkey[2] = fmin(fkey[2], kt);
+                if (ly == TY - 1 && ((pn >> 2) & 3u) == 2u) fkey[3] = fmin(fkey[3], kt);
+                if (C::D3) {
+                    if (lz == 0 && ((pn >> 4) & 3u) == 1u) fkey[4] = fmin(fkey[4], kt);
+                    if (lz == TZ - 1 && ((pn >> 4) & 3u) == 2u) fkey[5] = fmin(fkey[5], kt);
+                }
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < 6; ++f)
+            if (fkey[f] < inf64()) atomicMin(&s_face[f], (unsigned long long)as_u64(fmax(fkey[f], 0.0)));
+        if (ndone) atomicAdd(&s_done, ndone);
+        __syncthreads();
+
+        if (tid == 0) {
+            if (!visited)
+                __hip_atomic_fetch_or(S.tstate + tile, kV, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            for (int f = 0; f < 6; ++f) {
+                const uint32_t nb = s_nb[f];
+                const unsigned long long fk = s_face[f];
+                if ((nb & 0x40000000u) && fk != kInfBits) {
+                    int d = f >> 1, side = f & 1;
+                    int nt[3] = {tx, ty, tz};
+                    nt[d] += side ? 1 : -1;
+                    uint32_t nid = (uint32_t)(P.tile_off + (nt[2] * P.nty + nt[1]) * P.ntx + nt[0]);
+                    uint32_t old = __hip_atomic_fetch_or(S.tstate + nid, kQ, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                    if ((old & (kQ | kR)) == 0) {
+                        activate_push(S, nid, as_f64(fk));
+                    } else if (old & kR) {
+                        __hip_atomic_fetch_min((unsigned long long*)(A.tkey + nid), fk, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+            }
+            __hip_atomic_fetch_add(S.counters + 1, (unsigned long long)s_done, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            uint64_t kb = __hip_atomic_exchange((unsigned long long*)(A.tkey + tile), kInfBits,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            finish_run(S, (uint32_t)tile, kb == kInfBits ? 0.0 : as_f64(kb));
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace eik

@@ -1,0 +1,621 @@
+// C ABI of the Eikonal library (declared in include/eik.h): argument checks,
+// per-(device, stream) workspaces and the kernel sequence of each entry point.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "eik.h"
+#include "eik_adjoint.hpp"
+
+using namespace eik;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(EIK_EHIP, std::string(#expr " failed: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kThreads = 256;
+constexpr int kRings = 32;
+
+struct Workspace {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    // scheduler
+    uint64_t* items = nullptr;
+    uint32_t* ctr = nullptr;
+    uint32_t* tstate = nullptr;
+    uint64_t* tkey = nullptr;
+    int64_t tiles_cap = 0;
+    uint32_t ring_cap = 0;
+    // scalars: [0] cur [1] pending [2] flags [3] poisoned [4] srclist_count
+    int32_t* scal = nullptr;
+    unsigned long long* counters = nullptr;
+    int32_t* srclist = nullptr;
+    int64_t srclist_cap = 0;
+    // problem table and source offsets
+    Prob* probs = nullptr;
+    int64_t* src_off = nullptr;
+    int64_t probs_cap = 0;
+    std::vector<Prob> probs_host;      // what is on the device now
+    std::vector<int64_t> src_off_host;
+    // adjoint scratch
+    double* mu = nullptr;
+    int64_t mu_cap = 0;
+    uint64_t* tile_tmax = nullptr;     // per-tile largest time (adjoint priorities)
+    bool poisoned_host = true;         // rings need their first initialisation
+    int last_kind = 0;                 // 0 none, 1 forward, 2 adjoint
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
+
+template <class T>
+int grow(T** p, int64_t* cap, int64_t need, hipStream_t st) {
+    if (*cap >= need) return EIK_OK;
+    int64_t n = need + need / 4 + 64;
+    if (*p) {
+        HIP_TRY(hipStreamSynchronize(st));
+        HIP_TRY(hipFree(*p));
+        *p = nullptr;
+        *cap = 0;
+    }
+    hipError_t e = hipMalloc((void**)p, sizeof(T) * (size_t)n);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(EIK_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    *cap = n;
+    return EIK_OK;
+}
+
+int get_ws(hipStream_t st, Workspace** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto key = std::make_pair(dev, st);
+    auto it = g_ws.find(key);
+    if (it != g_ws.end()) {
+        *out = it->second;
+        return EIK_OK;
+    }
+    Workspace* w = new Workspace();
+    w->device = dev;
+    w->stream = st;
+    hipError_t e = hipMalloc((void**)&w->scal, 64 * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&w->counters, 8 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc((void**)&w->ctr, sizeof(uint32_t) * kRings * kCtrStride);
+    if (e != hipSuccess) {
+        delete w;
+        return fail(EIK_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    int32_t init[64] = {0};
+    init[3] = 1;  // poisoned: the first reset initialises the rings
+    HIP_TRY(hipMemcpy(w->scal, init, sizeof(init), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(w->ctr, 0, sizeof(uint32_t) * kRings * kCtrStride));
+    HIP_TRY(hipMemset(w->counters, 0, 8 * sizeof(unsigned long long)));
+    g_ws[key] = w;
+    *out = w;
+    return EIK_OK;
+}
+
+uint32_t next_pow2(uint64_t x) {
+    uint64_t p = 1;
+    while (p < x) p <<= 1;
+    return (uint32_t)p;
+}
+
+int ensure_tiles(Workspace& w, int64_t ntiles) {
+    if (ntiles > (int64_t)1 << 30) return fail(EIK_ENOTSUP, "more than 2^30 tiles");
+    int rc;
+    if ((rc = grow(&w.tstate, &w.tiles_cap, ntiles, w.stream))) return rc;
+    const uint32_t need_ring = next_pow2((uint64_t)w.tiles_cap);
+    if (need_ring > w.ring_cap) {
+        HIP_TRY(hipStreamSynchronize(w.stream));
+        if (w.items) HIP_TRY(hipFree(w.items));
+        if (w.tkey) HIP_TRY(hipFree(w.tkey));
+        if (w.tile_tmax) HIP_TRY(hipFree(w.tile_tmax));
+        w.items = nullptr;
+        w.tkey = nullptr;
+        w.tile_tmax = nullptr;
+        w.ring_cap = 0;
+        hipError_t e = hipMalloc((void**)&w.items, sizeof(uint64_t) * (size_t)kRings * need_ring);
+        if (e == hipSuccess) e = hipMalloc((void**)&w.tkey, sizeof(uint64_t) * (size_t)need_ring);
+        if (e == hipSuccess) e = hipMalloc((void**)&w.tile_tmax, sizeof(uint64_t) * (size_t)need_ring);
+        if (e != hipSuccess) return fail(EIK_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+        w.ring_cap = need_ring;
+        // fresh ring memory: the next reset must initialise it
+        int32_t one = 1;
+        HIP_TRY(hipMemcpy(w.scal + 3, &one, sizeof(one), hipMemcpyHostToDevice));
+    }
+    return EIK_OK;
+}
+
+int upload_table(Workspace& w, const std::vector<Prob>& probs, const std::vector<int64_t>& src_off) {
+    int64_t n = (int64_t)probs.size();
+    bool same = (int64_t)w.probs_host.size() == n && w.src_off_host == src_off &&
+                std::memcmp(w.probs_host.data(), probs.data(), sizeof(Prob) * (size_t)n) == 0;
+    if (same && w.probs) return EIK_OK;
+    if (w.probs_cap < n + 1) {
+        if (w.probs) {
+            HIP_TRY(hipStreamSynchronize(w.stream));
+            HIP_TRY(hipFree(w.probs));
+            HIP_TRY(hipFree(w.src_off));
+            w.probs = nullptr;
+            w.src_off = nullptr;
+        }
+        int64_t cap = n + 16;
+        hipError_t e = hipMalloc((void**)&w.probs, sizeof(Prob) * (size_t)cap);
+        if (e == hipSuccess) e = hipMalloc((void**)&w.src_off, sizeof(int64_t) * (size_t)(cap + 1));
+        if (e != hipSuccess) return fail(EIK_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+        w.probs_cap = cap;
+    }
+    // synchronous copies: the host vectors may be gone before the stream runs
+    HIP_TRY(hipStreamSynchronize(w.stream));
+    HIP_TRY(hipMemcpy(w.probs, probs.data(), sizeof(Prob) * (size_t)n, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(w.src_off, src_off.data(), sizeof(int64_t) * src_off.size(), hipMemcpyHostToDevice));
+    w.probs_host = probs;
+    w.src_off_host = src_off;
+    return EIK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// tile configurations
+// ---------------------------------------------------------------------------
+
+struct TileShape {
+    int x, y, z;
+};
+
+#define EIK_TILES_3D(X) X(32, 8, 4) X(16, 8, 8) X(8, 8, 8) X(64, 4, 4)
+#define EIK_TILES_2D(X) X(32, 32, 1) X(64, 16, 1) X(128, 8, 1) X(16, 16, 1)
+
+bool tile_supported(int ndim, int x, int y, int z) {
+#define EIK_MATCH(a, b, c) \
+    if (x == a && y == b && z == c) return (ndim == 3) == (c > 1);
+    EIK_TILES_3D(EIK_MATCH)
+    EIK_TILES_2D(EIK_MATCH)
+#undef EIK_MATCH
+    return false;
+}
+
+TileShape pick_tile(int ndim, const eik_opts* o) {
+    if (o && (o->tile[0] || o->tile[1] || o->tile[2])) return {o->tile[0], o->tile[1], o->tile[2]};
+    if (ndim == 3) return {32, 8, 4};
+    return {64, 16, 1};
+}
+
+int check_grid(const eik_grid* g) {
+    if (!g) return fail(EIK_EINVAL, "grid is NULL");
+    if (g->ndim != 2 && g->ndim != 3) return fail(EIK_EINVAL, "ndim must be 2 or 3");
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(EIK_EINVAL, "dims must be >= 1");
+    if (g->ndim == 2 && g->nz != 1) return fail(EIK_EINVAL, "2D grids need nz == 1");
+    if (!(g->h > 0.0) || !std::isfinite(g->h)) return fail(EIK_EINVAL, "h must be positive and finite");
+    if (g->field_kind != EIK_SPEED && g->field_kind != EIK_SLOWNESS)
+        return fail(EIK_EINVAL, "field_kind must be EIK_SPEED or EIK_SLOWNESS");
+    if ((int64_t)g->nx * g->ny * g->nz > ((int64_t)1 << 40)) return fail(EIK_ENOTSUP, "grid too large");
+    return EIK_OK;
+}
+
+int check_opts(const eik_opts* o) {
+    if (!o) return EIK_OK;
+    if (!(o->delta >= 0.0) || std::isnan(o->delta)) return fail(EIK_EINVAL, "delta must be >= 0");
+    if (o->grid_blocks < 0) return fail(EIK_EINVAL, "grid_blocks must be >= 0");
+    if (o->max_tile_visits < 0) return fail(EIK_EINVAL, "max_tile_visits must be >= 0");
+    if (o->flags != 0) return fail(EIK_EINVAL, "flags must be 0");
+    return EIK_OK;
+}
+
+Prob make_prob(const eik_grid& g, TileShape ts, int64_t pt_off, int64_t tile_off) {
+    Prob p;
+    p.nx = g.nx;
+    p.ny = g.ny;
+    p.nz = g.nz;
+    p.ntx = (g.nx + ts.x - 1) / ts.x;
+    p.nty = (g.ny + ts.y - 1) / ts.y;
+    p.ntz = (g.nz + ts.z - 1) / ts.z;
+    p.pt_off = pt_off;
+    p.tile_off = (int32_t)tile_off;
+    p.kind = g.field_kind;
+    p.h = g.h;
+    return p;
+}
+
+int64_t tiles_of(const Prob& p) { return (int64_t)p.ntx * p.nty * p.ntz; }
+
+Sched make_sched(Workspace& w, const eik_opts* o) {
+    Sched s;
+    s.items = w.items;
+    s.ctr = w.ctr;
+    s.tstate = w.tstate;
+    s.cur = w.scal + 0;
+    s.pending = w.scal + 1;
+    s.flags = (uint32_t*)(w.scal + 2);
+    s.poisoned = w.scal + 3;
+    s.counters = w.counters;
+    s.nrings = kRings;
+    s.cap_mask = w.ring_cap - 1;
+    double d = o ? o->delta : 0.0;
+    s.inv_delta = (d > 0.0 && std::isfinite(d)) ? 1.0 / d : 0.0;
+    s.max_visits = o ? (long long)o->max_tile_visits : 0;
+    return s;
+}
+
+template <class K>
+int occupancy_grid(K kernel, int threads, int* out) {
+    static std::map<const void*, int> cache;
+    static std::mutex m;
+    std::lock_guard<std::mutex> lk(m);
+    auto it = cache.find((const void*)kernel);
+    int per_cu;
+    if (it != cache.end()) {
+        per_cu = it->second;
+    } else {
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0));
+        if (per_cu < 1) per_cu = 1;
+        cache[(const void*)kernel] = per_cu;
+    }
+    int dev = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    *out = per_cu * cus;
+    return EIK_OK;
+}
+
+int blocks_for(int64_t n, int threads, int cap = 65536) {
+    int64_t b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+// The full forward sequence for one tile shape.
+template <int TX, int TY, int TZ>
+int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int64_t>& src_off,
+            int64_t ntiles, int64_t npts_total, const double* field, const int64_t* src_idx,
+            const double* src_t0, double* t, uint8_t* par, const eik_opts* o) {
+    int rc;
+    const int64_t nsrc = src_off.back();
+    if ((rc = ensure_tiles(w, ntiles))) return rc;
+    if ((rc = grow(&w.srclist, &w.srclist_cap, nsrc, w.stream))) return rc;
+    if ((rc = upload_table(w, probs, src_off))) return rc;
+    hipStream_t st = w.stream;
+    const int nprob = (int)probs.size();
+    Sched s = make_sched(w, o);
+    int32_t* srccnt = w.scal + 4;
+
+    hipLaunchKernelGGL(k_reset, dim3(blocks_for(std::max<int64_t>(ntiles, (int64_t)kRings * w.ring_cap), kThreads, 4096)),
+                       dim3(kThreads), 0, st, s, w.tkey, (int)ntiles, srccnt,
+                       (long long)kRings * w.ring_cap);
+    hipLaunchKernelGGL((k_src_mark<TX, TY, TZ>), dim3(blocks_for(nsrc, kThreads)), dim3(kThreads), 0, st,
+                       w.probs, nprob, w.src_off, src_idx, src_t0, (long long)nsrc, s, w.srclist, srccnt);
+    hipLaunchKernelGGL((k_src_fill<TX, TY, TZ>), dim3((unsigned)std::min<int64_t>(nsrc, 4096)),
+                       dim3(kThreads), 0, st, w.probs, nprob, t, w.srclist, srccnt);
+    hipLaunchKernelGGL((k_src_place<TX, TY, TZ>), dim3(blocks_for(nsrc, kThreads)), dim3(kThreads), 0, st,
+                       w.probs, nprob, w.src_off, src_idx, src_t0, (long long)nsrc, t, s);
+    HIP_TRY(hipGetLastError());
+
+    SolveArgs a;
+    a.probs = w.probs;
+    a.nprob = nprob;
+    a.field = field;
+    a.t = t;
+    a.tkey = w.tkey;
+    a.s = s;
+    int grid = 0;
+    if ((rc = occupancy_grid(k_solve<TX, TY, TZ, kThreads>, kThreads, &grid))) return rc;
+    if (o && o->grid_blocks > 0) grid = std::min(grid, o->grid_blocks);
+    if ((int64_t)grid > ntiles) grid = (int)ntiles;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL((k_solve<TX, TY, TZ, kThreads>), dim3(grid), dim3(kThreads), 0, st, a);
+    HIP_TRY(hipGetLastError());
+
+    if (par)
+        hipLaunchKernelGGL(k_parents, dim3(blocks_for(npts_total, kThreads, 1 << 16)), dim3(kThreads), 0,
+                           st, w.probs, nprob, (long long)npts_total, (const double*)t, par);
+    hipLaunchKernelGGL(k_src_unsign, dim3(blocks_for(nsrc, kThreads)), dim3(kThreads), 0, st, w.probs,
+                       nprob, w.src_off, src_idx, src_t0, (long long)nsrc, t);
+    if (o && o->max_tile_visits > 0)
+        hipLaunchKernelGGL((k_fill_unvisited<TX, TY, TZ>), dim3((unsigned)std::min<int64_t>(ntiles, 16384)),
+                           dim3(kThreads), 0, st, w.probs, nprob, (int)ntiles, t, (const uint32_t*)w.tstate);
+    HIP_TRY(hipGetLastError());
+    w.last_kind = 1;
+    return EIK_OK;
+}
+
+int dispatch_forward(TileShape ts, Workspace& w, const std::vector<Prob>& probs,
+                     const std::vector<int64_t>& src_off, int64_t ntiles, int64_t npts,
+                     const double* field, const int64_t* src_idx, const double* src_t0, double* t,
+                     uint8_t* par, const eik_opts* o) {
+#define EIK_CASE(a, b, c)                                                                      \
+    if (ts.x == a && ts.y == b && ts.z == c)                                                   \
+        return forward<a, b, c>(w, probs, src_off, ntiles, npts, field, src_idx, src_t0, t, par, o);
+    EIK_TILES_3D(EIK_CASE)
+    EIK_TILES_2D(EIK_CASE)
+#undef EIK_CASE
+    return fail(EIK_ENOTSUP, "unsupported tile shape");
+}
+
+template <int TX, int TY, int TZ>
+int adjoint(Workspace& w, const std::vector<Prob>& probs, int64_t ntiles, int64_t npts,
+            const double* field, const double* t, const uint8_t* par, const double* g, double* grad,
+            double* mu, const eik_opts* o) {
+    int rc;
+    if ((rc = ensure_tiles(w, ntiles))) return rc;
+    if (!mu) {
+        if ((rc = grow(&w.mu, &w.mu_cap, npts, w.stream))) return rc;
+        mu = w.mu;
+    }
+    std::vector<int64_t> soff(probs.size() + 1, 0);
+    if ((rc = upload_table(w, probs, soff))) return rc;
+    hipStream_t st = w.stream;
+    const int nprob = (int)probs.size();
+    Sched s = make_sched(w, o);
+    s.max_visits = 0;
+    unsigned long long* tref = w.counters + 4;
+    hipLaunchKernelGGL(k_reset, dim3(blocks_for(std::max<int64_t>(ntiles, (int64_t)kRings * w.ring_cap), kThreads, 4096)),
+                       dim3(kThreads), 0, st, s, w.tkey, (int)ntiles, w.scal + 4,
+                       (long long)kRings * w.ring_cap);
+    hipLaunchKernelGGL((k_adj_prep<TX, TY, TZ>), dim3((unsigned)std::min<int64_t>(ntiles, 65536)), dim3(kThreads),
+                       0, st, w.probs, nprob, (int)ntiles, t, w.tile_tmax, tref);
+    hipLaunchKernelGGL(k_adj_push_all, dim3(blocks_for(ntiles, kThreads, 4096)), dim3(kThreads), 0, st,
+                       (int)ntiles, (const uint64_t*)w.tile_tmax, (const unsigned long long*)tref, s);
+    HIP_TRY(hipGetLastError());
+    AdjArgs a;
+    a.probs = w.probs;
+    a.nprob = nprob;
+    a.field = field;
+    a.t = t;
+    a.par = par;
+    a.g = g;
+    a.mu = mu;
+    a.grad = grad;
+    a.tkey = w.tkey;
+    a.tref_bits = tref;
+    a.s = s;
+    int grid = 0;
+    if ((rc = occupancy_grid(k_adjoint<TX, TY, TZ, kThreads>, kThreads, &grid))) return rc;
+    if (o && o->grid_blocks > 0) grid = std::min(grid, o->grid_blocks);
+    if ((int64_t)grid > ntiles) grid = (int)ntiles;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL((k_adjoint<TX, TY, TZ, kThreads>), dim3(grid), dim3(kThreads), 0, st, a);
+    HIP_TRY(hipGetLastError());
+    w.last_kind = 2;
+    return EIK_OK;
+}
+
+int adjoint_run(Workspace& w, TileShape ts, const std::vector<Prob>& probs, int64_t ntiles, int64_t npts,
+                const double* field, const double* t, const uint8_t* par, const double* g, double* grad,
+                double* mu, const eik_opts* o) {
+#define EIK_CASE(a, b, c) \
+    if (ts.x == a && ts.y == b && ts.z == c) return adjoint<a, b, c>(w, probs, ntiles, npts, field, t, par, g, grad, mu, o);
+    EIK_TILES_3D(EIK_CASE)
+    EIK_TILES_2D(EIK_CASE)
+#undef EIK_CASE
+    return fail(EIK_ENOTSUP, "unsupported tile shape");
+}
+
+int build_problems(int32_t nprob, const eik_grid* grids, const int64_t* offsets, TileShape ts,
+                   std::vector<Prob>* probs, int64_t* ntiles, int64_t* npts) {
+    int64_t tile_off = 0;
+    for (int i = 0; i < nprob; ++i) {
+        int rc = check_grid(&grids[i]);
+        if (rc) return rc;
+        if (grids[i].ndim != grids[0].ndim) return fail(EIK_EINVAL, "all problems must share ndim");
+        int64_t n = (int64_t)grids[i].nx * grids[i].ny * grids[i].nz;
+        if (offsets[i + 1] - offsets[i] != n) return fail(EIK_EINVAL, "offsets do not match grid sizes");
+        if (offsets[i] < 0) return fail(EIK_EINVAL, "negative offset");
+        Prob p = make_prob(grids[i], ts, offsets[i], tile_off);
+        tile_off += tiles_of(p);
+        if (tile_off > ((int64_t)1 << 30)) return fail(EIK_ENOTSUP, "more than 2^30 tiles");
+        probs->push_back(p);
+    }
+    *ntiles = tile_off;
+    *npts = offsets[nprob];
+    return EIK_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// exported entry points
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char* eik_version(void) { return "eik-mi355x 0.1 (gfx950)"; }
+
+const char* eik_strerror(int code) {
+    switch (code) {
+        case EIK_OK: return "ok";
+        case EIK_EINVAL: return "invalid argument";
+        case EIK_EDOMAIN: return "field value not positive and finite";
+        case EIK_ENOMEM: return "out of device memory";
+        case EIK_EHIP: return "HIP runtime error";
+        case EIK_ELIMIT: return "tile visit limit reached (output is an upper bound)";
+        case EIK_ENOTSUP: return "not supported";
+        case EIK_EBADSRC: return "invalid source index or start time";
+        case EIK_EHANG: return "device watchdog expired";
+        default: return "unknown error";
+    }
+}
+
+const char* eik_last_error(void) { return g_last_error.c_str(); }
+
+int64_t eik_num_tiles(const eik_grid* g, const eik_opts* o) {
+    if (check_grid(g)) return -1;
+    TileShape ts = pick_tile(g->ndim, o);
+    if (!tile_supported(g->ndim, ts.x, ts.y, ts.z)) return -1;
+    return tiles_of(make_prob(*g, ts, 0, 0));
+}
+
+int eik_solve_batched(int32_t nprob, const eik_grid* grids_host, const int64_t* offsets_host,
+                      const double* field_packed, const int64_t* src_off_host, const int64_t* src_idx,
+                      const double* src_t0, double* t_packed, uint8_t* parents_packed,
+                      const eik_opts* opts, void* stream) {
+    if (nprob < 1 || !grids_host || !offsets_host || !src_off_host)
+        return fail(EIK_EINVAL, "nprob, grids, offsets and src offsets are required");
+    if (!field_packed || !src_idx || !t_packed) return fail(EIK_EINVAL, "NULL device pointer");
+    if (offsets_host[0] != 0 || src_off_host[0] != 0) return fail(EIK_EINVAL, "offsets must start at 0");
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    std::vector<int64_t> soff(src_off_host, src_off_host + nprob + 1);
+    for (int i = 0; i < nprob; ++i)
+        if (soff[i + 1] - soff[i] < 1) return fail(EIK_EINVAL, "every problem needs at least one source");
+    if (soff[nprob] > ((int64_t)1 << 31)) return fail(EIK_ENOTSUP, "too many sources");
+    TileShape ts = pick_tile(grids_host[0].ndim, opts);
+    if (!tile_supported(grids_host[0].ndim, ts.x, ts.y, ts.z))
+        return fail(EIK_ENOTSUP, "unsupported tile shape for this ndim");
+    std::vector<Prob> probs;
+    int64_t ntiles = 0, npts = 0;
+    if ((rc = build_problems(nprob, grids_host, offsets_host, ts, &probs, &ntiles, &npts))) return rc;
+    Workspace* w = nullptr;
+    if ((rc = get_ws((hipStream_t)stream, &w))) return rc;
+    return dispatch_forward(ts, *w, probs, soff, ntiles, npts, field_packed, src_idx, src_t0, t_packed,
+                            parents_packed, opts);
+}
+
+int eik_solve(const eik_grid* g, const double* field, int64_t nsrc, const int64_t* src_idx,
+              const double* src_t0, double* t_out, uint8_t* parents_out, const eik_opts* opts,
+              void* stream) {
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (nsrc < 1) return fail(EIK_EINVAL, "nsrc must be >= 1");
+    int64_t offs[2] = {0, (int64_t)g->nx * g->ny * g->nz};
+    int64_t soff[2] = {0, nsrc};
+    return eik_solve_batched(1, g, offs, field, soff, src_idx, src_t0, t_out, parents_out, opts, stream);
+}
+
+int eik_parents(const eik_grid* g, const double* t, int64_t nsrc, const int64_t* src_idx,
+                uint8_t* parents_out, void* stream) {
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!t || !parents_out || (nsrc > 0 && !src_idx)) return fail(EIK_EINVAL, "NULL device pointer");
+    if (nsrc < 0) return fail(EIK_EINVAL, "nsrc must be >= 0");
+    Workspace* w = nullptr;
+    if ((rc = get_ws((hipStream_t)stream, &w))) return rc;
+    TileShape ts = pick_tile(g->ndim, nullptr);
+    std::vector<Prob> probs{make_prob(*g, ts, 0, 0)};
+    std::vector<int64_t> soff{0, nsrc};
+    if ((rc = upload_table(*w, probs, soff))) return rc;
+    int64_t n = (int64_t)g->nx * g->ny * g->nz;
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_parents, dim3(blocks_for(n, kThreads, 1 << 16)), dim3(kThreads), 0, st, w->probs, 1,
+                       (long long)n, t, parents_out);
+    if (nsrc > 0)
+        hipLaunchKernelGGL(k_parents_mark_src, dim3(blocks_for(nsrc, kThreads)), dim3(kThreads), 0, st,
+                           w->probs, 1, w->src_off, src_idx, (long long)nsrc, parents_out);
+    HIP_TRY(hipGetLastError());
+    return EIK_OK;
+}
+
+int eik_adjoint_batched(int32_t nprob, const eik_grid* grids_host, const int64_t* offsets_host,
+                        const double* field_packed, const double* t_packed,
+                        const uint8_t* parents_packed, const double* dL_dt_packed, double* dL_ds_packed,
+                        double* mu_packed, const eik_opts* opts, void* stream) {
+    if (nprob < 1 || !grids_host || !offsets_host) return fail(EIK_EINVAL, "nprob, grids, offsets required");
+    if (!field_packed || !t_packed || !parents_packed || !dL_dt_packed || !dL_ds_packed)
+        return fail(EIK_EINVAL, "NULL device pointer");
+    if (offsets_host[0] != 0) return fail(EIK_EINVAL, "offsets must start at 0");
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    TileShape ts = pick_tile(grids_host[0].ndim, opts);
+    if (!tile_supported(grids_host[0].ndim, ts.x, ts.y, ts.z))
+        return fail(EIK_ENOTSUP, "unsupported tile shape for this ndim");
+    std::vector<Prob> probs;
+    int64_t ntiles = 0, npts = 0;
+    if ((rc = build_problems(nprob, grids_host, offsets_host, ts, &probs, &ntiles, &npts))) return rc;
+    Workspace* w = nullptr;
+    if ((rc = get_ws((hipStream_t)stream, &w))) return rc;
+    return adjoint_run(*w, ts, probs, ntiles, npts, field_packed, t_packed, parents_packed, dL_dt_packed,
+                       dL_ds_packed, mu_packed, opts);
+}
+
+int eik_adjoint(const eik_grid* g, const double* field, const double* t, const uint8_t* parents,
+                const double* dL_dt, double* dL_dslowness, double* mu_out, const eik_opts* opts,
+                void* stream) {
+    int rc = check_grid(g);
+    if (rc) return rc;
+    int64_t offs[2] = {0, (int64_t)g->nx * g->ny * g->nz};
+    return eik_adjoint_batched(1, g, offs, field, t, parents, dL_dt, dL_dslowness, mu_out, opts, stream);
+}
+
+int eik_reserve(int64_t ntiles, int64_t npts, void* stream) {
+    if (ntiles < 0 || npts < 0) return fail(EIK_EINVAL, "sizes must be >= 0");
+    Workspace* w = nullptr;
+    int rc;
+    if ((rc = get_ws((hipStream_t)stream, &w))) return rc;
+    if ((rc = ensure_tiles(*w, std::max<int64_t>(ntiles, 1)))) return rc;
+    if ((rc = grow(&w->mu, &w->mu_cap, std::max<int64_t>(npts, 1), w->stream))) return rc;
+    return EIK_OK;
+}
+
+int eik_status(void* stream, eik_stats* out) {
+    Workspace* w = nullptr;
+    int rc;
+    if ((rc = get_ws((hipStream_t)stream, &w))) return rc;
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    int32_t sc[8];
+    unsigned long long ctr[8];
+    HIP_TRY(hipMemcpy(sc, w->scal, sizeof(sc), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(ctr, w->counters, sizeof(ctr), hipMemcpyDeviceToHost));
+    uint32_t flags = (uint32_t)sc[2];
+    int code = EIK_OK;
+    if (flags & kFlagWatchdog) code = EIK_EHANG;
+    else if (flags & kFlagBadSrc) code = EIK_EBADSRC;
+    else if (flags & kFlagDomain) code = EIK_EDOMAIN;
+    else if (flags & kFlagLimit) code = EIK_ELIMIT;
+    if (out) {
+        out->tile_visits = (int64_t)ctr[0];
+        out->point_updates = (int64_t)ctr[1];
+        out->relax_passes = (int64_t)ctr[2];
+        out->ntiles = 0;
+        out->flags = flags;
+        out->status = code;
+    }
+    if (code != EIK_OK) g_last_error = eik_strerror(code);
+    return code;
+}
+
+void eik_release(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto& kv : g_ws) {
+        Workspace* w = kv.second;
+        int cur = 0;
+        if (hipGetDevice(&cur) == hipSuccess && cur != w->device) (void)hipSetDevice(w->device);
+        (void)hipStreamSynchronize(w->stream);
+        (void)hipFree(w->items);
+        (void)hipFree(w->ctr);
+        (void)hipFree(w->tstate);
+        (void)hipFree(w->tkey);
+        (void)hipFree(w->scal);
+        (void)hipFree(w->counters);
+        (void)hipFree(w->srclist);
+        (void)hipFree(w->probs);
+        (void)hipFree(w->src_off);
+        (void)hipFree(w->mu);
+        (void)hipFree(w->tile_tmax);
+        if (cur != w->device) (void)hipSetDevice(cur);
+        delete w;
+    }
+    g_ws.clear();
+}
+
+}  // extern "C"

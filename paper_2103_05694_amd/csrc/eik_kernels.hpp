@@ -1,0 +1,537 @@
+// Forward kernels: per-solve reset, source placement, the persistent
+// soft-priority tile solver, finalisation and the upwind-parent record.
+//
+// The persistent solver realises the paper's asynchronous marching method
+// (Algorithm "Asynchronous Marching Method") with a tile of the grid as the unit
+// of work: a workgroup claims the approximately earliest active tile, stages
+// its times, the 1-cell halo and the per-point constants in LDS, applies the
+// update operator (Algorithm "Eikonal Update Operator" with the exactly monotone
+// rounding) to dirty points until nothing in the tile changes, writes the
+// lowered points back and activates the face neighbours whose halo changed with
+// the priority floor(t / delta).  Theorem 1 (monotone + causal => one fixed
+// point for every order) is what makes the racing, out-of-order schedule
+// produce the same bits as sequential fast marching.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "eik_op.hpp"
+#include "eik_sched.hpp"
+
+namespace eik {
+
+// One problem of a (possibly batched) launch.
+struct Prob {
+    int32_t nx, ny, nz;      // points per axis
+    int32_t ntx, nty, ntz;   // tiles per axis
+    int64_t pt_off;          // first point in the packed arrays
+    int32_t tile_off;        // first global tile id
+    int32_t kind;            // 0 speed (q = h/v), 1 slowness (q = h*s)
+    double h;
+};
+
+struct SolveArgs {
+    const Prob* probs;
+    int nprob;
+    const double* field;
+    double* t;
+    uint64_t* tkey;          // [ntiles] pending requeue key (bits of a positive double)
+    Sched s;
+};
+
+__device__ __forceinline__ int find_prob(const Prob* probs, int nprob, int tile) {
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (probs[mid].tile_off <= tile) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ double field_q(double f, double h, int kind, bool& ok) {
+    double q = kind == 0 ? h / f : h * f;
+    double c = q * q;
+    ok = (f > 0.0) && (f < inf64()) && (c > 0.0) && (c < inf64());
+    return q;
+}
+
+// ---------------------------------------------------------------------------
+// per-solve set-up
+// ---------------------------------------------------------------------------
+
+// Clears tile states and requeue keys, the window, counters and flags.  When the
+// previous solve on this workspace ended abnormally (`poisoned`), it also
+// re-initialises the rings so no stale slot can be taken for a new item.
+__global__ void k_reset(Sched s, uint64_t* tkey, int ntiles, int32_t* srclist_count,
+                        long long ring_words) {
+    const bool wipe = __hip_atomic_load(s.poisoned, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    for (long long i = i0; i < ntiles; i += stride) {
+        s.tstate[i] = 0u;
+        tkey[i] = kInfBits;
+    }
+    if (wipe) {
+        for (long long i = i0; i < ring_words; i += stride) s.items[i] = ~0ull;
+        for (long long i = i0; i < (long long)s.nrings * kCtrStride; i += stride) s.ctr[i] = 0u;
+    }
+    if (i0 == 0) {
+        *s.cur = 0;
+        *s.pending = 0;
+        *s.flags = 0u;
+        s.counters[0] = s.counters[1] = s.counters[2] = s.counters[4] = 0ull;
+        *srclist_count = 0;
+    }
+}
+
+__device__ __forceinline__ int find_src_prob(const int64_t* src_off, int nprob, long long g) {
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (src_off[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ uint32_t tile_of_point(const Prob& P, int64_t local) {
+    int64_t x = local % P.nx, y = (local / P.nx) % P.ny, z = local / ((int64_t)P.nx * P.ny);
+    return (uint32_t)(P.tile_off + ((z / TZ) * P.nty + (y / TY)) * P.ntx + (x / TX));
+}
+
+__device__ __forceinline__ bool src_ok(const Prob& P, int64_t idx, double t0) {
+    int64_t n = (int64_t)P.nx * P.ny * P.nz;
+    return idx >= 0 && idx < n && t0 >= 0.0 && t0 < inf64() && !signbit(t0);
+}
+
+// Marks source tiles (S) and lists each one once.
+template <int TX, int TY, int TZ>
+__global__ void k_src_mark(const Prob* probs, int nprob, const int64_t* src_off,
+                           const int64_t* src_idx, const double* src_t0, long long nsrc, Sched s,
+                           int32_t* srclist, int32_t* srclist_count) {
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g == 0) *s.poisoned = 0;  // the reset before this kernel has wiped the rings
+    if (g >= nsrc) return;
+    int p = find_src_prob(src_off, nprob, g);
+    const Prob P = probs[p];
+    int64_t idx = src_idx[g];
+    double t0 = src_t0 ? src_t0[g] : 0.0;
+    if (!src_ok(P, idx, t0)) {
+        set_flag(s, kFlagBadSrc);
+        return;
+    }
+    uint32_t tile = tile_of_point<TX, TY, TZ>(P, idx);
+    uint32_t old = __hip_atomic_fetch_or(s.tstate + tile, kS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!(old & kS)) {
+        int k = __hip_atomic_fetch_add(srclist_count, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        srclist[k] = (int32_t)tile;
+    }
+}
+
+// Fills every listed source tile with +inf (blocks stride over the list).
+template <int TX, int TY, int TZ>
+__global__ void k_src_fill(const Prob* probs, int nprob, double* t, const int32_t* srclist,
+                           const int32_t* srclist_count) {
+    const int count = *srclist_count;
+    for (int b = blockIdx.x; b < count; b += gridDim.x) {
+        const int tile = srclist[b];
+        const Prob P = probs[find_prob(probs, nprob, tile)];
+        const int tl = tile - P.tile_off;
+        const int tx = tl % P.ntx, ty = (tl / P.ntx) % P.nty, tz = tl / (P.ntx * P.nty);
+        for (int i = threadIdx.x; i < TX * TY * TZ; i += blockDim.x) {
+            int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
+            int x = tx * TX + lx, y = ty * TY + ly, z = tz * TZ + lz;
+            if (x < P.nx && y < P.ny && z < P.nz)
+                t[P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x] = inf64();
+        }
+    }
+}
+
+// Writes each source as -t0 (the sign bit marks a fixed point during the solve;
+// min over duplicates through the signed image, where -0.0 is the smallest) and
+// queues its tile.
+template <int TX, int TY, int TZ>
+__global__ void k_src_place(const Prob* probs, int nprob, const int64_t* src_off,
+                            const int64_t* src_idx, const double* src_t0, long long nsrc,
+                            double* t, Sched s) {
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nsrc) return;
+    int p = find_src_prob(src_off, nprob, g);
+    const Prob P = probs[p];
+    int64_t idx = src_idx[g];
+    double t0 = src_t0 ? src_t0[g] : 0.0;
+    if (!src_ok(P, idx, t0)) return;
+    long long* ti = (long long*)(t + P.pt_off + idx);
+    __hip_atomic_fetch_min(ti, (long long)as_u64(-t0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t tile = tile_of_point<TX, TY, TZ>(P, idx);
+    uint32_t old = __hip_atomic_fetch_or(s.tstate + tile, kQ | kV, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    if (!(old & kQ)) activate_push(s, tile, t0);
+}
+
+// Restores +t0 at the sources.
+__global__ void k_src_unsign(const Prob* probs, int nprob, const int64_t* src_off,
+                             const int64_t* src_idx, const double* src_t0, long long nsrc, double* t) {
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nsrc) return;
+    int p = find_src_prob(src_off, nprob, g);
+    const Prob P = probs[p];
+    int64_t idx = src_idx[g];
+    double t0 = src_t0 ? src_t0[g] : 0.0;
+    if (!src_ok(P, idx, t0)) return;
+    double* ti = t + P.pt_off + idx;
+    *ti = fabs(*ti);
+}
+
+// After a capped (ELIMIT) solve: tiles never visited still hold stale memory;
+// give them +inf so the output is a valid upper bound.
+template <int TX, int TY, int TZ>
+__global__ void k_fill_unvisited(const Prob* probs, int nprob, int ntiles, double* t,
+                                 const uint32_t* tstate) {
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        if (tstate[tile] & kV) continue;
+        const Prob P = probs[find_prob(probs, nprob, tile)];
+        int tl = tile - P.tile_off;
+        int tx = tl % P.ntx, ty = (tl / P.ntx) % P.nty, tz = tl / (P.ntx * P.nty);
+        for (int i = threadIdx.x; i < TX * TY * TZ; i += blockDim.x) {
+            int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
+            int x = tx * TX + lx, y = ty * TY + ly, z = tz * TZ + lz;
+            if (x < P.nx && y < P.ny && z < P.nz)
+                t[P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x] = inf64();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the persistent solver
+// ---------------------------------------------------------------------------
+
+template <int TX, int TY, int TZ, int NT>
+struct TileCfg {
+    static constexpr bool D3 = TZ > 1;
+    static constexpr int SY = TX + 2;
+    static constexpr int SZ = (TX + 2) * (TY + 2);
+    static constexpr int HZ = D3 ? TZ + 2 : 1;
+    static constexpr int ZOFF = D3 ? 1 : 0;
+    static constexpr int NLDS = SZ * HZ;
+    static constexpr int NP = TX * TY * TZ;
+    static constexpr int NPT = NP / NT;
+    static_assert(NP % NT == 0, "tile points must be a multiple of the block size");
+    static_assert(NT % 64 == 0, "block must be whole waves");
+    __device__ static constexpr int lds(int lx, int ly, int lz) {
+        return (lz + ZOFF) * SZ + (ly + 1) * SY + (lx + 1);
+    }
+};
+
+__device__ __forceinline__ double hload(const double* p) {
+    // Halo cells belong to tiles other workgroups may be writing right now.
+    uint64_t u = __hip_atomic_load((const uint64_t*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return fabs(as_f64(u));
+}
+
+__device__ __forceinline__ void tstore(double* p, double v) {
+    __hip_atomic_store((uint64_t*)p, as_u64(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int TX, int TY, int TZ, int NT>
+__global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
+    using C = TileCfg<TX, TY, TZ, NT>;
+    constexpr int NPT = C::NPT;
+    __shared__ double sT[C::NLDS];
+    __shared__ double sQ[C::NP];
+    __shared__ uint8_t sDirty[2][C::NP];
+    __shared__ int s_tile;
+    __shared__ uint32_t s_state;
+    __shared__ uint32_t s_nb[6];
+    __shared__ unsigned long long s_face[6];
+    __shared__ unsigned int s_upd;
+
+    const int tid = threadIdx.x;
+    const Sched& S = A.s;
+
+    for (;;) {
+        // ---- claim ------------------------------------------------------
+        if (tid < 64) {
+            int tile = claim(S);
+            if (tid == 0) {
+                s_tile = tile;
+                if (tile >= 0) {
+                    unsigned long long v = __hip_atomic_fetch_add(S.counters, 1ull, __ATOMIC_RELAXED,
+                                                                  __HIP_MEMORY_SCOPE_AGENT);
+                    // Q -> R, acquiring everything released before the activations.
+                    uint32_t st = __hip_atomic_fetch_xor(S.tstate + tile, kQ | kR, __ATOMIC_ACQUIRE,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                    if ((st & (kQ | kR)) != kQ) set_flag(S, kFlagWatchdog);
+                    if (S.max_visits > 0 && (long long)v >= S.max_visits) {
+                        set_flag(S, kFlagLimit);
+                        st |= 0x80000000u;  // skip marker
+                    }
+                    s_state = st;
+                }
+            }
+        }
+        __syncthreads();
+        const int tile = s_tile;
+        if (tile < 0) break;
+        const uint32_t st = s_state;
+        const Prob P = A.probs[A.nprob == 1 ? 0 : find_prob(A.probs, A.nprob, tile)];
+        const int tl = tile - P.tile_off;
+        const int tx = tl % P.ntx, ty = (tl / P.ntx) % P.nty, tz = tl / (P.ntx * P.nty);
+        const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+
+        if (st & 0x80000000u) {  // visit cap reached: drop the tile
+            if (tid == 0) finish_run(S, (uint32_t)tile, 0.0);
+            __syncthreads();
+            continue;
+        }
+        const bool visited = (st & kV) != 0;
+
+        // neighbour tile states: x-, x+, y-, y+, z-, z+ (V bit says whether its
+        // interior holds real values; otherwise its face reads as +inf)
+        if (tid < 6) {
+            int d = tid >> 1, side = tid & 1;
+            int nt[3] = {tx, ty, tz};
+            int lim[3] = {P.ntx, P.nty, P.ntz};
+            nt[d] += side ? 1 : -1;
+            uint32_t w = 0;
+            if (nt[d] >= 0 && nt[d] < lim[d]) {
+                int nid = P.tile_off + (nt[2] * P.nty + nt[1]) * P.ntx + nt[0];
+                w = ld_rlx(S.tstate + nid) | 0x40000000u;  // bit 30: tile exists
+            }
+            s_nb[tid] = w;
+            s_face[tid] = kInfBits;
+        }
+        if (tid == 0) s_upd = 0u;
+
+        // ---- stage the tile in LDS ---------------------------------------
+        double t_in[NPT];
+#pragma unroll
+        for (int j = 0; j < NPT; ++j) {
+            const int p = tid + j * NT;
+            const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+            const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+            double tv = inf64(), q = 0.0;
+            if (x < P.nx && y < P.ny && z < P.nz) {
+                const int64_t gi = P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x;
+                bool ok;
+                q = field_q(A.field[gi], P.h, P.kind, ok);
+                if (!ok) {
+                    set_flag(S, kFlagDomain);
+                    q = 0.0;
+                }
+                if (visited) {
+                    tv = A.t[gi];
+                    if (signbit(tv)) {  // a source: fixed
+                        tv = fabs(tv);
+                        q = 0.0;
+                    }
+                }
+            }
+            sT[C::lds(lx, ly, lz)] = tv;
+            sQ[p] = q;
+            sDirty[0][p] = 1;
+            sDirty[1][p] = 0;
+            t_in[j] = tv;
+        }
+        __syncthreads();  // s_nb ready
+
+        // halo: x faces, y faces, (z faces)
+        {
+            constexpr int NXF = 2 * TY * TZ, NYF = 2 * TX * TZ, NZF = C::D3 ? 2 * TX * TY : 0;
+            for (int i = tid; i < NXF + NYF + NZF; i += NT) {
+                int lx, ly, lz, f;
+                if (i < NXF) {
+                    int side = i / (TY * TZ), r = i % (TY * TZ);
+                    ly = r % TY; lz = r / TY; lx = side ? TX : -1; f = side;
+                } else if (i < NXF + NYF) {
+                    int k = i - NXF, side = k / (TX * TZ), r = k % (TX * TZ);
+                    lx = r % TX; lz = r / TX; ly = side ? TY : -1; f = 2 + side;
+                } else {
+                    int k = i - NXF - NYF, side = k / (TX * TY), r = k % (TX * TY);
+                    lx = r % TX; ly = r / TX; lz = side ? TZ : -1; f = 4 + side;
+                }
+                const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+                double v = inf64();
+                const uint32_t nb = s_nb[f];
+                if ((nb & kV) && x >= 0 && x < P.nx && y >= 0 && y < P.ny && z >= 0 && z < P.nz)
+                    v = hload(A.t + P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x);
+                sT[C::lds(lx, ly, lz)] = v;
+            }
+        }
+        __syncthreads();
+
+        // ---- relax until the tile is quiet --------------------------------
+        int cb = 0;
+        int passes = 0;
+        for (;;) {
+            bool any = false;
+#pragma unroll
+            for (int j = 0; j < NPT; ++j) {
+                const int p = tid + j * NT;
+                if (sDirty[cb][p]) {
+                    sDirty[cb][p] = 0;
+                    const double q = sQ[p];
+                    if (q > 0.0) {
+                        const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+                        const int L = C::lds(lx, ly, lz);
+                        const double tc = sT[L];
+                        const double ax = fmin(sT[L - 1], sT[L + 1]);
+                        const double ay = fmin(sT[L - C::SY], sT[L + C::SY]);
+                        const double az = C::D3 ? fmin(sT[L - C::SZ], sT[L + C::SZ]) : inf64();
+                        bool ch;
+                        const double r = update(ax, ay, az, q, q * q, tc, ch);
+                        if (ch) {
+                            sT[L] = r;
+                            any = true;
+                            uint8_t* nd = sDirty[cb ^ 1];
+                            if (lx > 0) nd[p - 1] = 1;
+                            if (lx < TX - 1) nd[p + 1] = 1;
+                            if (ly > 0) nd[p - TX] = 1;
+                            if (ly < TY - 1) nd[p + TX] = 1;
+                            if (C::D3) {
+                                if (lz > 0) nd[p - TX * TY] = 1;
+                                if (lz < TZ - 1) nd[p + TX * TY] = 1;
+                            }
+                        }
+                    }
+                }
+            }
+            ++passes;
+            if (!__syncthreads_or(any)) break;
+            cb ^= 1;
+            if (passes > (1 << 20)) {
+                if (tid == 0) set_flag(S, kFlagWatchdog);
+                break;
+            }
+        }
+
+        // ---- write back lowered points, gather lowered face minima ---------
+        unsigned int nchg = 0;
+        double fmin_[6] = {inf64(), inf64(), inf64(), inf64(), inf64(), inf64()};
+#pragma unroll
+        for (int j = 0; j < NPT; ++j) {
+            const int p = tid + j * NT;
+            const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+            const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+            if (x < P.nx && y < P.ny && z < P.nz) {
+                const double v = sT[C::lds(lx, ly, lz)];
+                const bool lowered = v < t_in[j];
+                if (lowered || !visited) {
+                    tstore(A.t + P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x, v);
+                }
+                if (lowered) {
+                    ++nchg;
+                    if (lx == 0) fmin_[0] = fmin(fmin_[0], v);
+                    if (lx == TX - 1) fmin_[1] = fmin(fmin_[1], v);
+                    if (ly == 0) fmin_[2] = fmin(fmin_[2], v);
+                    if (ly == TY - 1) fmin_[3] = fmin(fmin_[3], v);
+                    if (C::D3) {
+                        if (lz == 0) fmin_[4] = fmin(fmin_[4], v);
+                        if (lz == TZ - 1) fmin_[5] = fmin(fmin_[5], v);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            if (fmin_[f] < inf64()) atomicMin(&s_face[f], (unsigned long long)as_u64(fmin_[f]));
+        }
+        if (nchg) atomicAdd(&s_upd, nchg);
+        __syncthreads();
+
+        // ---- publish: V bit, release, activate neighbours, end the run ------
+        if (tid == 0) {
+            if (!visited)
+                __hip_atomic_fetch_or(S.tstate + tile, kV, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            for (int f = 0; f < 6; ++f) {
+                const uint32_t nb = s_nb[f];
+                const unsigned long long fm = s_face[f];
+                if ((nb & 0x40000000u) && fm != kInfBits) {
+                    int d = f >> 1, side = f & 1;
+                    int nt[3] = {tx, ty, tz};
+                    nt[d] += side ? 1 : -1;
+                    uint32_t nid = (uint32_t)(P.tile_off + (nt[2] * P.nty + nt[1]) * P.ntx + nt[0]);
+                    uint32_t old = __hip_atomic_fetch_or(S.tstate + nid, kQ, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                    const double tm = as_f64(fm);
+                    if ((old & (kQ | kR)) == 0) {
+                        activate_push(S, nid, tm);
+                    } else if (old & kR) {
+                        __hip_atomic_fetch_min((unsigned long long*)(A.tkey + nid), fm,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+            }
+            __hip_atomic_fetch_add(S.counters + 1, (unsigned long long)s_upd, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(S.counters + 2, (unsigned long long)passes, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            uint64_t kb = __hip_atomic_exchange((unsigned long long*)(A.tkey + tile), kInfBits,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            double requeue_t = kb == kInfBits ? 0.0 : as_f64(kb);
+            finish_run(S, (uint32_t)tile, requeue_t);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// upwind-parent record
+// ---------------------------------------------------------------------------
+
+// One thread per point over all problems.  Reads |t| (a set sign bit marks a
+// source while the solve's encoding is still in place: then bit 7 is written).
+__global__ void k_parents(const Prob* probs, int nprob, long long npts_total, const double* t,
+                          uint8_t* par) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < npts_total; g += stride) {
+        int lo = 0, hi = nprob - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (probs[mid].pt_off <= g) lo = mid; else hi = mid - 1;
+        }
+        const Prob P = probs[lo];
+        const int64_t i = g - P.pt_off;
+        const double* tp = t + P.pt_off;
+        const double ti = tp[i];
+        if (signbit(ti)) {
+            par[g] = 0x80;
+            continue;
+        }
+        const int64_t x = i % P.nx, y = (i / P.nx) % P.ny, z = i / ((int64_t)P.nx * P.ny);
+        const int64_t sy = P.nx, sz = (int64_t)P.nx * P.ny;
+        uint8_t b = 0;
+        {
+            double l = x > 0 ? fabs(tp[i - 1]) : inf64();
+            double r = x < P.nx - 1 ? fabs(tp[i + 1]) : inf64();
+            if (fmin(l, r) < ti) b |= (l <= r) ? 1 : 2;
+        }
+        {
+            double l = y > 0 ? fabs(tp[i - sy]) : inf64();
+            double r = y < P.ny - 1 ? fabs(tp[i + sy]) : inf64();
+            if (fmin(l, r) < ti) b |= ((l <= r) ? 1 : 2) << 2;
+        }
+        if (P.nz > 1) {
+            double l = z > 0 ? fabs(tp[i - sz]) : inf64();
+            double r = z < P.nz - 1 ? fabs(tp[i + sz]) : inf64();
+            if (fmin(l, r) < ti) b |= ((l <= r) ? 1 : 2) << 4;
+        }
+        par[g] = b;
+    }
+}
+
+// Marks sources in a parent record computed from final (unsigned) times.
+__global__ void k_parents_mark_src(const Prob* probs, int nprob, const int64_t* src_off,
+                                   const int64_t* src_idx, long long nsrc, uint8_t* par) {
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nsrc) return;
+    int p = find_src_prob(src_off, nprob, g);
+    const Prob P = probs[p];
+    int64_t idx = src_idx[g];
+    if (idx < 0 || idx >= (int64_t)P.nx * P.ny * P.nz) return;
+    par[P.pt_off + idx] = 0x80;
+}
+
+}  // namespace eik
