@@ -1,0 +1,333 @@
+#!/usr/bin/env python3
+"""Benchmark of the Eikonal solver on one MI355X.
+
+Headline (the JSON `value`): grid points solved per second for the 3D
+512x512x256 layered + noise model (h = 10 m, 1500..6000 m/s in 8 layers times
+(1 + 0.1 g), one source at the surface centre, FP64).  One step = one complete
+forward solve through the C ABI: per-solve reset, source placement, the
+persistent soft-priority tile kernel and finalisation, with the speed field
+already resident in HBM.
+
+Also reported on the same JSON line:
+  * roofline: the persistent solve kernel's algorithmic bytes (16 B per point:
+    read the speed once, write the time once) over its mean duration measured
+    with HIP events on its stream during the timed steps, against 8 TB/s;
+    `traffic` comes from the committed rocprofv3 counter summary when it was
+    taken on the current kernel source, else null;
+  * cpu_baseline: the oracle (sequential binary-heap fast marching, 1 thread)
+    on a bounded sample (the same recipe at 256x256x128);
+  * batched: forward + adjoint shots/s for a tomography batch, one graph replay
+    of two persistent launches vs one plain solve + adjoint per shot.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "grid points solved/s & % HBM peak; batched fwd+adjoint shots/s vs plain"
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_solve_layered_512x512x256_pmc.txt")
+
+
+def kernel_source_hash() -> str:
+    csrc = os.path.join(ROOT, "paper_2103_05694_amd", "csrc")
+    m = hashlib.sha256()
+    for fn in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, fn), "rb") as f:
+            m.update(fn.encode())
+            m.update(f.read())
+    return m.hexdigest()[:16]
+
+
+def read_traffic(npts: int):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on this kernel source."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    kv = {}
+    with open(TRAFFIC_SUMMARY) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline() -> dict:
+    import numpy as np  # noqa: F401
+    import oracle
+    import workloads as W
+    p = W.layered_3d(256, 256, 128, h=10.0, seed=2)
+    t0 = time.perf_counter()
+    oracle.fmm(p.field, p.h, p.src)
+    dt = time.perf_counter() - t0
+    return {"value": p.npts / dt, "unit": "grid points/s", "cores": 1, "kind": "oracle",
+            "sample": "same layered+noise recipe (seed 2, surface-centre source) at 256x256x128 = "
+                      f"{p.npts} points, one sequential binary-heap solve, {dt:.1f} s"}
+
+
+def bench_single(args, torch, eik, W) -> dict:
+    p = W.layered_3d(512, 512, 256, h=10.0, seed=2)
+    log(f"input {p.name} sha {p.sha256()}")
+    f = torch.from_numpy(p.field).cuda()
+    src = torch.as_tensor(p.src).cuda()
+    out = torch.empty_like(f)
+    kw = dict(delta=args.delta, tile=args.tile, out=out, check_status=False)
+    for _ in range(args.warmup):
+        eik.solve(f, p.h, src, **kw)
+    eik.status()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        eik.solve(f, p.h, src, time_kernels=True, **kw)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = eik.status()
+    ms = wall * 1e3 / args.steps
+    kernel_ms = st.kernel_ms
+    algo_bytes = 16.0 * p.npts
+    achieved = algo_bytes / (kernel_ms * 1e-3) / 1e9
+    traffic = read_traffic(p.npts)
+    res = {
+        "npts": p.npts, "ms_per_step": ms, "kernel_ms": kernel_ms,
+        "kernel_launches": int(st.kernel_launches),
+        "visits_per_tile": st.tile_visits / max(st.ntiles, 1),
+        "updates_per_point": st.point_updates / p.npts,
+        "passes_per_visit": st.relax_passes / max(st.tile_visits, 1),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_solve (persistent soft-priority tile solver)",
+                     "algorithmic_bytes_per_launch": algo_bytes},
+    }
+    # with the parent record (adds 9 B/pt)
+    if args.parents:
+        par = torch.empty(f.shape, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(max(args.steps // 2, 1)):
+            eik.solve(f, p.h, src, parents=True, parents_out=par, **kw)
+        torch.cuda.synchronize()
+        res["ms_per_step_with_parents"] = (time.perf_counter() - t0) * 1e3 / max(args.steps // 2, 1)
+        eik.status()
+    return res
+
+
+def bench_tomography(args, torch, eik, W) -> dict:
+    """32 shots on 256x256x128 (h = 10 m), 1024 surface receivers, observed
+    times from a +5% slowness blob; batched graph replay vs per-shot plain."""
+    from paper_2103_05694_amd.batch import ShotBatch
+    case = W.tomography(256, 256, 128, nshots=args.shots, seed=5)
+    s0 = torch.from_numpy(case.s0).cuda()
+    s_true = torch.from_numpy(case.s_true).cuda()
+    srcs = [torch.tensor([int(s)]) for s in case.sources]
+    rec = torch.as_tensor(case.receivers).cuda()
+    obs = ShotBatch([s_true] * args.shots, case.h, srcs, [rec] * args.shots, kind="slowness",
+                    delta=args.tomo_delta)
+    obs.step()
+    obs.sync()
+    eik.status(obs.stream)
+    t_obs = [v.reshape(-1).index_select(0, rec) for v in obs.shot_views(obs.t)]
+    sb = ShotBatch([s0] * args.shots, case.h, srcs, [rec] * args.shots, t_obs=t_obs, kind="slowness",
+                   delta=args.tomo_delta)
+    sb.capture()
+    reps = max(args.steps // 4, 2)
+    for _ in range(2):
+        sb.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sb.replay()
+    torch.cuda.synchronize()
+    batched_s = (time.perf_counter() - t0) / reps
+    eik.status(sb.stream)
+    t_plain = torch.empty_like(sb.t)
+    g_plain = torch.empty_like(sb.grad)
+    sb.plain_step(t_plain, g_plain)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sb.plain_step(t_plain, g_plain)
+    torch.cuda.synchronize()
+    plain_s = (time.perf_counter() - t0) / reps
+    eik.status()
+    same_t = bool(torch.equal(t_plain, sb.t))
+    same_g = bool(torch.equal(g_plain, sb.grad))
+    return {"workload": f"tomography {args.shots} shots on 256x256x128, 1024 surface receivers",
+            "shots_per_s_batched_graph": args.shots / batched_s,
+            "shots_per_s_plain": args.shots / plain_s,
+            "speedup": plain_s / batched_s, "ms_per_batch_graph": batched_s * 1e3,
+            "ms_per_batch_plain": plain_s * 1e3, "bitwise_equal_t": same_t,
+            "bitwise_equal_grad": same_g, "loss": sb.loss()}
+
+
+def bench_uneven(args, torch, eik, W) -> dict:
+    """64 shots on layered models of uneven sizes (128^3, 192x192x128,
+    256x256x128), one random surface source each, misfit at a 32x32 surface
+    receiver grid against a +5% blob model; batched graph vs plain."""
+    from paper_2103_05694_amd.batch import ShotBatch
+    import numpy as np
+    shots = W.batched_shots(args.uneven_shots, seed=4)
+    fields, fields_true, srcs, recs = [], [], [], []
+    rng = np.random.default_rng(44)
+    for p in shots:
+        s = 1.0 / p.field
+        c = (int(rng.integers(20, p.nx - 20)), int(rng.integers(20, p.ny - 20)), int(rng.integers(20, p.nz - 20)))
+        fields.append(torch.from_numpy(s).cuda())
+        fields_true.append(torch.from_numpy(s * W.blob_perturbation(p.shape, c)).cuda())
+        srcs.append(torch.as_tensor(p.src))
+        step_x, step_y = p.nx // 32, p.ny // 32
+        rx = step_x // 2 + step_x * np.arange(32)
+        ry = step_y // 2 + step_y * np.arange(32)
+        RX, RY = np.meshgrid(rx, ry, indexing="xy")
+        recs.append(torch.as_tensor(W.flat_index(RX.ravel(), RY.ravel(), 0, p.nx, p.ny)).cuda())
+    npts = sum(p.npts for p in shots)
+    obs = ShotBatch(fields_true, 10.0, srcs, recs, kind="slowness", delta=args.tomo_delta)
+    obs.step()
+    obs.sync()
+    eik.status(obs.stream)
+    t_obs = [v.reshape(-1).index_select(0, r) for v, r in zip(obs.shot_views(obs.t), recs)]
+    del obs
+    sb = ShotBatch(fields, 10.0, srcs, recs, t_obs=t_obs, kind="slowness", delta=args.tomo_delta)
+    sb.capture()
+    reps = max(args.steps // 8, 2)
+    sb.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sb.replay()
+    torch.cuda.synchronize()
+    batched_s = (time.perf_counter() - t0) / reps
+    eik.status(sb.stream)
+    t_plain = torch.empty_like(sb.t)
+    g_plain = torch.empty_like(sb.grad)
+    sb.plain_step(t_plain, g_plain)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sb.plain_step(t_plain, g_plain)
+    torch.cuda.synchronize()
+    plain_s = (time.perf_counter() - t0) / reps
+    eik.status()
+    return {"workload": f"{len(shots)} uneven layered shots, {npts} points total",
+            "shots_per_s_batched_graph": len(shots) / batched_s,
+            "shots_per_s_plain": len(shots) / plain_s, "speedup": plain_s / batched_s,
+            "points_per_s_batched_fwd_adj": npts / batched_s,
+            "bitwise_equal_t": bool(torch.equal(t_plain, sb.t)),
+            "bitwise_equal_grad": bool(torch.equal(g_plain, sb.grad))}
+
+
+def profile_mode(args, torch, eik, W) -> None:
+    """A short run for rocprofv3: a plain 1 GiB device copy (counter
+    calibration), then a few solves of the headline workload."""
+    n = (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    p = W.layered_3d(512, 512, 256, h=10.0, seed=2)
+    f = torch.from_numpy(p.field).cuda()
+    src = torch.as_tensor(p.src).cuda()
+    for i in range(args.steps):
+        eik.solve(f, p.h, src, delta=args.delta, tile=args.tile, check_status=False)
+        torch.cuda.synchronize()
+        log(f"profile solve {i} done")
+    eik.status()
+    print(json.dumps({"profile_mode": True, "copy_bytes_each_way": n * 8, "solves": args.steps,
+                      "npts": p.npts, "source_hash": kernel_source_hash()}), flush=True)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--delta", type=float, default=None, help="bucket width (s); default from the tuning cache")
+    ap.add_argument("--tile", type=str, default=None, help="e.g. 32x8x4; default from the tuning cache")
+    ap.add_argument("--tomo-delta", type=float, default=0.05)
+    ap.add_argument("--shots", type=int, default=32)
+    ap.add_argument("--uneven-shots", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--parents", action="store_true")
+    ap.add_argument("--profile-mode", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(shots would shard across GPUs with one all-reduce of the gradient; not built).",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    import workloads as W
+    import paper_2103_05694_amd as eik
+    from paper_2103_05694_amd import autotune
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 2
+    if args.tile is not None:
+        args.tile = tuple(int(x) for x in args.tile.lower().split("x"))
+    cfg = autotune.lookup((256, 512, 512), "speed")
+    if args.delta is None:
+        args.delta = cfg["delta"] if cfg else 0.05
+    if args.tile is None:
+        args.tile = tuple(cfg["tile"]) if cfg else (32, 8, 4)
+
+    if args.profile_mode:
+        profile_mode(args, torch, eik, W)
+        return 0
+
+    log(f"single-source 3D solve, delta {args.delta}, tile {args.tile}")
+    single = bench_single(args, torch, eik, W)
+    log(f"single: {single['ms_per_step']:.3f} ms/step, kernel {single['kernel_ms']:.3f} ms")
+    extra = {"single": {k: v for k, v in single.items() if k != "roofline"}}
+    if not args.no_batched:
+        log("tomography batch")
+        extra["tomography_32"] = bench_tomography(args, torch, eik, W)
+        log(json.dumps(extra["tomography_32"]))
+    if not args.no_uneven:
+        log("uneven batch")
+        extra["uneven_64"] = bench_uneven(args, torch, eik, W)
+        log(json.dumps(extra["uneven_64"]))
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline()
+    value = single["npts"] / (single["ms_per_step"] * 1e-3)
+    line = {
+        "metric": METRIC, "value": value, "unit": "grid points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": single["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "3D 512x512x256 layered+noise speed (h=10 m, 1500-6000 m/s, 8 layers, "
+                               "seed 2), one surface-centre source, single forward solve",
+                   "delta": args.delta, "tile": list(args.tile), "points": single["npts"]},
+        "roofline": single["roofline"],
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -56,6 +56,8 @@ extern "C" {
 #define EIK_EBADSRC (-7)  /* a source index was out of range or a t0 invalid */
 #define EIK_EHANG (-8)    /* a device-side watchdog expired (internal error) */
 
+#define EIK_FLAG_TIME_KERNELS 1u  /* eik_opts.flags: time the persistent kernel with HIP events */
+
 #define EIK_SPEED 0       /* field holds speed v:    q = h / v */
 #define EIK_SLOWNESS 1    /* field holds slowness s: q = h * s */
 
@@ -72,7 +74,10 @@ typedef struct {
                                 3D 32x8x4, 16x8x8, 8x8x8, 64x4x4; 2D 32x32, 64x16, 128x8, 16x16 */
     int32_t grid_blocks;     /* persistent workgroups; 0 => fill the device */
     int64_t max_tile_visits; /* 0 => unlimited; else stop after this many tile visits (ELIMIT) */
-    uint32_t flags;          /* reserved, must be 0 */
+    uint32_t flags;          /* 0 or EIK_FLAG_TIME_KERNELS: record HIP events around the
+                                persistent kernel (solve or adjoint) on `stream`; eik_status
+                                then reports the mean duration of the kernels timed since the
+                                previous eik_status (at most 4096 launches in between) */
 } eik_opts;
 
 typedef struct {
@@ -82,6 +87,11 @@ typedef struct {
     int64_t relax_passes;    /* in-tile relaxation passes, summed over visits */
     uint32_t flags;          /* raw device flags (bit0 domain, bit1 limit, bit2 bad source, bit3 watchdog) */
     int32_t status;          /* the EIK_* code these flags map to */
+    double kernel_ms;        /* mean duration of the timed persistent kernels, or -1 */
+    int64_t kernel_launches; /* how many launches kernel_ms averages */
+    double phase_us[4];      /* forward solve, summed over workgroups (microseconds of wall
+                                clock): [0] claiming / waiting for work, [1] staging a tile
+                                and its halo in LDS, [2] relaxing, [3] write-back + publish */
 } eik_stats;
 
 /* Forward solve.

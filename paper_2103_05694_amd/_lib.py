@@ -23,6 +23,7 @@ EIK_EHANG = -8
 
 EIK_SPEED = 0
 EIK_SLOWNESS = 1
+EIK_FLAG_TIME_KERNELS = 1
 
 EXPORTED = (
     "eik_solve", "eik_parents", "eik_adjoint", "eik_solve_batched", "eik_adjoint_batched",
@@ -45,7 +46,9 @@ class eik_opts(ctypes.Structure):
 class eik_stats(ctypes.Structure):
     _fields_ = [("tile_visits", ctypes.c_int64), ("point_updates", ctypes.c_int64),
                 ("ntiles", ctypes.c_int64), ("relax_passes", ctypes.c_int64),
-                ("flags", ctypes.c_uint32), ("status", ctypes.c_int32)]
+                ("flags", ctypes.c_uint32), ("status", ctypes.c_int32),
+                ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_int64),
+                ("phase_us", ctypes.c_double * 4)]
 
 
 class EikError(RuntimeError):

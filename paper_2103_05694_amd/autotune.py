@@ -1,0 +1,125 @@
+"""Autotuner for the persistent solver's two free parameters: the tile shape
+and the priority bucket width delta.
+
+The paper leaves the priority scale open and notes that the best trade-off
+between priority inversions and contention depends on hardware and input
+(section "Deterministic Properties").  Neither parameter can change the
+result (Theorem 1), so the tuner times every candidate, checks that all
+candidates produce bit-identical times, and stores the fastest in a JSON cache
+keyed by (GPU arch, ndim, grid shape, field kind).  Candidate deltas are
+multiples of the median per-cell travel time h/v times the tile edge.
+
+    python -m paper_2103_05694_amd.autotune layered512 blocky4096
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+from typing import Dict, Iterable, List, Optional, Sequence, Tuple
+
+import torch
+
+from . import api
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "tuned.json")
+ARCH = "gfx950"
+
+TILES = {3: [(32, 8, 4), (16, 8, 8), (8, 8, 8), (64, 4, 4)],
+         2: [(64, 16), (32, 32), (128, 8), (16, 16)]}
+DELTA_FACTORS = (0.0, 0.5, 1.0, 2.0, 4.0, 8.0)
+
+
+def _key(shape: Sequence[int], kind: str) -> str:
+    return f"{ARCH}:{len(shape)}d:{'x'.join(str(int(s)) for s in shape)}:{kind}"
+
+
+def _load() -> Dict[str, dict]:
+    if os.path.exists(CACHE):
+        with open(CACHE) as f:
+            return json.load(f)
+    return {}
+
+
+def lookup(shape: Sequence[int], kind: str = "speed") -> Optional[dict]:
+    """Cached best configuration for this shape (exact), else None."""
+    return _load().get(_key(shape, kind))
+
+
+def _time(fn, reps: int) -> float:
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def tune(field: torch.Tensor, h: float, sources, kind: str = "speed",
+         tiles: Optional[Iterable[Tuple[int, ...]]] = None,
+         delta_factors: Sequence[float] = DELTA_FACTORS, reps: int = 5,
+         save: bool = True, log=print) -> dict:
+    """Time every (tile, delta) candidate on this problem; all must agree bitwise."""
+    nd = field.dim()
+    tiles = list(tiles) if tiles is not None else TILES[nd]
+    f64 = field.to(torch.float64)
+    q = (h / f64) if kind == "speed" else (h * f64)
+    qmed = float(q.flatten()[:: max(q.numel() // 100000, 1)].median())
+    ref = None
+    results: List[dict] = []
+    out = torch.empty_like(field)
+    for tile in tiles:
+        edge = min(tile[:nd])
+        for fac in delta_factors:
+            delta = fac * qmed * edge
+            fn = lambda: api.solve(field, h, sources, kind=kind, delta=delta, tile=tile, out=out,
+                                   check_status=False)
+            fn()
+            api.status()
+            t = out.clone()
+            if ref is None:
+                ref = t
+            elif not torch.equal(ref, t):
+                raise RuntimeError(f"candidate tile={tile} delta={delta} changed the result")
+            sec = _time(fn, reps)
+            api.status()
+            results.append({"tile": list(tile), "delta": delta, "delta_factor": fac, "ms": sec * 1e3})
+            log(f"  tile {tile} delta {delta:.4g} ({fac} x qmed x edge): {sec * 1e3:.3f} ms")
+    best = min(results, key=lambda r: r["ms"])
+    entry = {"tile": best["tile"], "delta": best["delta"], "ms": best["ms"], "qmed": qmed,
+             "candidates": results}
+    if save:
+        cache = _load()
+        cache[_key(field.shape, kind)] = entry
+        with open(CACHE, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+    return entry
+
+
+def _main(argv: List[str]) -> int:
+    root = os.path.dirname(HERE)
+    sys.path.insert(0, root)
+    import workloads as W
+    names = argv or ["layered512", "blocky4096"]
+    for name in names:
+        if name == "layered512":
+            p = W.layered_3d()
+        elif name == "layered256":
+            p = W.layered_3d(256, 256, 128)
+        elif name == "blocky4096":
+            p = W.blocky_2d()
+        else:
+            raise SystemExit(f"unknown workload {name}")
+        f = torch.from_numpy(p.field).cuda()
+        if p.ndim == 2:
+            f = f[0]
+        print(f"tuning {p.name}", flush=True)
+        e = tune(f, p.h, torch.as_tensor(p.src), log=lambda s: print(s, flush=True))
+        print(json.dumps({k: v for k, v in e.items() if k != "candidates"}), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(_main(sys.argv[1:]))

@@ -33,11 +33,11 @@ __device__ __forceinline__ double qnan64() { return as_f64(0x7FF8000000000000ull
 
 // Per tile: largest time (key source) and the problem-wide largest time.
 template <int TX, int TY, int TZ>
-__global__ void k_adj_prep(const Prob* probs, int nprob, int ntiles, const double* t,
-                           uint64_t* tile_tmax, unsigned long long* tref_bits) {
+__global__ void k_adj_prep(ProbTable T, int ntiles, const double* t, uint64_t* tile_tmax,
+                           unsigned long long* tref_bits) {
     __shared__ unsigned long long s_m;
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const Prob P = probs[nprob == 1 ? 0 : find_prob(probs, nprob, tile)];
+        const Prob P = prob_of_tile(T, tile);
         int tl = tile - P.tile_off;
         int tx = tl % P.ntx, ty = (tl / P.ntx) % P.nty, tz = tl / (P.ntx * P.nty);
         if (threadIdx.x == 0) s_m = 0ull;
@@ -77,8 +77,7 @@ __global__ void k_adj_push_all(int ntiles, const uint64_t* tile_tmax,
 }
 
 struct AdjArgs {
-    const Prob* probs;
-    int nprob;
+    ProbTable pt;
     const double* field;
     const double* t;
     const uint8_t* par;
@@ -101,6 +100,7 @@ __global__ void __launch_bounds__(NT) k_adjoint(AdjArgs A) {
     __shared__ int s_tile;
     __shared__ uint32_t s_state;
     __shared__ uint32_t s_nb[6];
+    __shared__ uint32_t s_nid[6];
     __shared__ unsigned long long s_face[6];
     __shared__ unsigned int s_done;
 
@@ -110,6 +110,7 @@ __global__ void __launch_bounds__(NT) k_adjoint(AdjArgs A) {
     constexpr int PSTEP[3] = {1, TX, TX * TY};
     constexpr int LSTEP[3] = {1, C::SY, C::SZ};
     constexpr int NAX = C::D3 ? 3 : 2;
+    unsigned long long my_visits = 0, my_done = 0;
 
     for (;;) {
         if (tid < 64) {
@@ -117,8 +118,8 @@ __global__ void __launch_bounds__(NT) k_adjoint(AdjArgs A) {
             if (tid == 0) {
                 s_tile = tile;
                 if (tile >= 0) {
-                    __hip_atomic_fetch_add(S.counters, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    uint32_t st = __hip_atomic_fetch_xor(S.tstate + tile, kQ | kR, __ATOMIC_ACQUIRE,
+                    ++my_visits;
+                    uint32_t st = __hip_atomic_fetch_xor(S.tstate + tile, kQ | kR, __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_AGENT);
                     if ((st & (kQ | kR)) != kQ) set_flag(S, kFlagWatchdog);
                     s_state = st;
@@ -130,7 +131,7 @@ __global__ void __launch_bounds__(NT) k_adjoint(AdjArgs A) {
         if (tile < 0) break;
         const uint32_t st = s_state;
         const bool visited = (st & kV) != 0;
-        const Prob P = A.probs[A.nprob == 1 ? 0 : find_prob(A.probs, A.nprob, tile)];
+        const Prob P = prob_of_tile(A.pt, tile);
         const int tl = tile - P.tile_off;
         const int tx = tl % P.ntx, ty = (tl / P.ntx) % P.nty, tz = tl / (P.ntx * P.nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
@@ -140,12 +141,13 @@ __global__ void __launch_bounds__(NT) k_adjoint(AdjArgs A) {
             int nt[3] = {tx, ty, tz};
             int lim[3] = {P.ntx, P.nty, P.ntz};
             nt[d] += side ? 1 : -1;
-            uint32_t w = 0;
+            uint32_t w = 0, nid = 0;
             if (nt[d] >= 0 && nt[d] < lim[d]) {
-                int nid = P.tile_off + (nt[2] * P.nty + nt[1]) * P.ntx + nt[0];
+                nid = (uint32_t)(P.tile_off + (nt[2] * P.nty + nt[1]) * P.ntx + nt[0]);
                 w = ld_rlx(S.tstate + nid) | 0x40000000u;
             }
             s_nb[tid] = w;
+            s_nid[tid] = nid;
             s_face[tid] = kInfBits;
         }
         if (tid == 0) s_done = 0u;
@@ -174,7 +176,9 @@ __global__ void __launch_bounds__(NT) k_adjoint(AdjArgs A) {
                 }
                 gv = A.g[gi];
                 if (pv & 0x80) mv = 0.0;
-                else mv = visited ? A.mu[gi] : qnan64();
+                else mv = visited ? as_f64(__hip_atomic_load((const uint64_t*)(A.mu + gi), __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT))
+                                  : qnan64();
             }
             sT[L] = tv;
             sP[L] = pv;
@@ -333,37 +337,16 @@ __global__ void __launch_bounds__(NT) k_adjoint(AdjArgs A) {
         for (int f = 0; f < 6; ++f)
             if (fkey[f] < inf64()) atomicMin(&s_face[f], (unsigned long long)as_u64(fmax(fkey[f], 0.0)));
         if (ndone) atomicAdd(&s_done, ndone);
+        stores_done();
         __syncthreads();
 
-        if (tid == 0) {
-            if (!visited)
-                __hip_atomic_fetch_or(S.tstate + tile, kV, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            for (int f = 0; f < 6; ++f) {
-                const uint32_t nb = s_nb[f];
-                const unsigned long long fk = s_face[f];
-                if ((nb & 0x40000000u) && fk != kInfBits) {
-                    int d = f >> 1, side = f & 1;
-                    int nt[3] = {tx, ty, tz};
-                    nt[d] += side ? 1 : -1;
-                    uint32_t nid = (uint32_t)(P.tile_off + (nt[2] * P.nty + nt[1]) * P.ntx + nt[0]);
-                    uint32_t old = __hip_atomic_fetch_or(S.tstate + nid, kQ, __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-                    if ((old & (kQ | kR)) == 0) {
-                        activate_push(S, nid, as_f64(fk));
-                    } else if (old & kR) {
-                        __hip_atomic_fetch_min((unsigned long long*)(A.tkey + nid), fk, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                }
-            }
-            __hip_atomic_fetch_add(S.counters + 1, (unsigned long long)s_done, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            uint64_t kb = __hip_atomic_exchange((unsigned long long*)(A.tkey + tile), kInfBits,
-                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            finish_run(S, (uint32_t)tile, kb == kInfBits ? 0.0 : as_f64(kb));
-        }
+        if (tid < 64) publish(S, A.tkey, (uint32_t)tile, !visited, s_nb, s_nid, s_face);
+        if (tid == 0) my_done += s_done;
         __syncthreads();
+    }
+    if (tid == 0) {
+        __hip_atomic_fetch_add(S.counters + 0, my_visits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(S.counters + 1, my_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

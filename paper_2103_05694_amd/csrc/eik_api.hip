@@ -60,9 +60,32 @@ struct Workspace {
     double* mu = nullptr;
     int64_t mu_cap = 0;
     uint64_t* tile_tmax = nullptr;     // per-tile largest time (adjoint priorities)
-    bool poisoned_host = true;         // rings need their first initialisation
     int last_kind = 0;                 // 0 none, 1 forward, 2 adjoint
+    int64_t last_ntiles = 0;
+    std::vector<hipEvent_t> ev;        // event pairs bracketing timed persistent kernels
+    size_t ev_used = 0;                // pairs recorded since the last eik_status
 };
+
+int timing_begin(Workspace& w, const eik_opts* o) {
+    if (!o || !(o->flags & EIK_FLAG_TIME_KERNELS)) return EIK_OK;
+    if (w.ev_used * 2 + 2 > w.ev.size()) {
+        if (w.ev_used >= 4096) return fail(EIK_EINVAL, "more than 4096 timed launches without eik_status");
+        for (int i = 0; i < 2; ++i) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            w.ev.push_back(e);
+        }
+    }
+    HIP_TRY(hipEventRecord(w.ev[2 * w.ev_used], w.stream));
+    return EIK_OK;
+}
+
+int timing_end(Workspace& w, const eik_opts* o) {
+    if (!o || !(o->flags & EIK_FLAG_TIME_KERNELS)) return EIK_OK;
+    HIP_TRY(hipEventRecord(w.ev[2 * w.ev_used + 1], w.stream));
+    ++w.ev_used;
+    return EIK_OK;
+}
 
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
@@ -100,7 +123,7 @@ int get_ws(hipStream_t st, Workspace** out) {
     w->device = dev;
     w->stream = st;
     hipError_t e = hipMalloc((void**)&w->scal, 64 * sizeof(int32_t));
-    if (e == hipSuccess) e = hipMalloc((void**)&w->counters, 8 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc((void**)&w->counters, 16 * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMalloc((void**)&w->ctr, sizeof(uint32_t) * kRings * kCtrStride);
     if (e != hipSuccess) {
         delete w;
@@ -110,7 +133,7 @@ int get_ws(hipStream_t st, Workspace** out) {
     init[3] = 1;  // poisoned: the first reset initialises the rings
     HIP_TRY(hipMemcpy(w->scal, init, sizeof(init), hipMemcpyHostToDevice));
     HIP_TRY(hipMemset(w->ctr, 0, sizeof(uint32_t) * kRings * kCtrStride));
-    HIP_TRY(hipMemset(w->counters, 0, 8 * sizeof(unsigned long long)));
+    HIP_TRY(hipMemset(w->counters, 0, 16 * sizeof(unsigned long long)));
     g_ws[key] = w;
     *out = w;
     return EIK_OK;
@@ -126,7 +149,7 @@ int ensure_tiles(Workspace& w, int64_t ntiles) {
     if (ntiles > (int64_t)1 << 30) return fail(EIK_ENOTSUP, "more than 2^30 tiles");
     int rc;
     if ((rc = grow(&w.tstate, &w.tiles_cap, ntiles, w.stream))) return rc;
-    const uint32_t need_ring = next_pow2((uint64_t)w.tiles_cap);
+    const uint32_t need_ring = next_pow2((uint64_t)std::max<int64_t>(w.tiles_cap, 2));
     if (need_ring > w.ring_cap) {
         HIP_TRY(hipStreamSynchronize(w.stream));
         if (w.items) HIP_TRY(hipFree(w.items));
@@ -148,11 +171,16 @@ int ensure_tiles(Workspace& w, int64_t ntiles) {
     return EIK_OK;
 }
 
-int upload_table(Workspace& w, const std::vector<Prob>& probs, const std::vector<int64_t>& src_off) {
+// Makes the device problem table (and, when `src_off` is given, the source
+// offsets) match; a no-op when they already do, so repeated calls with the same
+// problems enqueue nothing but kernels (HIP graph capture relies on this).
+int upload_table(Workspace& w, const std::vector<Prob>& probs, const std::vector<int64_t>* src_off) {
     int64_t n = (int64_t)probs.size();
-    bool same = (int64_t)w.probs_host.size() == n && w.src_off_host == src_off &&
-                std::memcmp(w.probs_host.data(), probs.data(), sizeof(Prob) * (size_t)n) == 0;
+    bool same = (int64_t)w.probs_host.size() == n &&
+                std::memcmp(w.probs_host.data(), probs.data(), sizeof(Prob) * (size_t)n) == 0 &&
+                (src_off == nullptr || w.src_off_host == *src_off);
     if (same && w.probs) return EIK_OK;
+    std::vector<int64_t> so = src_off ? *src_off : std::vector<int64_t>(probs.size() + 1, 0);
     if (w.probs_cap < n + 1) {
         if (w.probs) {
             HIP_TRY(hipStreamSynchronize(w.stream));
@@ -170,9 +198,26 @@ int upload_table(Workspace& w, const std::vector<Prob>& probs, const std::vector
     // synchronous copies: the host vectors may be gone before the stream runs
     HIP_TRY(hipStreamSynchronize(w.stream));
     HIP_TRY(hipMemcpy(w.probs, probs.data(), sizeof(Prob) * (size_t)n, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(w.src_off, src_off.data(), sizeof(int64_t) * src_off.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(w.src_off, so.data(), sizeof(int64_t) * so.size(), hipMemcpyHostToDevice));
     w.probs_host = probs;
-    w.src_off_host = src_off;
+    w.src_off_host = so;
+    return EIK_OK;
+}
+
+// Kernel-side problem table: a single problem travels by value (nothing to
+// upload, no synchronisation); a batch uses the device copy.
+int make_table(Workspace& w, const std::vector<Prob>& probs, const std::vector<int64_t>* src_off,
+               ProbTable* T) {
+    T->probs = nullptr;
+    T->src_off = nullptr;
+    T->nprob = (int)probs.size();
+    T->p0 = probs[0];
+    T->nsrc0 = src_off ? (*src_off)[1] - (*src_off)[0] : 0;
+    if (probs.size() == 1) return EIK_OK;
+    int rc = upload_table(w, probs, src_off);
+    if (rc) return rc;
+    T->probs = w.probs;
+    T->src_off = w.src_off;
     return EIK_OK;
 }
 
@@ -219,7 +264,7 @@ int check_opts(const eik_opts* o) {
     if (!(o->delta >= 0.0) || std::isnan(o->delta)) return fail(EIK_EINVAL, "delta must be >= 0");
     if (o->grid_blocks < 0) return fail(EIK_EINVAL, "grid_blocks must be >= 0");
     if (o->max_tile_visits < 0) return fail(EIK_EINVAL, "max_tile_visits must be >= 0");
-    if (o->flags != 0) return fail(EIK_EINVAL, "flags must be 0");
+    if (o->flags & ~EIK_FLAG_TIME_KERNELS) return fail(EIK_EINVAL, "unknown flags");
     return EIK_OK;
 }
 
@@ -295,7 +340,8 @@ int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int6
     const int64_t nsrc = src_off.back();
     if ((rc = ensure_tiles(w, ntiles))) return rc;
     if ((rc = grow(&w.srclist, &w.srclist_cap, nsrc, w.stream))) return rc;
-    if ((rc = upload_table(w, probs, src_off))) return rc;
+    ProbTable T;
+    if ((rc = make_table(w, probs, &src_off, &T))) return rc;
     hipStream_t st = w.stream;
     const int nprob = (int)probs.size();
     Sched s = make_sched(w, o);
@@ -305,16 +351,15 @@ int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int6
                        dim3(kThreads), 0, st, s, w.tkey, (int)ntiles, srccnt,
                        (long long)kRings * w.ring_cap);
     hipLaunchKernelGGL((k_src_mark<TX, TY, TZ>), dim3(blocks_for(nsrc, kThreads)), dim3(kThreads), 0, st,
-                       w.probs, nprob, w.src_off, src_idx, src_t0, (long long)nsrc, s, w.srclist, srccnt);
+                       T, src_idx, src_t0, (long long)nsrc, s, w.srclist, srccnt);
     hipLaunchKernelGGL((k_src_fill<TX, TY, TZ>), dim3((unsigned)std::min<int64_t>(nsrc, 4096)),
-                       dim3(kThreads), 0, st, w.probs, nprob, t, w.srclist, srccnt);
+                       dim3(kThreads), 0, st, T, t, w.srclist, srccnt);
     hipLaunchKernelGGL((k_src_place<TX, TY, TZ>), dim3(blocks_for(nsrc, kThreads)), dim3(kThreads), 0, st,
-                       w.probs, nprob, w.src_off, src_idx, src_t0, (long long)nsrc, t, s);
+                       T, src_idx, src_t0, (long long)nsrc, t, s);
     HIP_TRY(hipGetLastError());
 
     SolveArgs a;
-    a.probs = w.probs;
-    a.nprob = nprob;
+    a.pt = T;
     a.field = field;
     a.t = t;
     a.tkey = w.tkey;
@@ -324,19 +369,22 @@ int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int6
     if (o && o->grid_blocks > 0) grid = std::min(grid, o->grid_blocks);
     if ((int64_t)grid > ntiles) grid = (int)ntiles;
     if (grid < 1) grid = 1;
+    if ((rc = timing_begin(w, o))) return rc;
     hipLaunchKernelGGL((k_solve<TX, TY, TZ, kThreads>), dim3(grid), dim3(kThreads), 0, st, a);
     HIP_TRY(hipGetLastError());
+    if ((rc = timing_end(w, o))) return rc;
 
     if (par)
         hipLaunchKernelGGL(k_parents, dim3(blocks_for(npts_total, kThreads, 1 << 16)), dim3(kThreads), 0,
-                           st, w.probs, nprob, (long long)npts_total, (const double*)t, par);
-    hipLaunchKernelGGL(k_src_unsign, dim3(blocks_for(nsrc, kThreads)), dim3(kThreads), 0, st, w.probs,
-                       nprob, w.src_off, src_idx, src_t0, (long long)nsrc, t);
+                           st, T, (long long)npts_total, (const double*)t, par);
+    hipLaunchKernelGGL(k_src_unsign, dim3(blocks_for(nsrc, kThreads)), dim3(kThreads), 0, st, T, src_idx,
+                       src_t0, (long long)nsrc, t);
     if (o && o->max_tile_visits > 0)
         hipLaunchKernelGGL((k_fill_unvisited<TX, TY, TZ>), dim3((unsigned)std::min<int64_t>(ntiles, 16384)),
-                           dim3(kThreads), 0, st, w.probs, nprob, (int)ntiles, t, (const uint32_t*)w.tstate);
+                           dim3(kThreads), 0, st, T, (int)ntiles, t, (const uint32_t*)w.tstate);
     HIP_TRY(hipGetLastError());
     w.last_kind = 1;
+    w.last_ntiles = ntiles;
     return EIK_OK;
 }
 
@@ -363,8 +411,8 @@ int adjoint(Workspace& w, const std::vector<Prob>& probs, int64_t ntiles, int64_
         if ((rc = grow(&w.mu, &w.mu_cap, npts, w.stream))) return rc;
         mu = w.mu;
     }
-    std::vector<int64_t> soff(probs.size() + 1, 0);
-    if ((rc = upload_table(w, probs, soff))) return rc;
+    ProbTable T;
+    if ((rc = make_table(w, probs, nullptr, &T))) return rc;
     hipStream_t st = w.stream;
     const int nprob = (int)probs.size();
     Sched s = make_sched(w, o);
@@ -374,13 +422,12 @@ int adjoint(Workspace& w, const std::vector<Prob>& probs, int64_t ntiles, int64_
                        dim3(kThreads), 0, st, s, w.tkey, (int)ntiles, w.scal + 4,
                        (long long)kRings * w.ring_cap);
     hipLaunchKernelGGL((k_adj_prep<TX, TY, TZ>), dim3((unsigned)std::min<int64_t>(ntiles, 65536)), dim3(kThreads),
-                       0, st, w.probs, nprob, (int)ntiles, t, w.tile_tmax, tref);
+                       0, st, T, (int)ntiles, t, w.tile_tmax, tref);
     hipLaunchKernelGGL(k_adj_push_all, dim3(blocks_for(ntiles, kThreads, 4096)), dim3(kThreads), 0, st,
                        (int)ntiles, (const uint64_t*)w.tile_tmax, (const unsigned long long*)tref, s);
     HIP_TRY(hipGetLastError());
     AdjArgs a;
-    a.probs = w.probs;
-    a.nprob = nprob;
+    a.pt = T;
     a.field = field;
     a.t = t;
     a.par = par;
@@ -395,9 +442,12 @@ int adjoint(Workspace& w, const std::vector<Prob>& probs, int64_t ntiles, int64_
     if (o && o->grid_blocks > 0) grid = std::min(grid, o->grid_blocks);
     if ((int64_t)grid > ntiles) grid = (int)ntiles;
     if (grid < 1) grid = 1;
+    if ((rc = timing_begin(w, o))) return rc;
     hipLaunchKernelGGL((k_adjoint<TX, TY, TZ, kThreads>), dim3(grid), dim3(kThreads), 0, st, a);
     HIP_TRY(hipGetLastError());
+    if ((rc = timing_end(w, o))) return rc;
     w.last_kind = 2;
+    w.last_ntiles = ntiles;
     return EIK_OK;
 }
 
@@ -514,14 +564,15 @@ int eik_parents(const eik_grid* g, const double* t, int64_t nsrc, const int64_t*
     TileShape ts = pick_tile(g->ndim, nullptr);
     std::vector<Prob> probs{make_prob(*g, ts, 0, 0)};
     std::vector<int64_t> soff{0, nsrc};
-    if ((rc = upload_table(*w, probs, soff))) return rc;
+    ProbTable T;
+    if ((rc = make_table(*w, probs, &soff, &T))) return rc;
     int64_t n = (int64_t)g->nx * g->ny * g->nz;
     hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_parents, dim3(blocks_for(n, kThreads, 1 << 16)), dim3(kThreads), 0, st, w->probs, 1,
+    hipLaunchKernelGGL(k_parents, dim3(blocks_for(n, kThreads, 1 << 16)), dim3(kThreads), 0, st, T,
                        (long long)n, t, parents_out);
     if (nsrc > 0)
         hipLaunchKernelGGL(k_parents_mark_src, dim3(blocks_for(nsrc, kThreads)), dim3(kThreads), 0, st,
-                           w->probs, 1, w->src_off, src_idx, (long long)nsrc, parents_out);
+                           T, src_idx, (long long)nsrc, parents_out);
     HIP_TRY(hipGetLastError());
     return EIK_OK;
 }
@@ -573,7 +624,7 @@ int eik_status(void* stream, eik_stats* out) {
     if ((rc = get_ws((hipStream_t)stream, &w))) return rc;
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
     int32_t sc[8];
-    unsigned long long ctr[8];
+    unsigned long long ctr[16];
     HIP_TRY(hipMemcpy(sc, w->scal, sizeof(sc), hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(ctr, w->counters, sizeof(ctr), hipMemcpyDeviceToHost));
     uint32_t flags = (uint32_t)sc[2];
@@ -586,10 +637,23 @@ int eik_status(void* stream, eik_stats* out) {
         out->tile_visits = (int64_t)ctr[0];
         out->point_updates = (int64_t)ctr[1];
         out->relax_passes = (int64_t)ctr[2];
-        out->ntiles = 0;
+        out->ntiles = w->last_ntiles;
         out->flags = flags;
         out->status = code;
+        out->kernel_ms = -1.0;
+        out->kernel_launches = (int64_t)w->ev_used;
+        for (int i = 0; i < 4; ++i) out->phase_us[i] = (double)ctr[5 + i] / 100.0;  // 100 MHz clock
+        if (w->ev_used) {
+            double sum = 0.0;
+            for (size_t i = 0; i < w->ev_used; ++i) {
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, w->ev[2 * i], w->ev[2 * i + 1]));
+                sum += ms;
+            }
+            out->kernel_ms = sum / (double)w->ev_used;
+        }
     }
+    w->ev_used = 0;
     if (code != EIK_OK) g_last_error = eik_strerror(code);
     return code;
 }
@@ -612,6 +676,7 @@ void eik_release(void) {
         (void)hipFree(w->src_off);
         (void)hipFree(w->mu);
         (void)hipFree(w->tile_tmax);
+        for (hipEvent_t e : w->ev) (void)hipEventDestroy(e);
         if (cur != w->device) (void)hipSetDevice(cur);
         delete w;
     }

@@ -31,22 +31,52 @@ struct Prob {
     double h;
 };
 
-struct SolveArgs {
-    const Prob* probs;
+// Problem table of a launch.  A single problem travels by value in the kernel
+// arguments (no upload, no host synchronisation); batches read the device table.
+struct ProbTable {
+    const Prob* probs;       // device table, used when nprob > 1
+    const int64_t* src_off;  // device source offsets, used when nprob > 1
     int nprob;
+    Prob p0;                 // the problem when nprob == 1
+    int64_t nsrc0;           // its source count
+};
+
+struct SolveArgs {
+    ProbTable pt;
     const double* field;
     double* t;
     uint64_t* tkey;          // [ntiles] pending requeue key (bits of a positive double)
     Sched s;
 };
 
-__device__ __forceinline__ int find_prob(const Prob* probs, int nprob, int tile) {
-    int lo = 0, hi = nprob - 1;
+__device__ __forceinline__ Prob prob_of_tile(const ProbTable& T, int tile) {
+    if (T.nprob == 1) return T.p0;
+    int lo = 0, hi = T.nprob - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        if (probs[mid].tile_off <= tile) lo = mid; else hi = mid - 1;
+        if (T.probs[mid].tile_off <= tile) lo = mid; else hi = mid - 1;
     }
-    return lo;
+    return T.probs[lo];
+}
+
+__device__ __forceinline__ Prob prob_of_point(const ProbTable& T, long long g) {
+    if (T.nprob == 1) return T.p0;
+    int lo = 0, hi = T.nprob - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (T.probs[mid].pt_off <= g) lo = mid; else hi = mid - 1;
+    }
+    return T.probs[lo];
+}
+
+__device__ __forceinline__ Prob prob_of_source(const ProbTable& T, long long g) {
+    if (T.nprob == 1) return T.p0;
+    int lo = 0, hi = T.nprob - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (T.src_off[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    return T.probs[lo];
 }
 
 __device__ __forceinline__ double field_q(double f, double h, int kind, bool& ok) {
@@ -73,25 +103,18 @@ __global__ void k_reset(Sched s, uint64_t* tkey, int ntiles, int32_t* srclist_co
         tkey[i] = kInfBits;
     }
     if (wipe) {
-        for (long long i = i0; i < ring_words; i += stride) s.items[i] = ~0ull;
+        // cell i of every ring starts free for position i (lap 0)
+        const long long cap = (long long)s.cap_mask + 1;
+        for (long long i = i0; i < ring_words; i += stride) s.items[i] = (uint64_t)(i % cap) << 32;
         for (long long i = i0; i < (long long)s.nrings * kCtrStride; i += stride) s.ctr[i] = 0u;
     }
     if (i0 == 0) {
         *s.cur = 0;
         *s.pending = 0;
         *s.flags = 0u;
-        s.counters[0] = s.counters[1] = s.counters[2] = s.counters[4] = 0ull;
+        for (int i = 0; i < 16; ++i) s.counters[i] = 0ull;
         *srclist_count = 0;
     }
-}
-
-__device__ __forceinline__ int find_src_prob(const int64_t* src_off, int nprob, long long g) {
-    int lo = 0, hi = nprob - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (src_off[mid] <= g) lo = mid; else hi = mid - 1;
-    }
-    return lo;
 }
 
 template <int TX, int TY, int TZ>
@@ -107,14 +130,12 @@ __device__ __forceinline__ bool src_ok(const Prob& P, int64_t idx, double t0) {
 
 // Marks source tiles (S) and lists each one once.
 template <int TX, int TY, int TZ>
-__global__ void k_src_mark(const Prob* probs, int nprob, const int64_t* src_off,
-                           const int64_t* src_idx, const double* src_t0, long long nsrc, Sched s,
-                           int32_t* srclist, int32_t* srclist_count) {
+__global__ void k_src_mark(ProbTable T, const int64_t* src_idx, const double* src_t0, long long nsrc,
+                           Sched s, int32_t* srclist, int32_t* srclist_count) {
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g == 0) *s.poisoned = 0;  // the reset before this kernel has wiped the rings
     if (g >= nsrc) return;
-    int p = find_src_prob(src_off, nprob, g);
-    const Prob P = probs[p];
+    const Prob P = prob_of_source(T, g);
     int64_t idx = src_idx[g];
     double t0 = src_t0 ? src_t0[g] : 0.0;
     if (!src_ok(P, idx, t0)) {
@@ -131,12 +152,11 @@ __global__ void k_src_mark(const Prob* probs, int nprob, const int64_t* src_off,
 
 // Fills every listed source tile with +inf (blocks stride over the list).
 template <int TX, int TY, int TZ>
-__global__ void k_src_fill(const Prob* probs, int nprob, double* t, const int32_t* srclist,
-                           const int32_t* srclist_count) {
+__global__ void k_src_fill(ProbTable T, double* t, const int32_t* srclist, const int32_t* srclist_count) {
     const int count = *srclist_count;
     for (int b = blockIdx.x; b < count; b += gridDim.x) {
         const int tile = srclist[b];
-        const Prob P = probs[find_prob(probs, nprob, tile)];
+        const Prob P = prob_of_tile(T, tile);
         const int tl = tile - P.tile_off;
         const int tx = tl % P.ntx, ty = (tl / P.ntx) % P.nty, tz = tl / (P.ntx * P.nty);
         for (int i = threadIdx.x; i < TX * TY * TZ; i += blockDim.x) {
@@ -152,13 +172,11 @@ __global__ void k_src_fill(const Prob* probs, int nprob, double* t, const int32_
 // min over duplicates through the signed image, where -0.0 is the smallest) and
 // queues its tile.
 template <int TX, int TY, int TZ>
-__global__ void k_src_place(const Prob* probs, int nprob, const int64_t* src_off,
-                            const int64_t* src_idx, const double* src_t0, long long nsrc,
+__global__ void k_src_place(ProbTable T, const int64_t* src_idx, const double* src_t0, long long nsrc,
                             double* t, Sched s) {
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= nsrc) return;
-    int p = find_src_prob(src_off, nprob, g);
-    const Prob P = probs[p];
+    const Prob P = prob_of_source(T, g);
     int64_t idx = src_idx[g];
     double t0 = src_t0 ? src_t0[g] : 0.0;
     if (!src_ok(P, idx, t0)) return;
@@ -171,12 +189,11 @@ __global__ void k_src_place(const Prob* probs, int nprob, const int64_t* src_off
 }
 
 // Restores +t0 at the sources.
-__global__ void k_src_unsign(const Prob* probs, int nprob, const int64_t* src_off,
-                             const int64_t* src_idx, const double* src_t0, long long nsrc, double* t) {
+__global__ void k_src_unsign(ProbTable T, const int64_t* src_idx, const double* src_t0, long long nsrc,
+                             double* t) {
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= nsrc) return;
-    int p = find_src_prob(src_off, nprob, g);
-    const Prob P = probs[p];
+    const Prob P = prob_of_source(T, g);
     int64_t idx = src_idx[g];
     double t0 = src_t0 ? src_t0[g] : 0.0;
     if (!src_ok(P, idx, t0)) return;
@@ -187,11 +204,10 @@ __global__ void k_src_unsign(const Prob* probs, int nprob, const int64_t* src_of
 // After a capped (ELIMIT) solve: tiles never visited still hold stale memory;
 // give them +inf so the output is a valid upper bound.
 template <int TX, int TY, int TZ>
-__global__ void k_fill_unvisited(const Prob* probs, int nprob, int ntiles, double* t,
-                                 const uint32_t* tstate) {
+__global__ void k_fill_unvisited(ProbTable T, int ntiles, double* t, const uint32_t* tstate) {
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         if (tstate[tile] & kV) continue;
-        const Prob P = probs[find_prob(probs, nprob, tile)];
+        const Prob P = prob_of_tile(T, tile);
         int tl = tile - P.tile_off;
         int tx = tl % P.ntx, ty = (tl / P.ntx) % P.nty, tz = tl / (P.ntx * P.nty);
         for (int i = threadIdx.x; i < TX * TY * TZ; i += blockDim.x) {
@@ -241,14 +257,22 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
     __shared__ double sT[C::NLDS];
     __shared__ double sQ[C::NP];
     __shared__ uint8_t sDirty[2][C::NP];
+    __shared__ uint16_t sList[C::NP];
+    __shared__ int s_cnt[2];
     __shared__ int s_tile;
     __shared__ uint32_t s_state;
     __shared__ uint32_t s_nb[6];
+    __shared__ uint32_t s_nid[6];
     __shared__ unsigned long long s_face[6];
     __shared__ unsigned int s_upd;
 
     const int tid = threadIdx.x;
     const Sched& S = A.s;
+    // per-workgroup statistics, flushed once at exit; the phase times use the
+    // 100 MHz wall clock: [0] claim, [1] stage, [2] relax, [3] write + publish
+    unsigned long long my_visits = 0, my_updates = 0, my_passes = 0;
+    unsigned long long ph[4] = {0, 0, 0, 0};
+    unsigned long long tm = wall_clock64();
 
     for (;;) {
         // ---- claim ------------------------------------------------------
@@ -257,15 +281,17 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
             if (tid == 0) {
                 s_tile = tile;
                 if (tile >= 0) {
-                    unsigned long long v = __hip_atomic_fetch_add(S.counters, 1ull, __ATOMIC_RELAXED,
-                                                                  __HIP_MEMORY_SCOPE_AGENT);
-                    // Q -> R, acquiring everything released before the activations.
-                    uint32_t st = __hip_atomic_fetch_xor(S.tstate + tile, kQ | kR, __ATOMIC_ACQUIRE,
+                    // Q -> R; every load of this run is issued after it returned
+                    uint32_t st = __hip_atomic_fetch_xor(S.tstate + tile, kQ | kR, __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_AGENT);
                     if ((st & (kQ | kR)) != kQ) set_flag(S, kFlagWatchdog);
-                    if (S.max_visits > 0 && (long long)v >= S.max_visits) {
-                        set_flag(S, kFlagLimit);
-                        st |= 0x80000000u;  // skip marker
+                    if (S.max_visits > 0) {
+                        unsigned long long v = __hip_atomic_fetch_add(S.counters + 3, 1ull, __ATOMIC_RELAXED,
+                                                                      __HIP_MEMORY_SCOPE_AGENT);
+                        if ((long long)v >= S.max_visits) {
+                            set_flag(S, kFlagLimit);
+                            st |= 0x80000000u;  // skip marker
+                        }
                     }
                     s_state = st;
                 }
@@ -275,13 +301,19 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
         const int tile = s_tile;
         if (tile < 0) break;
         const uint32_t st = s_state;
-        const Prob P = A.probs[A.nprob == 1 ? 0 : find_prob(A.probs, A.nprob, tile)];
+        const Prob P = prob_of_tile(A.pt, tile);
         const int tl = tile - P.tile_off;
         const int tx = tl % P.ntx, ty = (tl / P.ntx) % P.nty, tz = tl / (P.ntx * P.nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+        if (tid == 0) {
+            ++my_visits;
+            const unsigned long long now = wall_clock64();
+            ph[0] += now - tm;
+            tm = now;
+        }
 
         if (st & 0x80000000u) {  // visit cap reached: drop the tile
-            if (tid == 0) finish_run(S, (uint32_t)tile, 0.0);
+            if (tid == 0) drop_run(S, (uint32_t)tile);
             __syncthreads();
             continue;
         }
@@ -294,15 +326,20 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
             int nt[3] = {tx, ty, tz};
             int lim[3] = {P.ntx, P.nty, P.ntz};
             nt[d] += side ? 1 : -1;
-            uint32_t w = 0;
+            uint32_t w = 0, nid = 0;
             if (nt[d] >= 0 && nt[d] < lim[d]) {
-                int nid = P.tile_off + (nt[2] * P.nty + nt[1]) * P.ntx + nt[0];
+                nid = (uint32_t)(P.tile_off + (nt[2] * P.nty + nt[1]) * P.ntx + nt[0]);
                 w = ld_rlx(S.tstate + nid) | 0x40000000u;  // bit 30: tile exists
             }
             s_nb[tid] = w;
+            s_nid[tid] = nid;
             s_face[tid] = kInfBits;
         }
-        if (tid == 0) s_upd = 0u;
+        if (tid == 0) {
+            s_upd = 0u;
+            s_cnt[0] = 0;
+            s_cnt[1] = 0;
+        }
 
         // ---- stage the tile in LDS ---------------------------------------
         double t_in[NPT];
@@ -321,7 +358,8 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
                     q = 0.0;
                 }
                 if (visited) {
-                    tv = A.t[gi];
+                    tv = as_f64(__hip_atomic_load((const uint64_t*)(A.t + gi), __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT));
                     if (signbit(tv)) {  // a source: fixed
                         tv = fabs(tv);
                         q = 0.0;
@@ -360,45 +398,73 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
             }
         }
         __syncthreads();
+        if (tid == 0) {
+            const unsigned long long now = wall_clock64();
+            ph[1] += now - tm;
+            tm = now;
+        }
 
         // ---- relax until the tile is quiet --------------------------------
+        // Each pass first compacts the dirty points into a dense list (wave
+        // ballot + prefix count, one LDS atomic per wave), then applies the
+        // operator to the list, so the waves run the operator only as many
+        // times as there are dirty points, not once per owned point.  A point
+        // whose value drops marks its in-tile neighbours dirty for the next
+        // pass; values read within a pass may already be newer (any order of
+        // monotone updates is valid).
+        const int lane = tid & 63;
         int cb = 0;
         int passes = 0;
         for (;;) {
-            bool any = false;
 #pragma unroll
             for (int j = 0; j < NPT; ++j) {
                 const int p = tid + j * NT;
-                if (sDirty[cb][p]) {
+                bool d = sDirty[cb][p] != 0;
+                if (d) {
                     sDirty[cb][p] = 0;
-                    const double q = sQ[p];
-                    if (q > 0.0) {
-                        const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
-                        const int L = C::lds(lx, ly, lz);
-                        const double tc = sT[L];
-                        const double ax = fmin(sT[L - 1], sT[L + 1]);
-                        const double ay = fmin(sT[L - C::SY], sT[L + C::SY]);
-                        const double az = C::D3 ? fmin(sT[L - C::SZ], sT[L + C::SZ]) : inf64();
-                        bool ch;
-                        const double r = update(ax, ay, az, q, q * q, tc, ch);
-                        if (ch) {
-                            sT[L] = r;
-                            any = true;
-                            uint8_t* nd = sDirty[cb ^ 1];
-                            if (lx > 0) nd[p - 1] = 1;
-                            if (lx < TX - 1) nd[p + 1] = 1;
-                            if (ly > 0) nd[p - TX] = 1;
-                            if (ly < TY - 1) nd[p + TX] = 1;
-                            if (C::D3) {
-                                if (lz > 0) nd[p - TX * TY] = 1;
-                                if (lz < TZ - 1) nd[p + TX * TY] = 1;
-                            }
-                        }
+                    d = sQ[p] > 0.0;
+                }
+                const unsigned long long m = __ballot(d);
+                if (m) {
+                    const int leader = __ffsll((long long)m) - 1;
+                    int base = 0;
+                    if (lane == leader) base = atomicAdd(&s_cnt[cb], (int)__popcll(m));
+                    base = __shfl(base, leader);
+                    if (d) sList[base + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)p;
+                }
+            }
+            __syncthreads();
+            const int n = s_cnt[cb];
+            if (n == 0) break;
+            // the other counter was last read before the previous barrier and is
+            // next filled after the coming one
+            if (tid == 0) s_cnt[cb ^ 1] = 0;
+            for (int i = tid; i < n; i += NT) {
+                const int p = sList[i];
+                const double q = sQ[p];
+                const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+                const int L = C::lds(lx, ly, lz);
+                const double tc = sT[L];
+                const double ax = fmin(sT[L - 1], sT[L + 1]);
+                const double ay = fmin(sT[L - C::SY], sT[L + C::SY]);
+                const double az = C::D3 ? fmin(sT[L - C::SZ], sT[L + C::SZ]) : inf64();
+                bool ch;
+                const double r = update(ax, ay, az, q, q * q, tc, ch);
+                if (ch) {
+                    sT[L] = r;
+                    uint8_t* nd = sDirty[cb ^ 1];
+                    if (lx > 0) nd[p - 1] = 1;
+                    if (lx < TX - 1) nd[p + 1] = 1;
+                    if (ly > 0) nd[p - TX] = 1;
+                    if (ly < TY - 1) nd[p + TX] = 1;
+                    if (C::D3) {
+                        if (lz > 0) nd[p - TX * TY] = 1;
+                        if (lz < TZ - 1) nd[p + TX * TY] = 1;
                     }
                 }
             }
             ++passes;
-            if (!__syncthreads_or(any)) break;
+            __syncthreads();
             cb ^= 1;
             if (passes > (1 << 20)) {
                 if (tid == 0) set_flag(S, kFlagWatchdog);
@@ -406,6 +472,11 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
             }
         }
 
+        if (tid == 0) {
+            const unsigned long long now = wall_clock64();
+            ph[2] += now - tm;
+            tm = now;
+        }
         // ---- write back lowered points, gather lowered face minima ---------
         unsigned int nchg = 0;
         double fmin_[6] = {inf64(), inf64(), inf64(), inf64(), inf64(), inf64()};
@@ -438,42 +509,29 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
             if (fmin_[f] < inf64()) atomicMin(&s_face[f], (unsigned long long)as_u64(fmin_[f]));
         }
         if (nchg) atomicAdd(&s_upd, nchg);
+        // every wave's stores complete before the block hands the tile's faces
+        // to the neighbours
+        stores_done();
         __syncthreads();
 
-        // ---- publish: V bit, release, activate neighbours, end the run ------
+        // ---- publish: V bit, activate neighbours, end the run --------------
+        if (tid < 64) publish(S, A.tkey, (uint32_t)tile, !visited, s_nb, s_nid, s_face);
         if (tid == 0) {
-            if (!visited)
-                __hip_atomic_fetch_or(S.tstate + tile, kV, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            for (int f = 0; f < 6; ++f) {
-                const uint32_t nb = s_nb[f];
-                const unsigned long long fm = s_face[f];
-                if ((nb & 0x40000000u) && fm != kInfBits) {
-                    int d = f >> 1, side = f & 1;
-                    int nt[3] = {tx, ty, tz};
-                    nt[d] += side ? 1 : -1;
-                    uint32_t nid = (uint32_t)(P.tile_off + (nt[2] * P.nty + nt[1]) * P.ntx + nt[0]);
-                    uint32_t old = __hip_atomic_fetch_or(S.tstate + nid, kQ, __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-                    const double tm = as_f64(fm);
-                    if ((old & (kQ | kR)) == 0) {
-                        activate_push(S, nid, tm);
-                    } else if (old & kR) {
-                        __hip_atomic_fetch_min((unsigned long long*)(A.tkey + nid), fm,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                }
-            }
-            __hip_atomic_fetch_add(S.counters + 1, (unsigned long long)s_upd, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(S.counters + 2, (unsigned long long)passes, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            uint64_t kb = __hip_atomic_exchange((unsigned long long*)(A.tkey + tile), kInfBits,
-                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            double requeue_t = kb == kInfBits ? 0.0 : as_f64(kb);
-            finish_run(S, (uint32_t)tile, requeue_t);
+            my_updates += s_upd;
+            my_passes += (unsigned long long)passes;
+            const unsigned long long now = wall_clock64();
+            ph[3] += now - tm;
+            tm = now;
         }
         __syncthreads();
+    }
+    if (tid == 0) {
+        ph[0] += wall_clock64() - tm;
+        for (int i = 0; i < 4; ++i)
+            __hip_atomic_fetch_add(S.counters + 5 + i, ph[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(S.counters + 0, my_visits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(S.counters + 1, my_updates, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(S.counters + 2, my_passes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -483,16 +541,10 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
 
 // One thread per point over all problems.  Reads |t| (a set sign bit marks a
 // source while the solve's encoding is still in place: then bit 7 is written).
-__global__ void k_parents(const Prob* probs, int nprob, long long npts_total, const double* t,
-                          uint8_t* par) {
+__global__ void k_parents(ProbTable T, long long npts_total, const double* t, uint8_t* par) {
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < npts_total; g += stride) {
-        int lo = 0, hi = nprob - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (probs[mid].pt_off <= g) lo = mid; else hi = mid - 1;
-        }
-        const Prob P = probs[lo];
+        const Prob P = prob_of_point(T, g);
         const int64_t i = g - P.pt_off;
         const double* tp = t + P.pt_off;
         const double ti = tp[i];
@@ -523,12 +575,10 @@ __global__ void k_parents(const Prob* probs, int nprob, long long npts_total, co
 }
 
 // Marks sources in a parent record computed from final (unsigned) times.
-__global__ void k_parents_mark_src(const Prob* probs, int nprob, const int64_t* src_off,
-                                   const int64_t* src_idx, long long nsrc, uint8_t* par) {
+__global__ void k_parents_mark_src(ProbTable T, const int64_t* src_idx, long long nsrc, uint8_t* par) {
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= nsrc) return;
-    int p = find_src_prob(src_off, nprob, g);
-    const Prob P = probs[p];
+    const Prob P = prob_of_source(T, g);
     int64_t idx = src_idx[g];
     if (idx < 0 || idx >= (int64_t)P.nx * P.ny * P.nz) return;
     par[P.pt_off + idx] = 0x80;

@@ -13,27 +13,49 @@
 //  * inversions are allowed (late pushes below `cur`, clamped far pushes):
 //    the operator is monotone and causal, so the order never changes results.
 //
-// Each ring is a bounded MPMC array of (sequence << 32 | tile) slots.  A tile is
-// queued at most once at a time (see the tile state machine), so a ring never
-// holds more than `ntiles` items and capacity = next_pow2(ntiles) suffices.
-// Head/tail counters are never reset, so slot sequence numbers never repeat and
-// stale slots from earlier solves are never mistaken for new items.
+// Each ring is a bounded MPMC array of 64-bit cells (sequence << 32 | tile),
+// positions taken with fetch-add.  A cell for position p is free when its
+// sequence equals p, full when it equals p + 1, and is freed for the next lap
+// (sequence p + cap) by the consumer after reading: a producer never overwrites
+// a cell whose item has been claimed but not yet read.  A tile is queued at most
+// once at a time (tile state machine below), so a ring never holds more than
+// `ntiles` items and capacity = next_pow2(max(ntiles, 2)) means no producer waits
+// on an unclaimed item.  Positions and counters are never reset between solves
+// (a solve ends with every ring drained), only re-initialised after a watchdog
+// expiry.
 //
 // Tile state word (one uint32 per tile):
 //   bit0 Q  queued / needs another run       bit1 R  a workgroup is running it
 //   bit2 V  interior of t holds real values  bit3 S  contains a point source
-// Activation = fetch_or(Q) after a release fence; whoever turns an idle word
+// Activation = fetch_or(Q) after the writer's stores completed; whoever turns an idle word
 // (no Q, no R) into Q pushes the tile.  A runner turns Q into R with an
 // acquiring RMW before it reads any t, and at the end either clears R (idle) or,
 // if Q was set meanwhile, keeps Q and pushes the tile again.  So every change
 // of a tile's halo or interior is followed by a run that starts after it, and
 // at most one workgroup runs a tile at any time.
+//
+// Memory ordering across the 8 XCDs (each with its own L2).  Every access to
+// data another workgroup may touch concurrently -- arrival times, adjoint
+// multipliers, tile states, queue cells and counters -- is a device-scope
+// (agent) atomic, which gfx950 issues with the device-scope cache policy
+// (loads and stores coherent at device scope without any cache maintenance).
+// Ordering then only needs completion: a writer waits until its stores have
+// been acknowledged (`stores_done`, s_waitcnt vmcnt(0) in every wave, then a
+// barrier) before the RMW that hands the data over, and a reader issues its
+// loads only after the RMW that took the data over has returned.  This replaces
+// agent-scope release/acquire fences, whose L2 write-back / invalidate on every
+// tile visit cost far more than the visit itself.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace eik {
+
+// Wait until every memory operation this wave issued has completed (device
+// scope for the device-scope atomics used for shared data); also a compiler
+// barrier.
+__device__ __forceinline__ void stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 constexpr uint32_t kQ = 1u, kR = 2u, kV = 4u, kS = 8u;
 constexpr int kMaxRings = 64;
@@ -58,7 +80,7 @@ struct Sched {
 };
 
 __device__ __forceinline__ uint32_t ld_acq(uint32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint32_t ld_rlx(uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -89,11 +111,22 @@ __device__ __forceinline__ void push_tile(const Sched& s, uint32_t tile, double 
     if (k > c + s.nrings - 1) k = c + s.nrings - 1;
     int r = (int)(k % s.nrings);
     uint32_t* ctr = s.ctr + r * kCtrStride;
-    uint32_t slot = __hip_atomic_fetch_add(ctr + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint64_t item = ((uint64_t)slot << 32) | tile;
-    __hip_atomic_store(s.items + (size_t)r * (s.cap_mask + 1) + (slot & s.cap_mask), item,
-                       __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(ctr + 2, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t pos = __hip_atomic_fetch_add(ctr + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t* cell = s.items + (size_t)r * (s.cap_mask + 1) + (pos & s.cap_mask);
+    // wait until the previous lap's consumer has read this cell (bounded: that
+    // consumer has already claimed it)
+    for (long long spin = 0;; ++spin) {
+        uint64_t it = __hip_atomic_load(cell, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)(it >> 32) == pos) break;
+        if (spin > (1ll << 24)) {
+            set_flag(s, kFlagWatchdog);
+            return;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __hip_atomic_store(cell, ((uint64_t)(pos + 1u) << 32) | tile, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    stores_done();
+    __hip_atomic_fetch_add(ctr + 2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Count a newly activated tile and enqueue it.  Single lane.
@@ -110,22 +143,27 @@ __device__ __forceinline__ void activate(const Sched& s, uint32_t tile, double t
     if ((old & (kQ | kR)) == 0) activate_push(s, tile, t);
 }
 
-// Try to take one item from ring r.  Returns the tile or -1.  Single lane.
+// Try to take one item from ring r.  Returns the tile, -1 (empty) or -2
+// (watchdog).  Single lane.
 __device__ __forceinline__ int try_claim(const Sched& s, int r) {
     uint32_t* ctr = s.ctr + r * kCtrStride;
-    int32_t old = (int32_t)__hip_atomic_fetch_sub(ctr + 2, 1u, __ATOMIC_ACQUIRE,
+    int32_t old = (int32_t)__hip_atomic_fetch_sub(ctr + 2, 1u, __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_AGENT);
     if (old <= 0) {
         __hip_atomic_fetch_add(ctr + 2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return -1;
     }
-    uint32_t slot = __hip_atomic_fetch_add(ctr + 0, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint64_t* p = s.items + (size_t)r * (s.cap_mask + 1) + (slot & s.cap_mask);
-    // The producer that reserved this slot has already advanced the tail and is
-    // about to store it; wait for the store with a bounded spin.
+    uint32_t pos = __hip_atomic_fetch_add(ctr + 0, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t* cell = s.items + (size_t)r * (s.cap_mask + 1) + (pos & s.cap_mask);
+    // The producer that reserved this position is about to fill the cell.
     for (long long spin = 0;; ++spin) {
-        uint64_t it = __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        if ((uint32_t)(it >> 32) == slot) return (int)(uint32_t)it;
+        uint64_t it = __hip_atomic_load(cell, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)(it >> 32) == pos + 1u) {
+            // free the cell for the next lap
+            __hip_atomic_store(cell, (uint64_t)(pos + s.cap_mask + 1u) << 32, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            return (int)(uint32_t)it;
+        }
         if (spin > (1ll << 24)) {
             set_flag(s, kFlagWatchdog);
             return -2;
@@ -157,33 +195,89 @@ __device__ __forceinline__ int claim(const Sched& s) {
             if (got >= 0 || got == -2) return got;
         }
         if (ld_rlx(s.pending) <= 0) return -1;
-        if (++idle > (1ll << 22)) {
+        if (++idle > (1ll << 21)) {
             if (lane == 0) set_flag(s, kFlagWatchdog);
             return -2;
         }
-        __builtin_amdgcn_s_sleep(2);
+        if (idle < 8) __builtin_amdgcn_s_sleep(2);
+        else __builtin_amdgcn_s_sleep(20);
     }
 }
 
-// End of a run of `tile` by its runner.  Returns true if the tile was re-queued
-// (Q was set during the run).  Single lane; caller passes the key for a requeue.
-__device__ __forceinline__ bool finish_run(const Sched& s, uint32_t tile, double requeue_t) {
+// End of a run of `tile`, executed by the 64 lanes of wave 0 after every wave
+// of the block has written its results and waited for them (stores_done).
+//   nb[f]   neighbour f's state word with bit 30 set when it exists,
+//   nid[f]  its tile id, face[f] the priority key bits of the lowered values on
+//           face f (kInfBits: nothing lowered there),
+//   first   the run wrote this tile's interior for the first time (sets V).
+// Lanes 0..5 activate the neighbours in parallel; the block's pending count
+// changes once, by (#newly queued neighbours + requeue - 1), before any push
+// makes the new items claimable, so it never under-counts live work.
+__device__ __forceinline__ void publish(const Sched& s, uint64_t* tkey, uint32_t tile, bool first,
+                                        const uint32_t* nb, const uint32_t* nid,
+                                        const unsigned long long* face) {
+    const int lane = threadIdx.x & 63;
+    if (first) {
+        if (lane == 0)
+            __hip_atomic_fetch_or(s.tstate + tile, kV, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        stores_done();
+    }
+    bool want = false;
+    uint32_t n = 0;
+    unsigned long long fk = kInfBits;
+    if (lane < 6) {
+        fk = face[lane];
+        if ((nb[lane] & 0x40000000u) && fk != kInfBits) {
+            n = nid[lane];
+            uint32_t old = __hip_atomic_fetch_or(s.tstate + n, kQ, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((old & (kQ | kR)) == 0) {
+                want = true;
+            } else if (old & kR) {
+                __hip_atomic_fetch_min((unsigned long long*)(tkey + n), fk, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+    const int k = __popcll(__ballot(want));
+    int requeue = 0;
+    double rkey = 0.0;
+    if (lane == 0) {
+        uint32_t* w = s.tstate + tile;
+        uint32_t old = ld_rlx(w);
+        for (;;) {
+            uint32_t seen = old;
+            if (__hip_atomic_compare_exchange_strong(w, &seen, old & ~kR, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT))
+                break;
+            old = seen;
+        }
+        if (old & kQ) {
+            requeue = 1;
+            uint64_t kb = __hip_atomic_exchange((unsigned long long*)(tkey + tile), kInfBits,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            rkey = kb == kInfBits ? 0.0 : as_f64(kb);
+        }
+        const int delta = k + requeue - 1;
+        if (delta != 0)
+            __hip_atomic_fetch_add(s.pending, delta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (want) push_tile(s, n, as_f64(fk));
+    if (lane == 0 && requeue) push_tile(s, tile, rkey);
+}
+
+// Drop a claimed tile without running it (visit cap reached).  Lane 0.
+__device__ __forceinline__ void drop_run(const Sched& s, uint32_t tile) {
     uint32_t* w = s.tstate + tile;
     uint32_t old = ld_rlx(w);
     for (;;) {
-        uint32_t nw = old & ~kR;
         uint32_t seen = old;
-        if (__hip_atomic_compare_exchange_strong(w, &seen, nw, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT)) {
-            if (old & kQ) {
-                push_tile(s, tile, requeue_t);  // stays counted in pending
-                return true;
-            }
-            __hip_atomic_fetch_sub(s.pending, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
-        }
+        if (__hip_atomic_compare_exchange_strong(w, &seen, old & ~kR, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            break;
         old = seen;
     }
+    if (old & kQ) push_tile(s, tile, 0.0);
+    else __hip_atomic_fetch_sub(s.pending, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace eik
