@@ -57,6 +57,8 @@ extern "C" {
 #define EIK_EHANG (-8)    /* a device-side watchdog expired (internal error) */
 
 #define EIK_FLAG_TIME_KERNELS 1u  /* eik_opts.flags: time the persistent kernel with HIP events */
+#define EIK_FLAG_WAVE_TILES 2u    /* eik_opts.flags: forward solve with one tile per wave (tiles
+                                     3D 8x8x4, 16x8x4, 8x8x8, 16x4x4; 2D 16x16, 32x16, 32x8) */
 
 #define EIK_SPEED 0       /* field holds speed v:    q = h / v */
 #define EIK_SLOWNESS 1    /* field holds slowness s: q = h * s */
@@ -78,6 +80,8 @@ typedef struct {
                                 persistent kernel (solve or adjoint) on `stream`; eik_status
                                 then reports the mean duration of the kernels timed since the
                                 previous eik_status (at most 4096 launches in between) */
+    int32_t lookahead;       /* 0..8: work may be taken from the lowest non-drained bucket
+                                and this many buckets above it (0 = strict bucket order) */
 } eik_opts;
 
 typedef struct {
@@ -92,6 +96,9 @@ typedef struct {
     double phase_us[4];      /* forward solve, summed over workgroups (microseconds of wall
                                 clock): [0] claiming / waiting for work, [1] staging a tile
                                 and its halo in LDS, [2] relaxing, [3] write-back + publish */
+    double process_us;       /* part of phase_us[2] spent applying the operator to the pass lists */
+    int64_t workgroups;      /* persistent workgroups of the last forward launch */
+    int64_t bucket_advances; /* times the lowest open priority bucket moved on */
 } eik_stats;
 
 /* Forward solve.

@@ -24,6 +24,7 @@ EIK_EHANG = -8
 EIK_SPEED = 0
 EIK_SLOWNESS = 1
 EIK_FLAG_TIME_KERNELS = 1
+EIK_FLAG_WAVE_TILES = 2
 
 EXPORTED = (
     "eik_solve", "eik_parents", "eik_adjoint", "eik_solve_batched", "eik_adjoint_batched",
@@ -40,7 +41,7 @@ class eik_grid(ctypes.Structure):
 class eik_opts(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_double), ("tile", ctypes.c_int32 * 3),
                 ("grid_blocks", ctypes.c_int32), ("max_tile_visits", ctypes.c_int64),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("lookahead", ctypes.c_int32)]
 
 
 class eik_stats(ctypes.Structure):
@@ -48,7 +49,8 @@ class eik_stats(ctypes.Structure):
                 ("ntiles", ctypes.c_int64), ("relax_passes", ctypes.c_int64),
                 ("flags", ctypes.c_uint32), ("status", ctypes.c_int32),
                 ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_int64),
-                ("phase_us", ctypes.c_double * 4)]
+                ("phase_us", ctypes.c_double * 4), ("process_us", ctypes.c_double),
+                ("workgroups", ctypes.c_int64), ("bucket_advances", ctypes.c_int64)]
 
 
 class EikError(RuntimeError):

@@ -38,7 +38,8 @@ def _grid_of(shape: Sequence[int], h: float, kind: str) -> eik_grid:
 
 
 def make_opts(delta: float = 0.0, tile: Optional[Sequence[int]] = None, grid_blocks: int = 0,
-              max_tile_visits: int = 0, time_kernels: bool = False) -> eik_opts:
+              max_tile_visits: int = 0, time_kernels: bool = False, lookahead: int = 0,
+              wave_tiles: bool = False) -> eik_opts:
     o = eik_opts()
     o.delta = float(delta)
     t = tuple(tile) if tile else (0, 0, 0)
@@ -48,7 +49,9 @@ def make_opts(delta: float = 0.0, tile: Optional[Sequence[int]] = None, grid_blo
         o.tile[i] = int(t[i])
     o.grid_blocks = int(grid_blocks)
     o.max_tile_visits = int(max_tile_visits)
-    o.flags = _lib.EIK_FLAG_TIME_KERNELS if time_kernels else 0
+    o.flags = (_lib.EIK_FLAG_TIME_KERNELS if time_kernels else 0) | \
+        (_lib.EIK_FLAG_WAVE_TILES if wave_tiles else 0)
+    o.lookahead = int(lookahead)
     return o
 
 
@@ -102,8 +105,11 @@ def solve(field: torch.Tensor, h: float, sources, t0: Optional[torch.Tensor] = N
           kind: str = "speed", parents: bool = False, delta: float = 0.0,
           tile: Optional[Sequence[int]] = None, grid_blocks: int = 0, max_tile_visits: int = 0,
           out: Optional[torch.Tensor] = None, parents_out: Optional[torch.Tensor] = None,
-          check_status: bool = True, stream=None, time_kernels: bool = False):
-    """First-arrival times; returns t, or (t, parents) when parents=True."""
+          check_status: bool = True, stream=None, time_kernels: bool = False, lookahead: int = 0,
+          wave_tiles: bool = False):
+    """First-arrival times; returns t, or (t, parents) when parents=True.  `wave_tiles`
+    selects the one-tile-per-wave solver (tile shapes 3D 8x8x4, 16x8x4, 8x8x8,
+    16x4x4; 2D 16x16, 32x16, 32x8)."""
     _check_field(field)
     L = _lib.load()
     g = _grid_of(field.shape, h, kind)
@@ -118,7 +124,7 @@ def solve(field: torch.Tensor, h: float, sources, t0: Optional[torch.Tensor] = N
     if parents:
         par = parents_out if parents_out is not None else torch.empty(field.shape, dtype=torch.uint8,
                                                                        device=field.device)
-    o = make_opts(delta, tile, grid_blocks, max_tile_visits, time_kernels)
+    o = make_opts(delta, tile, grid_blocks, max_tile_visits, time_kernels, lookahead, wave_tiles)
     rc = L.eik_solve(ctypes.byref(g), field.data_ptr(), src.numel(), src.data_ptr(),
                      t0d.data_ptr() if t0d is not None else None, t.data_ptr(),
                      par.data_ptr() if par is not None else None, ctypes.byref(o),
@@ -144,7 +150,8 @@ def adjoint(field: torch.Tensor, h: float, t: torch.Tensor, parents: torch.Tenso
             dL_dt: torch.Tensor, kind: str = "speed", delta: float = 0.0,
             tile: Optional[Sequence[int]] = None, grid_blocks: int = 0,
             out: Optional[torch.Tensor] = None, mu_out: Optional[torch.Tensor] = None,
-            check_status: bool = True, stream=None, time_kernels: bool = False) -> torch.Tensor:
+            check_status: bool = True, stream=None, time_kernels: bool = False,
+            lookahead: int = 0) -> torch.Tensor:
     """d loss / d slowness from d loss / d t through the recorded upwind parents."""
     for a in (field, t, dL_dt):
         _check_field(a)
@@ -155,7 +162,7 @@ def adjoint(field: torch.Tensor, h: float, t: torch.Tensor, parents: torch.Tenso
     L = _lib.load()
     g = _grid_of(field.shape, h, kind)
     grad = out if out is not None else torch.empty_like(field)
-    o = make_opts(delta, tile, grid_blocks, 0, time_kernels)
+    o = make_opts(delta, tile, grid_blocks, 0, time_kernels, lookahead)
     rc = L.eik_adjoint(ctypes.byref(g), field.data_ptr(), t.data_ptr(), parents.data_ptr(),
                        dL_dt.data_ptr(), grad.data_ptr(),
                        mu_out.data_ptr() if mu_out is not None else None, ctypes.byref(o),
@@ -258,10 +265,10 @@ def pack(fields: Sequence[torch.Tensor], hs: Union[float, Sequence[float]], sour
 
 def solve_packed(b: Batch, t_packed: torch.Tensor, par_packed: Optional[torch.Tensor] = None,
                  delta: float = 0.0, tile=None, grid_blocks: int = 0, stream=None,
-                 time_kernels: bool = False) -> None:
+                 time_kernels: bool = False, lookahead: int = 0, wave_tiles: bool = False) -> None:
     """Enqueue one batched forward launch (no host synchronisation)."""
     L = _lib.load()
-    o = make_opts(delta, tile, grid_blocks, 0, time_kernels)
+    o = make_opts(delta, tile, grid_blocks, 0, time_kernels, lookahead, wave_tiles)
     check(L.eik_solve_batched(b.nprob, b.grids, b.offsets, b.field.data_ptr(), b.src_off,
                               b.src.data_ptr(), b.t0.data_ptr() if b.t0 is not None else None,
                               t_packed.data_ptr(), par_packed.data_ptr() if par_packed is not None else None,
@@ -270,9 +277,10 @@ def solve_packed(b: Batch, t_packed: torch.Tensor, par_packed: Optional[torch.Te
 
 def adjoint_packed(b: Batch, t_packed: torch.Tensor, par_packed: torch.Tensor, g_packed: torch.Tensor,
                    grad_packed: torch.Tensor, mu_packed: Optional[torch.Tensor] = None, delta: float = 0.0,
-                   tile=None, grid_blocks: int = 0, stream=None, time_kernels: bool = False) -> None:
+                   tile=None, grid_blocks: int = 0, stream=None, time_kernels: bool = False,
+                   lookahead: int = 0) -> None:
     L = _lib.load()
-    o = make_opts(delta, tile, grid_blocks, 0, time_kernels)
+    o = make_opts(delta, tile, grid_blocks, 0, time_kernels, lookahead)
     check(L.eik_adjoint_batched(b.nprob, b.grids, b.offsets, b.field.data_ptr(), t_packed.data_ptr(),
                                 par_packed.data_ptr(), g_packed.data_ptr(), grad_packed.data_ptr(),
                                 mu_packed.data_ptr() if mu_packed is not None else None,

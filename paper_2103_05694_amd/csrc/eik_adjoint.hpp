@@ -72,7 +72,7 @@ __global__ void k_adj_push_all(int ntiles, const uint64_t* tile_tmax,
     for (int tile = blockIdx.x * blockDim.x + threadIdx.x; tile < ntiles; tile += gridDim.x * blockDim.x) {
         s.tstate[tile] = kQ;
         __hip_atomic_fetch_add(s.pending, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        push_tile(s, (uint32_t)tile, tref - as_f64(tile_tmax[tile]));
+        push_tile(s, (uint32_t)tile, tref - as_f64(tile_tmax[tile]), 0);
     }
 }
 
@@ -98,6 +98,7 @@ __global__ void __launch_bounds__(NT) k_adjoint(AdjArgs A) {
     __shared__ uint8_t sP[C::NLDS];
     __shared__ uint8_t sDirty[2][C::NP];
     __shared__ int s_tile;
+    __shared__ int64_t s_bucket;
     __shared__ uint32_t s_state;
     __shared__ uint32_t s_nb[6];
     __shared__ uint32_t s_nid[6];
@@ -114,9 +115,11 @@ __global__ void __launch_bounds__(NT) k_adjoint(AdjArgs A) {
 
     for (;;) {
         if (tid < 64) {
-            int tile = claim(S);
+            int64_t bucket = 0;
+            int tile = claim(S, &bucket);
             if (tid == 0) {
                 s_tile = tile;
+                s_bucket = bucket;
                 if (tile >= 0) {
                     ++my_visits;
                     uint32_t st = __hip_atomic_fetch_xor(S.tstate + tile, kQ | kR, __ATOMIC_RELAXED,
@@ -340,7 +343,7 @@ __global__ void __launch_bounds__(NT) k_adjoint(AdjArgs A) {
         stores_done();
         __syncthreads();
 
-        if (tid < 64) publish(S, A.tkey, (uint32_t)tile, !visited, s_nb, s_nid, s_face);
+        if (tid < 64) publish(S, A.tkey, (uint32_t)tile, s_bucket, !visited, s_nb, s_nid, s_face);
         if (tid == 0) my_done += s_done;
         __syncthreads();
     }

@@ -13,6 +13,7 @@
 
 #include "eik.h"
 #include "eik_adjoint.hpp"
+#include "eik_wave.hpp"
 
 using namespace eik;
 
@@ -34,6 +35,8 @@ int fail(int code, const std::string& msg) {
 
 constexpr int kThreads = 256;
 constexpr int kRings = 32;
+constexpr int kScalWords = 192;
+constexpr int kSCur = 0, kSPending = 64, kSFlags = 128, kSPoisoned = 129, kSSrcCount = 130;
 
 struct Workspace {
     int device = -1;
@@ -45,7 +48,8 @@ struct Workspace {
     uint64_t* tkey = nullptr;
     int64_t tiles_cap = 0;
     uint32_t ring_cap = 0;
-    // scalars: [0] cur [1] pending [2] flags [3] poisoned [4] srclist_count
+    // scalars, on separate 256-byte lines: cur, pending, then flags / poisoned /
+    // source-list count (see the kS* offsets)
     int32_t* scal = nullptr;
     unsigned long long* counters = nullptr;
     int32_t* srclist = nullptr;
@@ -122,15 +126,15 @@ int get_ws(hipStream_t st, Workspace** out) {
     Workspace* w = new Workspace();
     w->device = dev;
     w->stream = st;
-    hipError_t e = hipMalloc((void**)&w->scal, 64 * sizeof(int32_t));
+    hipError_t e = hipMalloc((void**)&w->scal, kScalWords * sizeof(int32_t));
     if (e == hipSuccess) e = hipMalloc((void**)&w->counters, 16 * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMalloc((void**)&w->ctr, sizeof(uint32_t) * kRings * kCtrStride);
     if (e != hipSuccess) {
         delete w;
         return fail(EIK_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
     }
-    int32_t init[64] = {0};
-    init[3] = 1;  // poisoned: the first reset initialises the rings
+    int32_t init[kScalWords] = {0};
+    init[kSPoisoned] = 1;  // the first reset initialises the rings
     HIP_TRY(hipMemcpy(w->scal, init, sizeof(init), hipMemcpyHostToDevice));
     HIP_TRY(hipMemset(w->ctr, 0, sizeof(uint32_t) * kRings * kCtrStride));
     HIP_TRY(hipMemset(w->counters, 0, 16 * sizeof(unsigned long long)));
@@ -166,7 +170,7 @@ int ensure_tiles(Workspace& w, int64_t ntiles) {
         w.ring_cap = need_ring;
         // fresh ring memory: the next reset must initialise it
         int32_t one = 1;
-        HIP_TRY(hipMemcpy(w.scal + 3, &one, sizeof(one), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(w.scal + kSPoisoned, &one, sizeof(one), hipMemcpyHostToDevice));
     }
     return EIK_OK;
 }
@@ -231,18 +235,30 @@ struct TileShape {
 
 #define EIK_TILES_3D(X) X(32, 8, 4) X(16, 8, 8) X(8, 8, 8) X(64, 4, 4)
 #define EIK_TILES_2D(X) X(32, 32, 1) X(64, 16, 1) X(128, 8, 1) X(16, 16, 1)
+// one tile per wave (EIK_FLAG_WAVE_TILES)
+#define EIK_WTILES_3D(X) X(8, 8, 4) X(16, 8, 4) X(8, 8, 8) X(16, 4, 4)
+#define EIK_WTILES_2D(X) X(16, 16, 1) X(32, 16, 1) X(32, 8, 1)
+constexpr int kWavesPerBlock = 4;
 
-bool tile_supported(int ndim, int x, int y, int z) {
+bool tile_supported(int ndim, int x, int y, int z, bool wave) {
 #define EIK_MATCH(a, b, c) \
     if (x == a && y == b && z == c) return (ndim == 3) == (c > 1);
-    EIK_TILES_3D(EIK_MATCH)
-    EIK_TILES_2D(EIK_MATCH)
+    if (wave) {
+        EIK_WTILES_3D(EIK_MATCH)
+        EIK_WTILES_2D(EIK_MATCH)
+    } else {
+        EIK_TILES_3D(EIK_MATCH)
+        EIK_TILES_2D(EIK_MATCH)
+    }
 #undef EIK_MATCH
     return false;
 }
 
+bool wave_mode(const eik_opts* o) { return o && (o->flags & EIK_FLAG_WAVE_TILES); }
+
 TileShape pick_tile(int ndim, const eik_opts* o) {
     if (o && (o->tile[0] || o->tile[1] || o->tile[2])) return {o->tile[0], o->tile[1], o->tile[2]};
+    if (wave_mode(o)) return ndim == 3 ? TileShape{8, 8, 4} : TileShape{16, 16, 1};
     if (ndim == 3) return {32, 8, 4};
     return {64, 16, 1};
 }
@@ -264,7 +280,8 @@ int check_opts(const eik_opts* o) {
     if (!(o->delta >= 0.0) || std::isnan(o->delta)) return fail(EIK_EINVAL, "delta must be >= 0");
     if (o->grid_blocks < 0) return fail(EIK_EINVAL, "grid_blocks must be >= 0");
     if (o->max_tile_visits < 0) return fail(EIK_EINVAL, "max_tile_visits must be >= 0");
-    if (o->flags & ~EIK_FLAG_TIME_KERNELS) return fail(EIK_EINVAL, "unknown flags");
+    if (o->flags & ~(EIK_FLAG_TIME_KERNELS | EIK_FLAG_WAVE_TILES)) return fail(EIK_EINVAL, "unknown flags");
+    if (o->lookahead < 0 || o->lookahead > 8) return fail(EIK_EINVAL, "lookahead must be in 0..8");
     return EIK_OK;
 }
 
@@ -290,16 +307,17 @@ Sched make_sched(Workspace& w, const eik_opts* o) {
     s.items = w.items;
     s.ctr = w.ctr;
     s.tstate = w.tstate;
-    s.cur = w.scal + 0;
-    s.pending = w.scal + 1;
-    s.flags = (uint32_t*)(w.scal + 2);
-    s.poisoned = w.scal + 3;
+    s.cur = w.scal + kSCur;
+    s.pending = w.scal + kSPending;
+    s.flags = (uint32_t*)(w.scal + kSFlags);
+    s.poisoned = w.scal + kSPoisoned;
     s.counters = w.counters;
     s.nrings = kRings;
     s.cap_mask = w.ring_cap - 1;
     double d = o ? o->delta : 0.0;
     s.inv_delta = (d > 0.0 && std::isfinite(d)) ? 1.0 / d : 0.0;
     s.max_visits = o ? (long long)o->max_tile_visits : 0;
+    s.lookahead = o ? o->lookahead : 0;
     return s;
 }
 
@@ -332,7 +350,7 @@ int blocks_for(int64_t n, int threads, int cap = 65536) {
 }
 
 // The full forward sequence for one tile shape.
-template <int TX, int TY, int TZ>
+template <int TX, int TY, int TZ, bool WAVE>
 int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int64_t>& src_off,
             int64_t ntiles, int64_t npts_total, const double* field, const int64_t* src_idx,
             const double* src_t0, double* t, uint8_t* par, const eik_opts* o) {
@@ -345,7 +363,7 @@ int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int6
     hipStream_t st = w.stream;
     const int nprob = (int)probs.size();
     Sched s = make_sched(w, o);
-    int32_t* srccnt = w.scal + 4;
+    int32_t* srccnt = w.scal + kSSrcCount;
 
     hipLaunchKernelGGL(k_reset, dim3(blocks_for(std::max<int64_t>(ntiles, (int64_t)kRings * w.ring_cap), kThreads, 4096)),
                        dim3(kThreads), 0, st, s, w.tkey, (int)ntiles, srccnt,
@@ -365,12 +383,23 @@ int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int6
     a.tkey = w.tkey;
     a.s = s;
     int grid = 0;
-    if ((rc = occupancy_grid(k_solve<TX, TY, TZ, kThreads>, kThreads, &grid))) return rc;
-    if (o && o->grid_blocks > 0) grid = std::min(grid, o->grid_blocks);
-    if ((int64_t)grid > ntiles) grid = (int)ntiles;
-    if (grid < 1) grid = 1;
-    if ((rc = timing_begin(w, o))) return rc;
-    hipLaunchKernelGGL((k_solve<TX, TY, TZ, kThreads>), dim3(grid), dim3(kThreads), 0, st, a);
+    if constexpr (WAVE) {
+        constexpr int nt = 64 * kWavesPerBlock;
+        if ((rc = occupancy_grid(k_solve_w<TX, TY, TZ, kWavesPerBlock>, nt, &grid))) return rc;
+        if (o && o->grid_blocks > 0) grid = std::min(grid, o->grid_blocks);
+        const int64_t need = (ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+        if ((int64_t)grid > need) grid = (int)need;
+        if (grid < 1) grid = 1;
+        if ((rc = timing_begin(w, o))) return rc;
+        hipLaunchKernelGGL((k_solve_w<TX, TY, TZ, kWavesPerBlock>), dim3(grid), dim3(nt), 0, st, a);
+    } else {
+        if ((rc = occupancy_grid(k_solve<TX, TY, TZ, kThreads>, kThreads, &grid))) return rc;
+        if (o && o->grid_blocks > 0) grid = std::min(grid, o->grid_blocks);
+        if ((int64_t)grid > ntiles) grid = (int)ntiles;
+        if (grid < 1) grid = 1;
+        if ((rc = timing_begin(w, o))) return rc;
+        hipLaunchKernelGGL((k_solve<TX, TY, TZ, kThreads>), dim3(grid), dim3(kThreads), 0, st, a);
+    }
     HIP_TRY(hipGetLastError());
     if ((rc = timing_end(w, o))) return rc;
 
@@ -394,10 +423,19 @@ int dispatch_forward(TileShape ts, Workspace& w, const std::vector<Prob>& probs,
                      uint8_t* par, const eik_opts* o) {
 #define EIK_CASE(a, b, c)                                                                      \
     if (ts.x == a && ts.y == b && ts.z == c)                                                   \
-        return forward<a, b, c>(w, probs, src_off, ntiles, npts, field, src_idx, src_t0, t, par, o);
-    EIK_TILES_3D(EIK_CASE)
-    EIK_TILES_2D(EIK_CASE)
+        return forward<a, b, c, false>(w, probs, src_off, ntiles, npts, field, src_idx, src_t0, t, par, o);
+#define EIK_WCASE(a, b, c)                                                                     \
+    if (ts.x == a && ts.y == b && ts.z == c)                                                   \
+        return forward<a, b, c, true>(w, probs, src_off, ntiles, npts, field, src_idx, src_t0, t, par, o);
+    if (wave_mode(o)) {
+        EIK_WTILES_3D(EIK_WCASE)
+        EIK_WTILES_2D(EIK_WCASE)
+    } else {
+        EIK_TILES_3D(EIK_CASE)
+        EIK_TILES_2D(EIK_CASE)
+    }
 #undef EIK_CASE
+#undef EIK_WCASE
     return fail(EIK_ENOTSUP, "unsupported tile shape");
 }
 
@@ -419,7 +457,7 @@ int adjoint(Workspace& w, const std::vector<Prob>& probs, int64_t ntiles, int64_
     s.max_visits = 0;
     unsigned long long* tref = w.counters + 4;
     hipLaunchKernelGGL(k_reset, dim3(blocks_for(std::max<int64_t>(ntiles, (int64_t)kRings * w.ring_cap), kThreads, 4096)),
-                       dim3(kThreads), 0, st, s, w.tkey, (int)ntiles, w.scal + 4,
+                       dim3(kThreads), 0, st, s, w.tkey, (int)ntiles, w.scal + kSSrcCount,
                        (long long)kRings * w.ring_cap);
     hipLaunchKernelGGL((k_adj_prep<TX, TY, TZ>), dim3((unsigned)std::min<int64_t>(ntiles, 65536)), dim3(kThreads),
                        0, st, T, (int)ntiles, t, w.tile_tmax, tref);
@@ -512,7 +550,7 @@ const char* eik_last_error(void) { return g_last_error.c_str(); }
 int64_t eik_num_tiles(const eik_grid* g, const eik_opts* o) {
     if (check_grid(g)) return -1;
     TileShape ts = pick_tile(g->ndim, o);
-    if (!tile_supported(g->ndim, ts.x, ts.y, ts.z)) return -1;
+    if (!tile_supported(g->ndim, ts.x, ts.y, ts.z, wave_mode(o))) return -1;
     return tiles_of(make_prob(*g, ts, 0, 0));
 }
 
@@ -531,7 +569,7 @@ int eik_solve_batched(int32_t nprob, const eik_grid* grids_host, const int64_t* 
         if (soff[i + 1] - soff[i] < 1) return fail(EIK_EINVAL, "every problem needs at least one source");
     if (soff[nprob] > ((int64_t)1 << 31)) return fail(EIK_ENOTSUP, "too many sources");
     TileShape ts = pick_tile(grids_host[0].ndim, opts);
-    if (!tile_supported(grids_host[0].ndim, ts.x, ts.y, ts.z))
+    if (!tile_supported(grids_host[0].ndim, ts.x, ts.y, ts.z, wave_mode(opts)))
         return fail(EIK_ENOTSUP, "unsupported tile shape for this ndim");
     std::vector<Prob> probs;
     int64_t ntiles = 0, npts = 0;
@@ -587,8 +625,9 @@ int eik_adjoint_batched(int32_t nprob, const eik_grid* grids_host, const int64_t
     if (offsets_host[0] != 0) return fail(EIK_EINVAL, "offsets must start at 0");
     int rc = check_opts(opts);
     if (rc) return rc;
+    if (wave_mode(opts)) return fail(EIK_ENOTSUP, "the adjoint runs one tile per block (no EIK_FLAG_WAVE_TILES)");
     TileShape ts = pick_tile(grids_host[0].ndim, opts);
-    if (!tile_supported(grids_host[0].ndim, ts.x, ts.y, ts.z))
+    if (!tile_supported(grids_host[0].ndim, ts.x, ts.y, ts.z, false))
         return fail(EIK_ENOTSUP, "unsupported tile shape for this ndim");
     std::vector<Prob> probs;
     int64_t ntiles = 0, npts = 0;
@@ -623,11 +662,11 @@ int eik_status(void* stream, eik_stats* out) {
     int rc;
     if ((rc = get_ws((hipStream_t)stream, &w))) return rc;
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
-    int32_t sc[8];
+    int32_t sc[kScalWords];
     unsigned long long ctr[16];
     HIP_TRY(hipMemcpy(sc, w->scal, sizeof(sc), hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(ctr, w->counters, sizeof(ctr), hipMemcpyDeviceToHost));
-    uint32_t flags = (uint32_t)sc[2];
+    uint32_t flags = (uint32_t)sc[kSFlags];
     int code = EIK_OK;
     if (flags & kFlagWatchdog) code = EIK_EHANG;
     else if (flags & kFlagBadSrc) code = EIK_EBADSRC;
@@ -643,6 +682,9 @@ int eik_status(void* stream, eik_stats* out) {
         out->kernel_ms = -1.0;
         out->kernel_launches = (int64_t)w->ev_used;
         for (int i = 0; i < 4; ++i) out->phase_us[i] = (double)ctr[5 + i] / 100.0;  // 100 MHz clock
+        out->process_us = (double)ctr[9] / 100.0;
+        out->workgroups = (int64_t)ctr[10];
+        out->bucket_advances = (int64_t)ctr[11];
         if (w->ev_used) {
             double sum = 0.0;
             for (size_t i = 0; i < w->ev_used; ++i) {

@@ -185,7 +185,7 @@ __global__ void k_src_place(ProbTable T, const int64_t* src_idx, const double* s
     uint32_t tile = tile_of_point<TX, TY, TZ>(P, idx);
     uint32_t old = __hip_atomic_fetch_or(s.tstate + tile, kQ | kV, __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_AGENT);
-    if (!(old & kQ)) activate_push(s, tile, t0);
+    if (!(old & kQ)) activate_push(s, tile, t0, 0);
 }
 
 // Restores +t0 at the sources.
@@ -260,6 +260,7 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
     __shared__ uint16_t sList[C::NP];
     __shared__ int s_cnt[2];
     __shared__ int s_tile;
+    __shared__ int64_t s_bucket;
     __shared__ uint32_t s_state;
     __shared__ uint32_t s_nb[6];
     __shared__ uint32_t s_nid[6];
@@ -271,15 +272,17 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
     // per-workgroup statistics, flushed once at exit; the phase times use the
     // 100 MHz wall clock: [0] claim, [1] stage, [2] relax, [3] write + publish
     unsigned long long my_visits = 0, my_updates = 0, my_passes = 0;
-    unsigned long long ph[4] = {0, 0, 0, 0};
+    unsigned long long ph[6] = {0, 0, 0, 0, 0, 0};
     unsigned long long tm = wall_clock64();
 
     for (;;) {
         // ---- claim ------------------------------------------------------
         if (tid < 64) {
-            int tile = claim(S);
+            int64_t bucket = 0;
+            int tile = claim(S, &bucket);
             if (tid == 0) {
                 s_tile = tile;
+                s_bucket = bucket;
                 if (tile >= 0) {
                     // Q -> R; every load of this run is issued after it returned
                     uint32_t st = __hip_atomic_fetch_xor(S.tstate + tile, kQ | kR, __ATOMIC_RELAXED,
@@ -313,7 +316,7 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
         }
 
         if (st & 0x80000000u) {  // visit cap reached: drop the tile
-            if (tid == 0) drop_run(S, (uint32_t)tile);
+            if (tid == 0) drop_run(S, (uint32_t)tile, s_bucket);
             __syncthreads();
             continue;
         }
@@ -434,6 +437,8 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
                 }
             }
             __syncthreads();
+            unsigned long long tg = 0;
+            if (tid == 0) tg = wall_clock64();
             const int n = s_cnt[cb];
             if (n == 0) break;
             // the other counter was last read before the previous barrier and is
@@ -452,19 +457,22 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
                 const double r = update(ax, ay, az, q, q * q, tc, ch);
                 if (ch) {
                     sT[L] = r;
+                    // only neighbours above the new value can depend on it
+                    // (the operator is causal), so only they need another look
                     uint8_t* nd = sDirty[cb ^ 1];
-                    if (lx > 0) nd[p - 1] = 1;
-                    if (lx < TX - 1) nd[p + 1] = 1;
-                    if (ly > 0) nd[p - TX] = 1;
-                    if (ly < TY - 1) nd[p + TX] = 1;
+                    if (lx > 0 && sT[L - 1] > r) nd[p - 1] = 1;
+                    if (lx < TX - 1 && sT[L + 1] > r) nd[p + 1] = 1;
+                    if (ly > 0 && sT[L - C::SY] > r) nd[p - TX] = 1;
+                    if (ly < TY - 1 && sT[L + C::SY] > r) nd[p + TX] = 1;
                     if (C::D3) {
-                        if (lz > 0) nd[p - TX * TY] = 1;
-                        if (lz < TZ - 1) nd[p + TX * TY] = 1;
+                        if (lz > 0 && sT[L - C::SZ] > r) nd[p - TX * TY] = 1;
+                        if (lz < TZ - 1 && sT[L + C::SZ] > r) nd[p + TX * TY] = 1;
                     }
                 }
             }
             ++passes;
             __syncthreads();
+            if (tid == 0) ph[5] += wall_clock64() - tg;
             cb ^= 1;
             if (passes > (1 << 20)) {
                 if (tid == 0) set_flag(S, kFlagWatchdog);
@@ -515,7 +523,7 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
         __syncthreads();
 
         // ---- publish: V bit, activate neighbours, end the run --------------
-        if (tid < 64) publish(S, A.tkey, (uint32_t)tile, !visited, s_nb, s_nid, s_face);
+        if (tid < 64) publish(S, A.tkey, (uint32_t)tile, s_bucket, !visited, s_nb, s_nid, s_face);
         if (tid == 0) {
             my_updates += s_upd;
             my_passes += (unsigned long long)passes;
@@ -529,6 +537,8 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
         ph[0] += wall_clock64() - tm;
         for (int i = 0; i < 4; ++i)
             __hip_atomic_fetch_add(S.counters + 5 + i, ph[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(S.counters + 9, ph[5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(S.counters + 10, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(S.counters + 0, my_visits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(S.counters + 1, my_updates, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(S.counters + 2, my_passes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

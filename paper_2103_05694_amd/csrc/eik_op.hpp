@@ -12,11 +12,10 @@
 // S is non-decreasing in r and non-increasing in each a_k even in floating
 // point, so the result is monotone and causal (Theorem 1 applies verbatim).
 //
-// Evaluation: a closed-form guess in the upwind-shifted variables, then exact
-// one-ulp steps of the predicate on the integer image of positive doubles (which
-// orders them), with a bisection fallback.  The guess only changes how many
-// predicate evaluations are needed; the returned value is fixed by the
-// predicate.  Compile with -ffp-contract=off: every operation in the predicate
+// Evaluation: a closed-form guess in the upwind-shifted variables, then the
+// predicate on the integer image of positive doubles (which orders them) at the
+// guess and its neighbours, with a serial search as fallback.  The guess only
+// changes how much work is needed; the returned value is fixed by the predicate.  Compile with -ffp-contract=off: every operation in the predicate
 // is a separately rounded binary64 operation.
 #pragma once
 
@@ -54,48 +53,29 @@ __device__ __forceinline__ void sort3(double& a0, double& a1, double& a2) {
 }
 
 // Closed-form Godunov estimate from sorted minima (u = r - a0 solves the one-,
-// two- or three-term quadratic).  Accuracy only affects the step count below.
+// two- or three-term quadratic), computed without branches so all three
+// candidates overlap; infinities select the right candidate (fmax drops NaN).
+// Accuracy only affects how often the exact search below needs its fallback.
 __device__ __forceinline__ double guess(double a0, double a1, double a2, double q, double c) {
-    double r = a0 + q;
-    if (r > a1) {
-        double b1 = a1 - a0;
-        double disc = fmax(c + c - b1 * b1, 0.0);
-        r = a0 + 0.5 * (b1 + __builtin_sqrt(disc));
-        if (r > a2) {
-            double b2 = a2 - a0;
-            double sb = b1 + b2;
-            double disc3 = fmax(sb * sb - 3.0 * (b1 * b1 + b2 * b2 - c), 0.0);
-            r = a0 + (sb + __builtin_sqrt(disc3)) * (1.0 / 3.0);
-        }
-    }
-    return r;
+    const double r1 = a0 + q;
+    const double b1 = a1 - a0;
+    const double d2 = fmax(c + c - b1 * b1, 0.0);
+    const double r2 = a0 + 0.5 * (b1 + __builtin_sqrt(d2));
+    const double b2 = a2 - a0;
+    const double sb = b1 + b2;
+    const double d3 = fmax(sb * sb - 3.0 * (b1 * b1 + b2 * b2 - c), 0.0);
+    const double r3 = a0 + (sb + __builtin_sqrt(d3)) * (1.0 / 3.0);
+    return r1 <= a1 ? r1 : (r2 <= a2 ? r2 : r3);
 }
 
-// The exact operator.  Returns the new value if it is < tcur, else tcur.
-// Preconditions: q > 0, c = fl(q*q) in (0, inf), tcur >= 0 (may be +inf).
-// `x`, `y`, `z` are the axis minima in any order (+inf where absent).
-__device__ __forceinline__ double update(double x, double y, double z, double q, double c,
-                                         double tcur, bool& changed) {
-    changed = false;
-    double a0 = x, a1 = y, a2 = z;
-    sort3(a0, a1, a2);
-    if (!(a0 < tcur)) return tcur;                 // result > a0 >= tcur: nothing to do
-    // r < tcur  <=>  S(prev(tcur)) >= c  (S is monotone): one predicate
-    // evaluation rejects every non-improving ("empty") update.
-    const uint64_t tcb = as_u64(tcur);
-    if (!reaches(as_f64(tcb - 1), a0, a1, a2, c)) return tcur;
-
-    const uint64_t A0 = as_u64(a0);                // reaches(a0) is false (all d <= 0)
-    double g = guess(a0, a1, a2, q, c);
-    uint64_t G = as_u64(g);
-    if (!(g > a0)) G = A0 + 1;
-    if (G >= tcb) G = tcb - 1;                      // reaches(tcb - 1) holds
+// Serial search kept for the rare inputs whose guess is more than one ulp off:
+// unit steps from G, then bisection (reaches(L) false, reaches(H) true).
+__device__ __noinline__ double search_slow(double a0, double a1, double a2, double c, uint64_t A0,
+                                           uint64_t G, uint64_t tcb) {
     uint64_t L, H;
     bool ok = false;
     if (reaches(as_f64(G), a0, a1, a2, c)) {
         H = G;
-        // walk down while the predecessor still satisfies the predicate
-#pragma unroll 1
         for (int i = 0; i < 4; ++i) {
             uint64_t P = H - 1;
             if (P == A0 || !reaches(as_f64(P), a0, a1, a2, c)) { ok = true; break; }
@@ -105,7 +85,6 @@ __device__ __forceinline__ double update(double x, double y, double z, double q,
     } else {
         L = G;
         H = tcb - 1;
-#pragma unroll 1
         for (int i = 0; i < 4; ++i) {
             uint64_t N = L + 1;
             if (reaches(as_f64(N), a0, a1, a2, c)) { H = N; ok = true; break; }
@@ -113,13 +92,48 @@ __device__ __forceinline__ double update(double x, double y, double z, double q,
         }
     }
     if (!ok) {
-        // Bisection keeps reaches(L) false and reaches(H) true.
-#pragma unroll 1
         while (H - L > 1) {
             uint64_t M = L + ((H - L) >> 1);
             if (reaches(as_f64(M), a0, a1, a2, c)) H = M; else L = M;
         }
     }
+    return as_f64(H);
+}
+
+// The exact operator.  Returns the new value if it is < tcur, else tcur.
+// Preconditions: q > 0, c = fl(q*q) in (0, inf), tcur >= 0 (may be +inf).
+// `x`, `y`, `z` are the axis minima in any order (+inf where absent).
+//
+// First r < tcur  <=>  S(prev(tcur)) >= c (S is monotone), so one predicate
+// rejects every non-improving update.  Then four independent predicate
+// evaluations run side by side at G-2 .. G+1 around the guess G; the answer is
+// the first of G-1, G, G+1 that satisfies the predicate when the one below it
+// does not (reaches(a0) is always false).  Otherwise the serial search decides.
+__device__ __forceinline__ double update(double x, double y, double z, double q, double c,
+                                         double tcur, bool& changed) {
+    changed = false;
+    double a0 = x, a1 = y, a2 = z;
+    sort3(a0, a1, a2);
+    if (!(a0 < tcur)) return tcur;                 // result > a0 >= tcur: nothing to do
+    const uint64_t tcb = as_u64(tcur);
+    // most evaluations in a relaxation do not improve the point: one predicate
+    // rejects them before the guess is computed
+    if (!reaches(as_f64(tcb - 1), a0, a1, a2, c)) return tcur;
+    const uint64_t A0 = as_u64(a0);
+    // reaches(tcb - 1) is false whenever tcb - 1 <= A0, so here G ends up in
+    // [A0 + 1, tcb - 1]
+    uint64_t G = as_u64(guess(a0, a1, a2, q, c));
+    if (!(G >= A0 + 2)) G = A0 + 2;                // also catches a NaN pattern
+    if (G > tcb - 1) G = tcb - 1;
+    const bool pm2 = (G >= A0 + 3) && reaches(as_f64(G - 2), a0, a1, a2, c);
+    const bool pm = (G >= A0 + 2) && reaches(as_f64(G - 1), a0, a1, a2, c);
+    const bool p0 = reaches(as_f64(G), a0, a1, a2, c);
+    const bool pp = reaches(as_f64(G + 1), a0, a1, a2, c);
+    uint64_t H;
+    if (pm && !pm2) H = G - 1;
+    else if (p0 && !pm) H = G;
+    else if (pp && !p0) H = G + 1;
+    else return (changed = true, search_slow(a0, a1, a2, c, A0, G, tcb));
     changed = true;
     return as_f64(H);
 }

@@ -8,10 +8,16 @@
 //
 //  * a tile pushed with time t goes to bucket k = floor(t / delta), clamped to
 //    the window [cur, cur + NB); ring k mod NB holds it;
-//  * a claimer scans the NB rings from `cur` (one lane per ring, one ballot)
-//    and takes from the first non-empty one, advancing `cur` past empty rings;
-//  * inversions are allowed (late pushes below `cur`, clamped far pushes):
-//    the operator is monotone and causal, so the order never changes results.
+//  * a claimer takes work only from the current bucket `cur`; `cur` moves on
+//    (to the next non-empty bucket) only once bucket `cur` is drained: nothing
+//    queued in it and no tile claimed from it still running.  This is the
+//    bucket discipline of delta-stepping: within a bucket any order and any
+//    degree of parallelism, across buckets increasing time, so the number of
+//    premature (later lowered again) tile runs stays small;
+//  * pushes happen only from tiles running in bucket `cur` (or before the
+//    solve starts), so `cur` cannot move while a push computes its ring;
+//  * delta = 0 puts everything in one bucket (a plain FIFO worklist);
+//  * the operator is monotone and causal, so none of this changes results.
 //
 // Each ring is a bounded MPMC array of 64-bit cells (sequence << 32 | tile),
 // positions taken with fetch-add.  A cell for position p is free when its
@@ -59,14 +65,17 @@ __device__ __forceinline__ void stores_done() { asm volatile("s_waitcnt vmcnt(0)
 
 constexpr uint32_t kQ = 1u, kR = 2u, kV = 4u, kS = 8u;
 constexpr int kMaxRings = 64;
-constexpr int kCtrStride = 32;  // uint32 words between ring counters (128 B)
+// Each ring counter (head, tail, count, running) lives in its own 256-byte
+// line, so polling one does not slow the atomics on the others.
+constexpr int kCtrPad = 64;                 // uint32 words per counter line
+constexpr int kCtrStride = 4 * kCtrPad;     // uint32 words per ring
 
 // device status flags
 constexpr uint32_t kFlagDomain = 1u, kFlagLimit = 2u, kFlagBadSrc = 4u, kFlagWatchdog = 8u;
 
 struct Sched {
     uint64_t* items;     // [nrings][cap]
-    uint32_t* ctr;       // per ring r: ctr[r*kCtrStride + {0 head, 1 tail, 2 count}]
+    uint32_t* ctr;       // ring counters, see ring_head / ring_tail / ring_count / ring_run
     uint32_t* tstate;    // [ntiles]
     int32_t* cur;        // lowest bucket of the window
     int32_t* pending;    // tiles queued or running
@@ -77,7 +86,13 @@ struct Sched {
     uint32_t cap_mask;
     double inv_delta;    // 1/delta, 0 => single bucket
     long long max_visits;  // 0 => unlimited
+    int lookahead;       // claims may come from buckets cur .. cur + lookahead
 };
+
+__device__ __forceinline__ uint32_t* ring_head(const Sched& s, int r) { return s.ctr + r * kCtrStride; }
+__device__ __forceinline__ uint32_t* ring_tail(const Sched& s, int r) { return s.ctr + r * kCtrStride + kCtrPad; }
+__device__ __forceinline__ uint32_t* ring_count(const Sched& s, int r) { return s.ctr + r * kCtrStride + 2 * kCtrPad; }
+__device__ __forceinline__ uint32_t* ring_run(const Sched& s, int r) { return s.ctr + r * kCtrStride + 3 * kCtrPad; }
 
 __device__ __forceinline__ uint32_t ld_acq(uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -103,15 +118,16 @@ __device__ __forceinline__ int64_t bucket_of(const Sched& s, double t) {
 }
 
 // Enqueue `tile` with time key `t`.  The caller has already counted it in
-// `pending`.  Single lane.
-__device__ __forceinline__ void push_tile(const Sched& s, uint32_t tile, double t) {
+// `pending`.  `base` is the bucket the pushing run was claimed from (0 before
+// the solve starts): `cur` cannot pass it while that run is live and is at least
+// base - lookahead, so buckets in [base, base + nrings - 1 - lookahead] never
+// alias a bucket behind `cur`.  Single lane.
+__device__ __forceinline__ void push_tile(const Sched& s, uint32_t tile, double t, int64_t base) {
     int64_t k = bucket_of(s, t);
-    int64_t c = ld_rlx(s.cur);
-    if (k < c) k = c;
-    if (k > c + s.nrings - 1) k = c + s.nrings - 1;
+    if (k < base) k = base;
+    if (k > base + s.nrings - 1 - s.lookahead) k = base + s.nrings - 1 - s.lookahead;
     int r = (int)(k % s.nrings);
-    uint32_t* ctr = s.ctr + r * kCtrStride;
-    uint32_t pos = __hip_atomic_fetch_add(ctr + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t pos = __hip_atomic_fetch_add(ring_tail(s, r), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint64_t* cell = s.items + (size_t)r * (s.cap_mask + 1) + (pos & s.cap_mask);
     // wait until the previous lap's consumer has read this cell (bounded: that
     // consumer has already claimed it)
@@ -126,34 +142,25 @@ __device__ __forceinline__ void push_tile(const Sched& s, uint32_t tile, double 
     }
     __hip_atomic_store(cell, ((uint64_t)(pos + 1u) << 32) | tile, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     stores_done();
-    __hip_atomic_fetch_add(ctr + 2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(ring_count(s, r), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Count a newly activated tile and enqueue it.  Single lane.
-__device__ __forceinline__ void activate_push(const Sched& s, uint32_t tile, double t) {
+__device__ __forceinline__ void activate_push(const Sched& s, uint32_t tile, double t, int64_t base) {
     __hip_atomic_fetch_add(s.pending, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    push_tile(s, tile, t);
-}
-
-// Mark `tile` as needing a run because data it reads changed (the caller has
-// issued an agent-scope release fence after those writes).  Single lane.
-__device__ __forceinline__ void activate(const Sched& s, uint32_t tile, double t) {
-    uint32_t old = __hip_atomic_fetch_or(s.tstate + tile, kQ, __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
-    if ((old & (kQ | kR)) == 0) activate_push(s, tile, t);
+    push_tile(s, tile, t, base);
 }
 
 // Try to take one item from ring r.  Returns the tile, -1 (empty) or -2
 // (watchdog).  Single lane.
 __device__ __forceinline__ int try_claim(const Sched& s, int r) {
-    uint32_t* ctr = s.ctr + r * kCtrStride;
-    int32_t old = (int32_t)__hip_atomic_fetch_sub(ctr + 2, 1u, __ATOMIC_RELAXED,
+    int32_t old = (int32_t)__hip_atomic_fetch_sub(ring_count(s, r), 1u, __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_AGENT);
     if (old <= 0) {
-        __hip_atomic_fetch_add(ctr + 2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(ring_count(s, r), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return -1;
     }
-    uint32_t pos = __hip_atomic_fetch_add(ctr + 0, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t pos = __hip_atomic_fetch_add(ring_head(s, r), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint64_t* cell = s.items + (size_t)r * (s.cap_mask + 1) + (pos & s.cap_mask);
     // The producer that reserved this position is about to fill the cell.
     for (long long spin = 0;; ++spin) {
@@ -172,35 +179,79 @@ __device__ __forceinline__ int try_claim(const Sched& s, int r) {
     }
 }
 
-// Called by all 64 lanes of one wave.  Returns a tile, or -1 when no work is
-// left anywhere (pending == 0), or -2 on a watchdog expiry.
-__device__ __forceinline__ int claim(const Sched& s) {
+// Idle back-off: s_sleep takes an immediate, so sleep in units of 127.
+__device__ __forceinline__ void idle_sleep(int units) {
+    for (int i = 0; i < units; ++i) __builtin_amdgcn_s_sleep(127);
+}
+
+// Called by all 64 lanes of one wave.  Returns a tile and the bucket it came
+// from (*bucket), or -1 when no work is left anywhere (pending == 0), or -2 on
+// a watchdog expiry.
+__device__ __forceinline__ int claim(const Sched& s, int64_t* bucket) {
     const int lane = threadIdx.x & 63;
+    const int win = s.lookahead + 1;
     long long idle = 0;
     for (;;) {
-        int32_t c = ld_rlx(s.cur);
-        int r = lane < s.nrings ? (int)(((int64_t)c + lane) % s.nrings) : 0;
-        int32_t cnt = lane < s.nrings ? (int32_t)ld_rlx(s.ctr + r * kCtrStride + 2) : 0;
-        unsigned long long mask = __ballot(cnt > 0);
-        while (mask) {
-            int j = __ffsll((long long)mask) - 1;
-            mask &= mask - 1;
+        const int32_t c = ld_rlx(s.cur);
+        const int r = (int)(((int64_t)c + lane) % s.nrings);
+        // running count first, then queued count: a finishing run increments the
+        // counts of its pushes before it decrements its running count, so a
+        // bucket seen with nothing running and nothing queued really is drained
+        int32_t cnt = 0, run = 0;
+        if (lane == 0) run = (int32_t)ld_rlx(ring_run(s, r));
+        stores_done();
+        if (lane < win) cnt = (int32_t)ld_rlx(ring_count(s, r));
+        const unsigned long long mask = __ballot(cnt > 0);
+        if (mask) {
+            // lowest bucket of the window with queued work; count ourselves as
+            // running there first, so it cannot look drained while we hold a claim
+            const int j = __ffsll((long long)mask) - 1;
+            const int rj = (int)(((int64_t)c + j) % s.nrings);
             int got = -1;
             if (lane == 0) {
-                got = try_claim(s, (int)(((int64_t)c + j) % s.nrings));
-                if (got >= 0 && j > 0)
-                    __hip_atomic_fetch_max(s.cur, c + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                uint32_t* rc = ring_run(s, rj);
+                __hip_atomic_fetch_add(rc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                stores_done();
+                got = try_claim(s, rj);
+                if (got < 0) __hip_atomic_fetch_sub(rc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             got = __shfl(got, 0);
-            if (got >= 0 || got == -2) return got;
+            if (got >= 0) {
+                *bucket = (int64_t)c + j;
+                return got;
+            }
+            if (got == -2) return -2;
+            continue;
         }
-        if (ld_rlx(s.pending) <= 0) return -1;
-        if (++idle > (1ll << 21)) {
+        const int run0 = __shfl(run, 0);
+        if (run0 <= 0) {
+            // bucket `cur` drained: find the next non-empty bucket (full scan)
+            int32_t cf = 0;
+            if (lane < s.nrings) cf = (int32_t)ld_rlx(ring_count(s, r));
+            const unsigned long long m2 = __ballot(cf > 0) & ~1ull;
+            if (m2) {
+                const int j = __ffsll((long long)m2) - 1;
+                if (lane == 0) {
+                    int32_t expect = c;
+                    if (__hip_atomic_compare_exchange_strong(s.cur, &expect, c + j, __ATOMIC_RELAXED,
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                        __hip_atomic_fetch_add(s.counters + 11, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                continue;
+            }
+            if (ld_rlx(s.pending) <= 0) return -1;
+        }
+        ++idle;
+        if (idle > (1ll << 19)) {
             if (lane == 0) set_flag(s, kFlagWatchdog);
             return -2;
         }
-        if (idle < 8) __builtin_amdgcn_s_sleep(2);
-        else __builtin_amdgcn_s_sleep(20);
+        // exponential back-off, ~0.1 us doubling up to ~25 us, keeps idle
+        // workgroups from flooding the counters the busy ones need
+        if (idle < 2) __builtin_amdgcn_s_sleep(4);
+        else if (idle < 3) __builtin_amdgcn_s_sleep(16);
+        else if (idle < 4) __builtin_amdgcn_s_sleep(64);
+        else idle_sleep(idle < 5 ? 1 : (idle < 6 ? 2 : (idle < 7 ? 4 : 8)));
     }
 }
 
@@ -213,7 +264,7 @@ __device__ __forceinline__ int claim(const Sched& s) {
 // Lanes 0..5 activate the neighbours in parallel; the block's pending count
 // changes once, by (#newly queued neighbours + requeue - 1), before any push
 // makes the new items claimable, so it never under-counts live work.
-__device__ __forceinline__ void publish(const Sched& s, uint64_t* tkey, uint32_t tile, bool first,
+__device__ __forceinline__ void publish(const Sched& s, uint64_t* tkey, uint32_t tile, int64_t bucket, bool first,
                                         const uint32_t* nb, const uint32_t* nid,
                                         const unsigned long long* face) {
     const int lane = threadIdx.x & 63;
@@ -261,12 +312,17 @@ __device__ __forceinline__ void publish(const Sched& s, uint64_t* tkey, uint32_t
         if (delta != 0)
             __hip_atomic_fetch_add(s.pending, delta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (want) push_tile(s, n, as_f64(fk));
-    if (lane == 0 && requeue) push_tile(s, tile, rkey);
+    if (want) push_tile(s, n, as_f64(fk), bucket);
+    if (lane == 0 && requeue) push_tile(s, tile, rkey, bucket);
+    // this run's own pushes are queued: the bucket it came from may now drain
+    stores_done();
+    if (lane == 0)
+        __hip_atomic_fetch_sub(ring_run(s, (int)(bucket % s.nrings)), 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Drop a claimed tile without running it (visit cap reached).  Lane 0.
-__device__ __forceinline__ void drop_run(const Sched& s, uint32_t tile) {
+__device__ __forceinline__ void drop_run(const Sched& s, uint32_t tile, int64_t bucket) {
     uint32_t* w = s.tstate + tile;
     uint32_t old = ld_rlx(w);
     for (;;) {
@@ -276,8 +332,11 @@ __device__ __forceinline__ void drop_run(const Sched& s, uint32_t tile) {
             break;
         old = seen;
     }
-    if (old & kQ) push_tile(s, tile, 0.0);
+    if (old & kQ) push_tile(s, tile, 0.0, bucket);
     else __hip_atomic_fetch_sub(s.pending, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    stores_done();
+    __hip_atomic_fetch_sub(ring_run(s, (int)(bucket % s.nrings)), 1u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace eik

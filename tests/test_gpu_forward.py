@@ -78,15 +78,50 @@ def ragged_cases():
 CASES = ragged_cases()
 
 
+@pytest.fixture(scope="module")
+def layered_small():
+    return W.layered_3d(96, 80, 48, h=10.0, seed=2)
+
+
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_ragged_and_degenerate_shapes(gpu, O, case):
     name, f, h, src, t0 = case
     ref = O.fmm(f, h, src, t0)
     tiles = TILES_2D if f.shape[0] == 1 else TILES_3D
     for tile in tiles:
-        for delta in (0.0, 0.5):
-            t = gpu_solve(gpu, f, h, src, t0, tile=tile, delta=delta)
-            assert_bitwise(t, ref, f"{name} tile {tile} delta {delta}")
+        for delta, la in ((0.0, 0), (0.5, 0), (0.25, 3)):
+            t = gpu_solve(gpu, f, h, src, t0, tile=tile, delta=delta, lookahead=la)
+            assert_bitwise(t, ref, f"{name} tile {tile} delta {delta} lookahead {la}")
+
+
+WTILES_3D = [(8, 8, 4), (16, 8, 4), (8, 8, 8), (16, 4, 4)]
+WTILES_2D = [(16, 16), (32, 16), (32, 8)]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_wave_tiles_ragged(gpu, O, case):
+    name, f, h, src, t0 = case
+    ref = O.fmm(f, h, src, t0)
+    tiles = WTILES_2D if f.shape[0] == 1 else WTILES_3D
+    for tile in tiles:
+        for delta, la in ((0.0, 0), (0.5, 0), (0.25, 2)):
+            t = gpu_solve(gpu, f, h, src, t0, tile=tile, delta=delta, lookahead=la, wave_tiles=True)
+            assert_bitwise(t, ref, f"{name} wave tile {tile} delta {delta} lookahead {la}")
+
+
+def test_wave_tiles_scaled_workloads(gpu, O, layered_small):
+    p = layered_small
+    ref = O.fmm(p.field, p.h, p.src)
+    for tile in WTILES_3D:
+        for delta, la in ((0.0, 0), (0.02, 0), (0.01, 2)):
+            t = gpu_solve(gpu, p.field, p.h, p.src, tile=tile, delta=delta, lookahead=la, wave_tiles=True)
+            assert_bitwise(t, ref, f"layered wave tile {tile} delta {delta}")
+    q = W.blocky_2d(n=512, nsrc=16, seed=3, block=16)
+    ref = O.fmm(q.field, q.h, q.src)
+    for tile in WTILES_2D:
+        for delta, la in ((0.0, 0), (4.0, 0), (2.0, 4)):
+            t = gpu_solve(gpu, q.field, q.h, q.src, tile=tile, delta=delta, lookahead=la, wave_tiles=True)
+            assert_bitwise(t, ref, f"blocky wave tile {tile} delta {delta}")
 
 
 def test_slowness_field(gpu, O):
@@ -98,27 +133,22 @@ def test_slowness_field(gpu, O):
     assert_bitwise(t, ref, "slowness")
 
 
-@pytest.fixture(scope="module")
-def layered_small():
-    return W.layered_3d(96, 80, 48, h=10.0, seed=2)
-
-
 @pytest.mark.parametrize("tile", TILES_3D)
 def test_layered_3d_scaled(gpu, O, layered_small, tile):
     p = layered_small
     ref = O.fmm(p.field, p.h, p.src)
-    for delta in (0.0, 0.02, 0.2):
-        t = gpu_solve(gpu, p.field, p.h, p.src, tile=tile, delta=delta)
-        assert_bitwise(t, ref, f"layered tile {tile} delta {delta}")
+    for delta, la in ((0.0, 0), (0.02, 0), (0.02, 2), (0.2, 1), (0.005, 8)):
+        t = gpu_solve(gpu, p.field, p.h, p.src, tile=tile, delta=delta, lookahead=la)
+        assert_bitwise(t, ref, f"layered tile {tile} delta {delta} lookahead {la}")
 
 
 @pytest.mark.parametrize("tile", TILES_2D)
 def test_blocky_2d_scaled(gpu, O, tile):
     p = W.blocky_2d(n=512, nsrc=16, seed=3, block=16)
     ref = O.fmm(p.field, p.h, p.src)
-    for delta in (0.0, 4.0, 64.0):
-        t = gpu_solve(gpu, p.field, p.h, p.src, tile=tile, delta=delta)
-        assert_bitwise(t, ref, f"blocky tile {tile} delta {delta}")
+    for delta, la in ((0.0, 0), (4.0, 0), (4.0, 4), (64.0, 1)):
+        t = gpu_solve(gpu, p.field, p.h, p.src, tile=tile, delta=delta, lookahead=la)
+        assert_bitwise(t, ref, f"blocky tile {tile} delta {delta} lookahead {la}")
 
 
 def test_run_to_run_determinism(gpu, O, layered_small):
