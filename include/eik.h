@@ -59,6 +59,8 @@ extern "C" {
 #define EIK_FLAG_TIME_KERNELS 1u  /* eik_opts.flags: time the persistent kernel with HIP events */
 #define EIK_FLAG_WAVE_TILES 2u    /* eik_opts.flags: forward solve with one tile per wave (tiles
                                      3D 8x8x4, 16x8x4, 8x8x8, 16x4x4; 2D 16x16, 32x16, 32x8) */
+#define EIK_FLAG_TIMELINE 4u      /* eik_opts.flags: record when the lowest open priority bucket
+                                     moves on (read back with eik_timeline) */
 
 #define EIK_SPEED 0       /* field holds speed v:    q = h / v */
 #define EIK_SLOWNESS 1    /* field holds slowness s: q = h * s */
@@ -99,6 +101,7 @@ typedef struct {
     double process_us;       /* part of phase_us[2] spent applying the operator to the pass lists */
     int64_t workgroups;      /* persistent workgroups of the last forward launch */
     int64_t bucket_advances; /* times the lowest open priority bucket moved on */
+    int64_t handoffs;        /* runs that started on a neighbour handed on by the previous run */
 } eik_stats;
 
 /* Forward solve.
@@ -178,6 +181,16 @@ int64_t eik_num_tiles(const eik_grid* g, const eik_opts* opts);
 /* Synchronises `stream`, copies the device status of the last call on it into
  * *out_host (may be NULL) and returns its EIK_* code. */
 int eik_status(void* stream, eik_stats* out_host);
+
+/* Schedule record of the last persistent launch on `stream` that ran with
+ * EIK_FLAG_TIMELINE (the soft-priority bucket order of the section "The
+ * Asynchronous Marching Method"): synchronises `stream`, writes for the first
+ * min(cap, n) bucket advances the time since the launch's reset (t_us_host,
+ * microseconds) and the bucket the window moved to (bucket_host), and the time
+ * from reset to the last workgroup's exit (*span_us_host, may be NULL).
+ * Returns n, the number of advances (the record holds at most 65536), or a
+ * negative EIK_* code. */
+int eik_timeline(void* stream, int32_t cap, double* t_us_host, int64_t* bucket_host, double* span_us_host);
 
 const char* eik_strerror(int code);
 const char* eik_last_error(void);

@@ -25,11 +25,12 @@ EIK_SPEED = 0
 EIK_SLOWNESS = 1
 EIK_FLAG_TIME_KERNELS = 1
 EIK_FLAG_WAVE_TILES = 2
+EIK_FLAG_TIMELINE = 4
 
 EXPORTED = (
     "eik_solve", "eik_parents", "eik_adjoint", "eik_solve_batched", "eik_adjoint_batched",
     "eik_reserve", "eik_num_tiles", "eik_status", "eik_strerror", "eik_last_error",
-    "eik_release", "eik_version",
+    "eik_release", "eik_version", "eik_timeline",
 )
 
 
@@ -50,7 +51,8 @@ class eik_stats(ctypes.Structure):
                 ("flags", ctypes.c_uint32), ("status", ctypes.c_int32),
                 ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_int64),
                 ("phase_us", ctypes.c_double * 4), ("process_us", ctypes.c_double),
-                ("workgroups", ctypes.c_int64), ("bucket_advances", ctypes.c_int64)]
+                ("workgroups", ctypes.c_int64), ("bucket_advances", ctypes.c_int64),
+                ("handoffs", ctypes.c_int64)]
 
 
 class EikError(RuntimeError):
@@ -95,6 +97,8 @@ def load() -> ctypes.CDLL:
     L.eik_num_tiles.argtypes = [_gp, _op]
     L.eik_status.restype = _i32
     L.eik_status.argtypes = [_vp, ctypes.POINTER(eik_stats)]
+    L.eik_timeline.restype = _i32
+    L.eik_timeline.argtypes = [_vp, _i32, _vp, _vp, _vp]
     L.eik_strerror.restype = ctypes.c_char_p
     L.eik_strerror.argtypes = [_i32]
     L.eik_last_error.restype = ctypes.c_char_p

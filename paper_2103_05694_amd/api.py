@@ -39,7 +39,7 @@ def _grid_of(shape: Sequence[int], h: float, kind: str) -> eik_grid:
 
 def make_opts(delta: float = 0.0, tile: Optional[Sequence[int]] = None, grid_blocks: int = 0,
               max_tile_visits: int = 0, time_kernels: bool = False, lookahead: int = 0,
-              wave_tiles: bool = False) -> eik_opts:
+              wave_tiles: bool = False, timeline: bool = False) -> eik_opts:
     o = eik_opts()
     o.delta = float(delta)
     t = tuple(tile) if tile else (0, 0, 0)
@@ -50,7 +50,7 @@ def make_opts(delta: float = 0.0, tile: Optional[Sequence[int]] = None, grid_blo
     o.grid_blocks = int(grid_blocks)
     o.max_tile_visits = int(max_tile_visits)
     o.flags = (_lib.EIK_FLAG_TIME_KERNELS if time_kernels else 0) | \
-        (_lib.EIK_FLAG_WAVE_TILES if wave_tiles else 0)
+        (_lib.EIK_FLAG_WAVE_TILES if wave_tiles else 0) | (_lib.EIK_FLAG_TIMELINE if timeline else 0)
     o.lookahead = int(lookahead)
     return o
 
@@ -101,12 +101,27 @@ def status(stream=None, raise_on_error: bool = True) -> eik_stats:
     return st
 
 
+def timeline(stream=None, cap: int = 1 << 16):
+    """Bucket advances of the last launch run with timeline=True: (times in us
+    since its reset, bucket moved to, span in us of the whole launch)."""
+    import numpy as np
+    L = _lib.load()
+    t = np.zeros(cap, dtype=np.float64)
+    b = np.zeros(cap, dtype=np.int64)
+    span = np.zeros(1, dtype=np.float64)
+    n = L.eik_timeline(ctypes.c_void_p(_stream_handle(stream)), cap, t.ctypes.data, b.ctypes.data,
+                       span.ctypes.data)
+    check(n if n < 0 else 0)
+    m = min(n, cap)
+    return t[:m].copy(), b[:m].copy(), float(span[0])
+
+
 def solve(field: torch.Tensor, h: float, sources, t0: Optional[torch.Tensor] = None,
           kind: str = "speed", parents: bool = False, delta: float = 0.0,
           tile: Optional[Sequence[int]] = None, grid_blocks: int = 0, max_tile_visits: int = 0,
           out: Optional[torch.Tensor] = None, parents_out: Optional[torch.Tensor] = None,
           check_status: bool = True, stream=None, time_kernels: bool = False, lookahead: int = 0,
-          wave_tiles: bool = False):
+          wave_tiles: bool = False, timeline: bool = False):
     """First-arrival times; returns t, or (t, parents) when parents=True.  `wave_tiles`
     selects the one-tile-per-wave solver (tile shapes 3D 8x8x4, 16x8x4, 8x8x8,
     16x4x4; 2D 16x16, 32x16, 32x8)."""
@@ -124,7 +139,7 @@ def solve(field: torch.Tensor, h: float, sources, t0: Optional[torch.Tensor] = N
     if parents:
         par = parents_out if parents_out is not None else torch.empty(field.shape, dtype=torch.uint8,
                                                                        device=field.device)
-    o = make_opts(delta, tile, grid_blocks, max_tile_visits, time_kernels, lookahead, wave_tiles)
+    o = make_opts(delta, tile, grid_blocks, max_tile_visits, time_kernels, lookahead, wave_tiles, timeline)
     rc = L.eik_solve(ctypes.byref(g), field.data_ptr(), src.numel(), src.data_ptr(),
                      t0d.data_ptr() if t0d is not None else None, t.data_ptr(),
                      par.data_ptr() if par is not None else None, ctypes.byref(o),

@@ -36,6 +36,7 @@ int fail(int code, const std::string& msg) {
 constexpr int kThreads = 256;
 constexpr int kRings = 32;
 constexpr int kScalWords = 192;
+constexpr int kTimelineCap = 1 << 16;
 constexpr int kSCur = 0, kSPending = 64, kSFlags = 128, kSPoisoned = 129, kSSrcCount = 130;
 
 struct Workspace {
@@ -44,6 +45,7 @@ struct Workspace {
     // scheduler
     uint64_t* items = nullptr;
     uint32_t* ctr = nullptr;
+    unsigned long long* timeline = nullptr;  // bucket advance record (EIK_FLAG_TIMELINE)
     uint32_t* tstate = nullptr;
     uint64_t* tkey = nullptr;
     int64_t tiles_cap = 0;
@@ -129,6 +131,7 @@ int get_ws(hipStream_t st, Workspace** out) {
     hipError_t e = hipMalloc((void**)&w->scal, kScalWords * sizeof(int32_t));
     if (e == hipSuccess) e = hipMalloc((void**)&w->counters, 16 * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMalloc((void**)&w->ctr, sizeof(uint32_t) * kRings * kCtrStride);
+    if (e == hipSuccess) e = hipMalloc((void**)&w->timeline, sizeof(unsigned long long) * (2 + 2 * kTimelineCap));
     if (e != hipSuccess) {
         delete w;
         return fail(EIK_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
@@ -138,6 +141,7 @@ int get_ws(hipStream_t st, Workspace** out) {
     HIP_TRY(hipMemcpy(w->scal, init, sizeof(init), hipMemcpyHostToDevice));
     HIP_TRY(hipMemset(w->ctr, 0, sizeof(uint32_t) * kRings * kCtrStride));
     HIP_TRY(hipMemset(w->counters, 0, 16 * sizeof(unsigned long long)));
+    HIP_TRY(hipMemset(w->timeline, 0, sizeof(unsigned long long) * (2 + 2 * kTimelineCap)));
     g_ws[key] = w;
     *out = w;
     return EIK_OK;
@@ -280,7 +284,8 @@ int check_opts(const eik_opts* o) {
     if (!(o->delta >= 0.0) || std::isnan(o->delta)) return fail(EIK_EINVAL, "delta must be >= 0");
     if (o->grid_blocks < 0) return fail(EIK_EINVAL, "grid_blocks must be >= 0");
     if (o->max_tile_visits < 0) return fail(EIK_EINVAL, "max_tile_visits must be >= 0");
-    if (o->flags & ~(EIK_FLAG_TIME_KERNELS | EIK_FLAG_WAVE_TILES)) return fail(EIK_EINVAL, "unknown flags");
+    if (o->flags & ~(EIK_FLAG_TIME_KERNELS | EIK_FLAG_WAVE_TILES | EIK_FLAG_TIMELINE))
+        return fail(EIK_EINVAL, "unknown flags");
     if (o->lookahead < 0 || o->lookahead > 8) return fail(EIK_EINVAL, "lookahead must be in 0..8");
     return EIK_OK;
 }
@@ -318,6 +323,9 @@ Sched make_sched(Workspace& w, const eik_opts* o) {
     s.inv_delta = (d > 0.0 && std::isfinite(d)) ? 1.0 / d : 0.0;
     s.max_visits = o ? (long long)o->max_tile_visits : 0;
     s.lookahead = o ? o->lookahead : 0;
+    const bool tl = o && (o->flags & EIK_FLAG_TIMELINE);
+    s.timeline = tl ? w.timeline : nullptr;
+    s.timeline_cap = tl ? kTimelineCap : 0;
     return s;
 }
 
@@ -361,7 +369,6 @@ int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int6
     ProbTable T;
     if ((rc = make_table(w, probs, &src_off, &T))) return rc;
     hipStream_t st = w.stream;
-    const int nprob = (int)probs.size();
     Sched s = make_sched(w, o);
     int32_t* srccnt = w.scal + kSSrcCount;
 
@@ -370,8 +377,8 @@ int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int6
                        (long long)kRings * w.ring_cap);
     hipLaunchKernelGGL((k_src_mark<TX, TY, TZ>), dim3(blocks_for(nsrc, kThreads)), dim3(kThreads), 0, st,
                        T, src_idx, src_t0, (long long)nsrc, s, w.srclist, srccnt);
-    hipLaunchKernelGGL((k_src_fill<TX, TY, TZ>), dim3((unsigned)std::min<int64_t>(nsrc, 4096)),
-                       dim3(kThreads), 0, st, T, t, w.srclist, srccnt);
+    hipLaunchKernelGGL(k_fill_inf, dim3(blocks_for(npts_total, kThreads, 8192)), dim3(kThreads), 0, st,
+                       (long long)npts_total, t);
     hipLaunchKernelGGL((k_src_place<TX, TY, TZ>), dim3(blocks_for(nsrc, kThreads)), dim3(kThreads), 0, st,
                        T, src_idx, src_t0, (long long)nsrc, t, s);
     HIP_TRY(hipGetLastError());
@@ -408,9 +415,6 @@ int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int6
                            st, T, (long long)npts_total, (const double*)t, par);
     hipLaunchKernelGGL(k_src_unsign, dim3(blocks_for(nsrc, kThreads)), dim3(kThreads), 0, st, T, src_idx,
                        src_t0, (long long)nsrc, t);
-    if (o && o->max_tile_visits > 0)
-        hipLaunchKernelGGL((k_fill_unvisited<TX, TY, TZ>), dim3((unsigned)std::min<int64_t>(ntiles, 16384)),
-                           dim3(kThreads), 0, st, T, (int)ntiles, t, (const uint32_t*)w.tstate);
     HIP_TRY(hipGetLastError());
     w.last_kind = 1;
     w.last_ntiles = ntiles;
@@ -452,7 +456,6 @@ int adjoint(Workspace& w, const std::vector<Prob>& probs, int64_t ntiles, int64_
     ProbTable T;
     if ((rc = make_table(w, probs, nullptr, &T))) return rc;
     hipStream_t st = w.stream;
-    const int nprob = (int)probs.size();
     Sched s = make_sched(w, o);
     s.max_visits = 0;
     unsigned long long* tref = w.counters + 4;
@@ -685,6 +688,7 @@ int eik_status(void* stream, eik_stats* out) {
         out->process_us = (double)ctr[9] / 100.0;
         out->workgroups = (int64_t)ctr[10];
         out->bucket_advances = (int64_t)ctr[11];
+        out->handoffs = (int64_t)ctr[12];
         if (w->ev_used) {
             double sum = 0.0;
             for (size_t i = 0; i < w->ev_used; ++i) {
@@ -700,6 +704,28 @@ int eik_status(void* stream, eik_stats* out) {
     return code;
 }
 
+int eik_timeline(void* stream, int32_t cap, double* t_us_host, int64_t* bucket_host, double* span_us_host) {
+    if (cap < 0 || (cap > 0 && (!t_us_host || !bucket_host))) return fail(EIK_EINVAL, "bad timeline buffers");
+    Workspace* w = nullptr;
+    int rc;
+    if ((rc = get_ws((hipStream_t)stream, &w))) return rc;
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    unsigned long long ctr[16];
+    HIP_TRY(hipMemcpy(ctr, w->counters, sizeof(ctr), hipMemcpyDeviceToHost));
+    const int64_t n = std::min<int64_t>((int64_t)ctr[11], kTimelineCap);
+    std::vector<unsigned long long> tl((size_t)(2 + 2 * n));
+    HIP_TRY(hipMemcpy(tl.data(), w->timeline, sizeof(unsigned long long) * tl.size(), hipMemcpyDeviceToHost));
+    const unsigned long long t0 = tl[0];
+    if (span_us_host) span_us_host[0] = tl[1] > t0 ? (double)(tl[1] - t0) / 100.0 : 0.0;
+    const int64_t m = std::min<int64_t>(n, cap);
+    for (int64_t i = 0; i < m; ++i) {
+        const unsigned long long ti = tl[2 + 2 * i];
+        t_us_host[i] = ti > t0 ? (double)(ti - t0) / 100.0 : 0.0;
+        bucket_host[i] = (int64_t)tl[3 + 2 * i];
+    }
+    return (int)n;
+}
+
 void eik_release(void) {
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto& kv : g_ws) {
@@ -709,6 +735,7 @@ void eik_release(void) {
         (void)hipStreamSynchronize(w->stream);
         (void)hipFree(w->items);
         (void)hipFree(w->ctr);
+        (void)hipFree(w->timeline);
         (void)hipFree(w->tstate);
         (void)hipFree(w->tkey);
         (void)hipFree(w->scal);

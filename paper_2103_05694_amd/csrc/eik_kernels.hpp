@@ -106,9 +106,15 @@ __global__ void k_reset(Sched s, uint64_t* tkey, int ntiles, int32_t* srclist_co
         // cell i of every ring starts free for position i (lap 0)
         const long long cap = (long long)s.cap_mask + 1;
         for (long long i = i0; i < ring_words; i += stride) s.items[i] = (uint64_t)(i % cap) << 32;
-        for (long long i = i0; i < (long long)s.nrings * kCtrStride; i += stride) s.ctr[i] = 0u;
+        // head = tail = 0; count word = bias (0 queued, 0 running)
+        for (long long i = i0; i < (long long)s.nrings * kCtrStride; i += stride)
+            s.ctr[i] = (i % kCtrStride) == kCrWord ? (uint32_t)kCountBias : 0u;
     }
     if (i0 == 0) {
+        if (s.timeline) {
+            s.timeline[0] = wall_clock64();
+            s.timeline[1] = 0ull;
+        }
         *s.cur = 0;
         *s.pending = 0;
         *s.flags = 0u;
@@ -150,22 +156,12 @@ __global__ void k_src_mark(ProbTable T, const int64_t* src_idx, const double* sr
     }
 }
 
-// Fills every listed source tile with +inf (blocks stride over the list).
-template <int TX, int TY, int TZ>
-__global__ void k_src_fill(ProbTable T, double* t, const int32_t* srclist, const int32_t* srclist_count) {
-    const int count = *srclist_count;
-    for (int b = blockIdx.x; b < count; b += gridDim.x) {
-        const int tile = srclist[b];
-        const Prob P = prob_of_tile(T, tile);
-        const int tl = tile - P.tile_off;
-        const int tx = tl % P.ntx, ty = (tl / P.ntx) % P.nty, tz = tl / (P.ntx * P.nty);
-        for (int i = threadIdx.x; i < TX * TY * TZ; i += blockDim.x) {
-            int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
-            int x = tx * TX + lx, y = ty * TY + ly, z = tz * TZ + lz;
-            if (x < P.nx && y < P.ny && z < P.nz)
-                t[P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x] = inf64();
-        }
-    }
+// t := +inf at every point of the launch (grid-stride), before the sources
+// are placed: a solve starts from the upper bound +inf everywhere.
+__global__ void k_fill_inf(long long npts_total, double* t) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < npts_total; i += stride)
+        t[i] = inf64();
 }
 
 // Writes each source as -t0 (the sign bit marks a fixed point during the solve;
@@ -201,24 +197,6 @@ __global__ void k_src_unsign(ProbTable T, const int64_t* src_idx, const double* 
     *ti = fabs(*ti);
 }
 
-// After a capped (ELIMIT) solve: tiles never visited still hold stale memory;
-// give them +inf so the output is a valid upper bound.
-template <int TX, int TY, int TZ>
-__global__ void k_fill_unvisited(ProbTable T, int ntiles, double* t, const uint32_t* tstate) {
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        if (tstate[tile] & kV) continue;
-        const Prob P = prob_of_tile(T, tile);
-        int tl = tile - P.tile_off;
-        int tx = tl % P.ntx, ty = (tl / P.ntx) % P.nty, tz = tl / (P.ntx * P.nty);
-        for (int i = threadIdx.x; i < TX * TY * TZ; i += blockDim.x) {
-            int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
-            int x = tx * TX + lx, y = ty * TY + ly, z = tz * TZ + lz;
-            if (x < P.nx && y < P.ny && z < P.nz)
-                t[P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x] = inf64();
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
 // the persistent solver
 // ---------------------------------------------------------------------------
@@ -250,13 +228,35 @@ __device__ __forceinline__ void tstore(double* p, double v) {
     __hip_atomic_store((uint64_t*)p, as_u64(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Dirty flags of the in-tile relaxation: one byte per point, stored so that
+// the NPT points of one thread (p = tid + j * NT) are adjacent and one LDS
+// access reads or clears all of them.
+template <int NT, int NPT>
+__device__ __forceinline__ int didx(int p) {
+    return (p % NT) * NPT + p / NT;
+}
+template <int NPT>
+__device__ __forceinline__ uint32_t ld_flags(const uint8_t* f) {
+    if constexpr (NPT == 4) return *(const uint32_t*)f;
+    else if constexpr (NPT == 2) return *(const uint16_t*)f;
+    else return *f;
+}
+template <int NPT>
+__device__ __forceinline__ void st_flags(uint8_t* f, uint32_t v) {
+    if constexpr (NPT == 4) *(uint32_t*)f = v;
+    else if constexpr (NPT == 2) *(uint16_t*)f = (uint16_t)v;
+    else *f = (uint8_t)v;
+}
+
 template <int TX, int TY, int TZ, int NT>
 __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
     using C = TileCfg<TX, TY, TZ, NT>;
     constexpr int NPT = C::NPT;
+    static_assert(NPT == 1 || NPT == 2 || NPT == 4, "1, 2 or 4 points per thread");
+    constexpr uint32_t kAllDirty = NPT == 4 ? 0x01010101u : (NPT == 2 ? 0x0101u : 0x01u);
     __shared__ double sT[C::NLDS];
     __shared__ double sQ[C::NP];
-    __shared__ uint8_t sDirty[2][C::NP];
+    __shared__ __align__(4) uint8_t sDirty[2][C::NP];
     __shared__ uint16_t sList[C::NP];
     __shared__ int s_cnt[2];
     __shared__ int s_tile;
@@ -266,21 +266,31 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
     __shared__ uint32_t s_nid[6];
     __shared__ unsigned long long s_face[6];
     __shared__ unsigned int s_upd;
+    __shared__ int s_next;  // tile handed on by the previous run's publish, or -1
 
     const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const unsigned long long lanes_below = (1ull << lane) - 1ull;
     const Sched& S = A.s;
     // per-workgroup statistics, flushed once at exit; the phase times use the
     // 100 MHz wall clock: [0] claim, [1] stage, [2] relax, [3] write + publish
-    unsigned long long my_visits = 0, my_updates = 0, my_passes = 0;
+    unsigned long long my_visits = 0, my_updates = 0, my_passes = 0, my_cont = 0;
     unsigned long long ph[6] = {0, 0, 0, 0, 0, 0};
     unsigned long long tm = wall_clock64();
+    if (tid == 0) {
+        s_next = -1;
+        s_bucket = 0;
+    }
 
     for (;;) {
-        // ---- claim ------------------------------------------------------
+        // ---- claim (or take the tile handed on) ----------------------------
         if (tid < 64) {
-            int64_t bucket = 0;
-            int tile = claim(S, &bucket);
+            int64_t bucket = s_bucket;
+            int tile = s_next;
+            if (tile < 0) tile = claim(S, &bucket);
+            else if (tid == 0) ++my_cont;
             if (tid == 0) {
+                s_next = -1;
                 s_tile = tile;
                 s_bucket = bucket;
                 if (tile >= 0) {
@@ -322,8 +332,7 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
         }
         const bool visited = (st & kV) != 0;
 
-        // neighbour tile states: x-, x+, y-, y+, z-, z+ (V bit says whether its
-        // interior holds real values; otherwise its face reads as +inf)
+        // face neighbours x-, x+, y-, y+, z-, z+ (bit 30: the tile exists)
         if (tid < 6) {
             int d = tid >> 1, side = tid & 1;
             int nt[3] = {tx, ty, tz};
@@ -332,7 +341,7 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
             uint32_t w = 0, nid = 0;
             if (nt[d] >= 0 && nt[d] < lim[d]) {
                 nid = (uint32_t)(P.tile_off + (nt[2] * P.nty + nt[1]) * P.ntx + nt[0]);
-                w = ld_rlx(S.tstate + nid) | 0x40000000u;  // bit 30: tile exists
+                w = 0x40000000u;
             }
             s_nb[tid] = w;
             s_nid[tid] = nid;
@@ -344,8 +353,11 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
             s_cnt[1] = 0;
         }
 
-        // ---- stage the tile in LDS ---------------------------------------
+        // ---- stage the tile and its halo in LDS ----------------------------
+        // t starts at +inf everywhere, so every in-grid value read here is a
+        // valid upper bound: interior and halo loads go out together.
         double t_in[NPT];
+        uint32_t live = 0;  // bit j: point j is in the grid and not a source
 #pragma unroll
         for (int j = 0; j < NPT; ++j) {
             const int p = tid + j * NT;
@@ -360,42 +372,37 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
                     set_flag(S, kFlagDomain);
                     q = 0.0;
                 }
-                if (visited) {
-                    tv = as_f64(__hip_atomic_load((const uint64_t*)(A.t + gi), __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT));
-                    if (signbit(tv)) {  // a source: fixed
-                        tv = fabs(tv);
-                        q = 0.0;
-                    }
+                tv = as_f64(__hip_atomic_load((const uint64_t*)(A.t + gi), __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT));
+                if (signbit(tv)) {  // a source: fixed
+                    tv = fabs(tv);
+                    q = 0.0;
                 }
             }
+            if (q > 0.0) live |= 1u << j;
             sT[C::lds(lx, ly, lz)] = tv;
             sQ[p] = q;
-            sDirty[0][p] = 1;
-            sDirty[1][p] = 0;
             t_in[j] = tv;
         }
-        __syncthreads();  // s_nb ready
-
-        // halo: x faces, y faces, (z faces)
+        st_flags<NPT>(sDirty[0] + tid * NPT, kAllDirty);
+        st_flags<NPT>(sDirty[1] + tid * NPT, 0u);
         {
             constexpr int NXF = 2 * TY * TZ, NYF = 2 * TX * TZ, NZF = C::D3 ? 2 * TX * TY : 0;
             for (int i = tid; i < NXF + NYF + NZF; i += NT) {
-                int lx, ly, lz, f;
+                int lx, ly, lz;
                 if (i < NXF) {
                     int side = i / (TY * TZ), r = i % (TY * TZ);
-                    ly = r % TY; lz = r / TY; lx = side ? TX : -1; f = side;
+                    ly = r % TY; lz = r / TY; lx = side ? TX : -1;
                 } else if (i < NXF + NYF) {
                     int k = i - NXF, side = k / (TX * TZ), r = k % (TX * TZ);
-                    lx = r % TX; lz = r / TX; ly = side ? TY : -1; f = 2 + side;
+                    lx = r % TX; lz = r / TX; ly = side ? TY : -1;
                 } else {
                     int k = i - NXF - NYF, side = k / (TX * TY), r = k % (TX * TY);
-                    lx = r % TX; ly = r / TX; lz = side ? TZ : -1; f = 4 + side;
+                    lx = r % TX; ly = r / TX; lz = side ? TZ : -1;
                 }
                 const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
                 double v = inf64();
-                const uint32_t nb = s_nb[f];
-                if ((nb & kV) && x >= 0 && x < P.nx && y >= 0 && y < P.ny && z >= 0 && z < P.nz)
+                if (x >= 0 && x < P.nx && y >= 0 && y < P.ny && z >= 0 && z < P.nz)
                     v = hload(A.t + P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x);
                 sT[C::lds(lx, ly, lz)] = v;
             }
@@ -408,32 +415,42 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
         }
 
         // ---- relax until the tile is quiet --------------------------------
-        // Each pass first compacts the dirty points into a dense list (wave
-        // ballot + prefix count, one LDS atomic per wave), then applies the
-        // operator to the list, so the waves run the operator only as many
-        // times as there are dirty points, not once per owned point.  A point
-        // whose value drops marks its in-tile neighbours dirty for the next
-        // pass; values read within a pass may already be newer (any order of
+        // Each pass first compacts the dirty points into a dense list (every
+        // thread reads its points' flags with one LDS access; per-point ballots
+        // give each point its place in the wave's segment, one LDS atomic per
+        // wave reserves the segment), then applies the operator to the list,
+        // so the waves run the operator only as many times as there are dirty
+        // points, not once per owned point.  A point whose value drops marks
+        // its in-tile neighbours above the new value dirty for the next pass;
+        // values read within a pass may already be newer (any order of
         // monotone updates is valid).
-        const int lane = tid & 63;
         int cb = 0;
         int passes = 0;
         for (;;) {
+            {
+                uint8_t* df = sDirty[cb] + tid * NPT;
+                const uint32_t fl = ld_flags<NPT>(df);
+                if (fl) st_flags<NPT>(df, 0u);
+                uint32_t m = 0;
 #pragma unroll
-            for (int j = 0; j < NPT; ++j) {
-                const int p = tid + j * NT;
-                bool d = sDirty[cb][p] != 0;
-                if (d) {
-                    sDirty[cb][p] = 0;
-                    d = sQ[p] > 0.0;
+                for (int j = 0; j < NPT; ++j) m |= ((fl >> (8 * j)) & 1u) << j;
+                m &= live;
+                unsigned long long B[NPT];
+                int tot = 0;
+#pragma unroll
+                for (int j = 0; j < NPT; ++j) {
+                    B[j] = __ballot((m >> j) & 1u);
+                    tot += __popcll(B[j]);
                 }
-                const unsigned long long m = __ballot(d);
-                if (m) {
-                    const int leader = __ffsll((long long)m) - 1;
+                if (tot) {
                     int base = 0;
-                    if (lane == leader) base = atomicAdd(&s_cnt[cb], (int)__popcll(m));
-                    base = __shfl(base, leader);
-                    if (d) sList[base + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)p;
+                    if (lane == 0) base = atomicAdd(&s_cnt[cb], tot);
+                    base = __shfl(base, 0);
+#pragma unroll
+                    for (int j = 0; j < NPT; ++j) {
+                        if ((m >> j) & 1u) sList[base + __popcll(B[j] & lanes_below)] = (uint16_t)(tid + j * NT);
+                        base += __popcll(B[j]);
+                    }
                 }
             }
             __syncthreads();
@@ -460,13 +477,13 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
                     // only neighbours above the new value can depend on it
                     // (the operator is causal), so only they need another look
                     uint8_t* nd = sDirty[cb ^ 1];
-                    if (lx > 0 && sT[L - 1] > r) nd[p - 1] = 1;
-                    if (lx < TX - 1 && sT[L + 1] > r) nd[p + 1] = 1;
-                    if (ly > 0 && sT[L - C::SY] > r) nd[p - TX] = 1;
-                    if (ly < TY - 1 && sT[L + C::SY] > r) nd[p + TX] = 1;
+                    if (lx > 0 && sT[L - 1] > r) nd[didx<NT, NPT>(p - 1)] = 1;
+                    if (lx < TX - 1 && sT[L + 1] > r) nd[didx<NT, NPT>(p + 1)] = 1;
+                    if (ly > 0 && sT[L - C::SY] > r) nd[didx<NT, NPT>(p - TX)] = 1;
+                    if (ly < TY - 1 && sT[L + C::SY] > r) nd[didx<NT, NPT>(p + TX)] = 1;
                     if (C::D3) {
-                        if (lz > 0 && sT[L - C::SZ] > r) nd[p - TX * TY] = 1;
-                        if (lz < TZ - 1 && sT[L + C::SZ] > r) nd[p + TX * TY] = 1;
+                        if (lz > 0 && sT[L - C::SZ] > r) nd[didx<NT, NPT>(p - TX * TY)] = 1;
+                        if (lz < TZ - 1 && sT[L + C::SZ] > r) nd[didx<NT, NPT>(p + TX * TY)] = 1;
                     }
                 }
             }
@@ -495,11 +512,8 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
             const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
             if (x < P.nx && y < P.ny && z < P.nz) {
                 const double v = sT[C::lds(lx, ly, lz)];
-                const bool lowered = v < t_in[j];
-                if (lowered || !visited) {
+                if (v < t_in[j]) {
                     tstore(A.t + P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x, v);
-                }
-                if (lowered) {
                     ++nchg;
                     if (lx == 0) fmin_[0] = fmin(fmin_[0], v);
                     if (lx == TX - 1) fmin_[1] = fmin(fmin_[1], v);
@@ -522,8 +536,11 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
         stores_done();
         __syncthreads();
 
-        // ---- publish: V bit, activate neighbours, end the run --------------
-        if (tid < 64) publish(S, A.tkey, (uint32_t)tile, s_bucket, !visited, s_nb, s_nid, s_face);
+        // ---- publish: activate neighbours, end the run or hand on ----------
+        if (tid < 64) {
+            const int nxt = publish(S, A.tkey, (uint32_t)tile, s_bucket, !visited, s_nb, s_nid, s_face, true);
+            if (tid == 0) s_next = nxt;
+        }
         if (tid == 0) {
             my_updates += s_upd;
             my_passes += (unsigned long long)passes;
@@ -539,6 +556,10 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
             __hip_atomic_fetch_add(S.counters + 5 + i, ph[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(S.counters + 9, ph[5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(S.counters + 10, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(S.counters + 12, my_cont, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (S.timeline)
+            __hip_atomic_fetch_max(S.timeline + 1, (unsigned long long)wall_clock64(), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(S.counters + 0, my_visits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(S.counters + 1, my_updates, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(S.counters + 2, my_passes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

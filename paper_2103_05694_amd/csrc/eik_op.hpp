@@ -31,16 +31,16 @@ __device__ __forceinline__ double as_f64(uint64_t u) { return __longlong_as_doub
 __device__ __forceinline__ uint64_t as_u64(double d) { return (uint64_t)__double_as_longlong(d); }
 __device__ __forceinline__ double inf64() { return as_f64(kInfBits); }
 
-// S(r) >= c with a0 <= a1 <= a2 (a1, a2 may be +inf).
+// S(r) >= c with a0 <= a1 <= a2 (a1, a2 may be +inf).  T_k is computed as
+// fl(m * m) with m = max(d, 0): for d > 0 that is fl(d * d), otherwise m is a
+// zero of either sign and the square is +0, so the bits are those of the
+// definition (d is never NaN: r is finite and every a_k is finite or +inf).
 __device__ __forceinline__ bool reaches(double r, double a0, double a1, double a2, double c) {
-    double d0 = r - a0;
-    double d1 = r - a1;
-    double d2 = r - a2;
-    double s0 = d0 > 0.0 ? d0 * d0 : 0.0;
-    double s1 = d1 > 0.0 ? d1 * d1 : 0.0;
-    double s2 = d2 > 0.0 ? d2 * d2 : 0.0;
-    double s = s0 + s1;
-    s = s + s2;
+    const double m0 = fmax(r - a0, 0.0);
+    const double m1 = fmax(r - a1, 0.0);
+    const double m2 = fmax(r - a2, 0.0);
+    double s = m0 * m0 + m1 * m1;
+    s = s + m2 * m2;
     return s >= c;
 }
 
@@ -52,6 +52,20 @@ __device__ __forceinline__ void sort3(double& a0, double& a1, double& a2) {
     a1 = fmax(lo, m);
 }
 
+// Square root for the estimate below: the hardware reciprocal square root
+// refined by one coupled Newton step and one residual correction (about one
+// ulp).  Not correctly rounded, and NaN for x == 0: the estimate only steers
+// the exact search, which handles any starting point.
+__device__ __forceinline__ double est_sqrt(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, hh = 0.5 * y;
+    const double e = fma(-g, hh, 0.5);
+    g = fma(g, e, g);
+    hh = fma(hh, e, hh);
+    const double d = fma(-g, g, x);
+    return fma(d, hh, g);
+}
+
 // Closed-form Godunov estimate from sorted minima (u = r - a0 solves the one-,
 // two- or three-term quadratic), computed without branches so all three
 // candidates overlap; infinities select the right candidate (fmax drops NaN).
@@ -60,11 +74,11 @@ __device__ __forceinline__ double guess(double a0, double a1, double a2, double 
     const double r1 = a0 + q;
     const double b1 = a1 - a0;
     const double d2 = fmax(c + c - b1 * b1, 0.0);
-    const double r2 = a0 + 0.5 * (b1 + __builtin_sqrt(d2));
+    const double r2 = a0 + 0.5 * (b1 + est_sqrt(d2));
     const double b2 = a2 - a0;
     const double sb = b1 + b2;
     const double d3 = fmax(sb * sb - 3.0 * (b1 * b1 + b2 * b2 - c), 0.0);
-    const double r3 = a0 + (sb + __builtin_sqrt(d3)) * (1.0 / 3.0);
+    const double r3 = a0 + (sb + est_sqrt(d3)) * (1.0 / 3.0);
     return r1 <= a1 ? r1 : (r2 <= a2 ? r2 : r3);
 }
 
@@ -105,10 +119,12 @@ __device__ __noinline__ double search_slow(double a0, double a1, double a2, doub
 // `x`, `y`, `z` are the axis minima in any order (+inf where absent).
 //
 // First r < tcur  <=>  S(prev(tcur)) >= c (S is monotone), so one predicate
-// rejects every non-improving update.  Then four independent predicate
-// evaluations run side by side at G-2 .. G+1 around the guess G; the answer is
-// the first of G-1, G, G+1 that satisfies the predicate when the one below it
-// does not (reaches(a0) is always false).  Otherwise the serial search decides.
+// rejects every non-improving update.  Then the predicate is evaluated at
+// G-2 .. G+1 around the guess G as four independent chains; the answer is the
+// first of G-1, G, G+1 that satisfies it while the one below does not.  G is
+// clamped to [A0 + 2, prev(tcur)], so G - 2 >= A0 (where the predicate is
+// false when G - 2 == A0, as S(a0) = 0 < c).  Otherwise the serial search
+// decides.
 __device__ __forceinline__ double update(double x, double y, double z, double q, double c,
                                          double tcur, bool& changed) {
     changed = false;
@@ -120,22 +136,33 @@ __device__ __forceinline__ double update(double x, double y, double z, double q,
     // rejects them before the guess is computed
     if (!reaches(as_f64(tcb - 1), a0, a1, a2, c)) return tcur;
     const uint64_t A0 = as_u64(a0);
-    // reaches(tcb - 1) is false whenever tcb - 1 <= A0, so here G ends up in
-    // [A0 + 1, tcb - 1]
+    // reaches(tcb - 1) is false whenever tcb - 1 <= A0, so here tcb - 1 > A0
     uint64_t G = as_u64(guess(a0, a1, a2, q, c));
     if (!(G >= A0 + 2)) G = A0 + 2;                // also catches a NaN pattern
     if (G > tcb - 1) G = tcb - 1;
-    const bool pm2 = (G >= A0 + 3) && reaches(as_f64(G - 2), a0, a1, a2, c);
-    const bool pm = (G >= A0 + 2) && reaches(as_f64(G - 1), a0, a1, a2, c);
-    const bool p0 = reaches(as_f64(G), a0, a1, a2, c);
-    const bool pp = reaches(as_f64(G + 1), a0, a1, a2, c);
-    uint64_t H;
-    if (pm && !pm2) H = G - 1;
-    else if (p0 && !pm) H = G;
-    else if (pp && !p0) H = G + 1;
-    else return (changed = true, search_slow(a0, a1, a2, c, A0, G, tcb));
+    // S is non-decreasing in r, so the four outcomes are false...false
+    // true...true and their count locates the answer: 3 -> G-1, 2 -> G,
+    // 1 -> G+1; 4 (the answer is below G-1) or 0 (above G+1) need the search.
+    // The chains are written side by side so that they interleave.
+    double r[4], m0[4], m1[4], m2[4], sm[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r[k] = as_f64(G - 2 + (uint64_t)k);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) m0[k] = fmax(r[k] - a0, 0.0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) m1[k] = fmax(r[k] - a1, 0.0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) m2[k] = fmax(r[k] - a2, 0.0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sm[k] = m0[k] * m0[k] + m1[k] * m1[k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sm[k] = sm[k] + m2[k] * m2[k];
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cnt += sm[k] >= c ? 1 : 0;
     changed = true;
-    return as_f64(H);
+    if (cnt == 0 || cnt == 4) return search_slow(a0, a1, a2, c, A0, G, tcb);
+    return as_f64(G + 2 - (uint64_t)cnt);
 }
 
 }  // namespace eik

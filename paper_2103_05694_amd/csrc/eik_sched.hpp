@@ -20,7 +20,10 @@
 //  * the operator is monotone and causal, so none of this changes results.
 //
 // Each ring is a bounded MPMC array of 64-bit cells (sequence << 32 | tile),
-// positions taken with fetch-add.  A cell for position p is free when its
+// positions taken with fetch-add.  Its queued count and the number of runs
+// claimed from it share one 64-bit word (running << 32 | count + 2^31), so a
+// claim is one RMW (running + 1, count - 1) and one load shows whether the
+// bucket is drained (nothing queued and nothing running at the same instant).  A cell for position p is free when its
 // sequence equals p, full when it equals p + 1, and is freed for the next lap
 // (sequence p + cap) by the consumer after reading: a producer never overwrites
 // a cell whose item has been claimed but not yet read.  A tile is queued at most
@@ -65,21 +68,24 @@ __device__ __forceinline__ void stores_done() { asm volatile("s_waitcnt vmcnt(0)
 
 constexpr uint32_t kQ = 1u, kR = 2u, kV = 4u, kS = 8u;
 constexpr int kMaxRings = 64;
-// Each ring counter (head, tail, count, running) lives in its own 256-byte
+// Each ring counter (head, tail, count + running) lives in its own 256-byte
 // line, so polling one does not slow the atomics on the others.
 constexpr int kCtrPad = 64;                 // uint32 words per counter line
 constexpr int kCtrStride = 4 * kCtrPad;     // uint32 words per ring
+constexpr int kCrWord = 2 * kCtrPad;        // offset of the count + running word
+constexpr uint64_t kCountBias = 1ull << 31; // count is stored biased, so it may dip below 0
+constexpr uint64_t kRunOne = 1ull << 32;
 
 // device status flags
 constexpr uint32_t kFlagDomain = 1u, kFlagLimit = 2u, kFlagBadSrc = 4u, kFlagWatchdog = 8u;
 
 struct Sched {
     uint64_t* items;     // [nrings][cap]
-    uint32_t* ctr;       // ring counters, see ring_head / ring_tail / ring_count / ring_run
+    uint32_t* ctr;       // ring counters, see ring_head / ring_tail / ring_cr
     uint32_t* tstate;    // [ntiles]
     int32_t* cur;        // lowest bucket of the window
     int32_t* pending;    // tiles queued or running
-    unsigned long long* counters;  // [0] visits [1] point updates [2] relax passes
+    unsigned long long* counters;  // statistics: [0] visits [1] point updates [2] relax passes ...
     uint32_t* flags;     // device status flags
     int32_t* poisoned;   // set on a watchdog expiry: the next reset re-initialises the rings
     int nrings;
@@ -87,12 +93,22 @@ struct Sched {
     double inv_delta;    // 1/delta, 0 => single bucket
     long long max_visits;  // 0 => unlimited
     int lookahead;       // claims may come from buckets cur .. cur + lookahead
+    unsigned long long* timeline;  // NULL, or [0] start, [1] end, then (time, bucket) per advance
+    int timeline_cap;    // advances the timeline can hold
 };
 
 __device__ __forceinline__ uint32_t* ring_head(const Sched& s, int r) { return s.ctr + r * kCtrStride; }
 __device__ __forceinline__ uint32_t* ring_tail(const Sched& s, int r) { return s.ctr + r * kCtrStride + kCtrPad; }
-__device__ __forceinline__ uint32_t* ring_count(const Sched& s, int r) { return s.ctr + r * kCtrStride + 2 * kCtrPad; }
-__device__ __forceinline__ uint32_t* ring_run(const Sched& s, int r) { return s.ctr + r * kCtrStride + 3 * kCtrPad; }
+__device__ __forceinline__ unsigned long long* ring_cr(const Sched& s, int r) {
+    return (unsigned long long*)(s.ctr + r * kCtrStride + kCrWord);
+}
+__device__ __forceinline__ int32_t cr_count(uint64_t w) { return (int32_t)((int64_t)(w & 0xffffffffull) - (int64_t)kCountBias); }
+__device__ __forceinline__ unsigned long long ld_cr(const Sched& s, int r) {
+    return __hip_atomic_load(ring_cr(s, r), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void cr_add(const Sched& s, int r, uint64_t v) {
+    __hip_atomic_fetch_add(ring_cr(s, r), (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __device__ __forceinline__ uint32_t ld_acq(uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -141,8 +157,26 @@ __device__ __forceinline__ void push_tile(const Sched& s, uint32_t tile, double 
         __builtin_amdgcn_s_sleep(1);
     }
     __hip_atomic_store(cell, ((uint64_t)(pos + 1u) << 32) | tile, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // everything this wave did before (the live-work count included) completes
+    // before the item becomes claimable
     stores_done();
-    __hip_atomic_fetch_add(ring_count(s, r), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    cr_add(s, r, 1);
+}
+
+// Push bucket of a time key as push_tile computes it.
+__device__ __forceinline__ int64_t push_bucket(const Sched& s, double t, int64_t base) {
+    int64_t k = bucket_of(s, t);
+    if (k < base) k = base;
+    if (k > base + s.nrings - 1 - s.lookahead) k = base + s.nrings - 1 - s.lookahead;
+    return k;
+}
+
+// End of the runs claimed from `bucket` by this workgroup: its pushes were
+// counted first (push_tile waits for that), so the bucket never looks drained
+// while work it produced is in flight.  Single lane.
+__device__ __forceinline__ void end_run(const Sched& s, int64_t bucket) {
+    stores_done();
+    cr_add(s, (int)(bucket % s.nrings), 0ull - kRunOne);
 }
 
 // Count a newly activated tile and enqueue it.  Single lane.
@@ -151,13 +185,14 @@ __device__ __forceinline__ void activate_push(const Sched& s, uint32_t tile, dou
     push_tile(s, tile, t, base);
 }
 
-// Try to take one item from ring r.  Returns the tile, -1 (empty) or -2
-// (watchdog).  Single lane.
+// Try to take one item from ring r: one RMW counts the claimer as running and
+// takes one queued item.  Returns the tile, -1 (empty) or -2 (watchdog).
+// Single lane.
 __device__ __forceinline__ int try_claim(const Sched& s, int r) {
-    int32_t old = (int32_t)__hip_atomic_fetch_sub(ring_count(s, r), 1u, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-    if (old <= 0) {
-        __hip_atomic_fetch_add(ring_count(s, r), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t old = __hip_atomic_fetch_add(ring_cr(s, r), (unsigned long long)(kRunOne - 1),
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cr_count(old) <= 0) {
+        cr_add(s, r, 0ull - (kRunOne - 1));
         return -1;
     }
     uint32_t pos = __hip_atomic_fetch_add(ring_head(s, r), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -185,8 +220,8 @@ __device__ __forceinline__ void idle_sleep(int units) {
 }
 
 // Called by all 64 lanes of one wave.  Returns a tile and the bucket it came
-// from (*bucket), or -1 when no work is left anywhere (pending == 0), or -2 on
-// a watchdog expiry.
+// from (*bucket), counted as running there, or -1 when no work is left anywhere
+// (pending == 0), or -2 on a watchdog expiry.
 __device__ __forceinline__ int claim(const Sched& s, int64_t* bucket) {
     const int lane = threadIdx.x & 63;
     const int win = s.lookahead + 1;
@@ -194,27 +229,14 @@ __device__ __forceinline__ int claim(const Sched& s, int64_t* bucket) {
     for (;;) {
         const int32_t c = ld_rlx(s.cur);
         const int r = (int)(((int64_t)c + lane) % s.nrings);
-        // running count first, then queued count: a finishing run increments the
-        // counts of its pushes before it decrements its running count, so a
-        // bucket seen with nothing running and nothing queued really is drained
-        int32_t cnt = 0, run = 0;
-        if (lane == 0) run = (int32_t)ld_rlx(ring_run(s, r));
-        stores_done();
-        if (lane < win) cnt = (int32_t)ld_rlx(ring_count(s, r));
-        const unsigned long long mask = __ballot(cnt > 0);
+        unsigned long long w = kCountBias;  // nothing queued, nothing running
+        if (lane < win) w = ld_cr(s, r);
+        const unsigned long long mask = __ballot(cr_count(w) > 0);
         if (mask) {
-            // lowest bucket of the window with queued work; count ourselves as
-            // running there first, so it cannot look drained while we hold a claim
+            // lowest bucket of the window with queued work
             const int j = __ffsll((long long)mask) - 1;
-            const int rj = (int)(((int64_t)c + j) % s.nrings);
             int got = -1;
-            if (lane == 0) {
-                uint32_t* rc = ring_run(s, rj);
-                __hip_atomic_fetch_add(rc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                stores_done();
-                got = try_claim(s, rj);
-                if (got < 0) __hip_atomic_fetch_sub(rc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
+            if (lane == 0) got = try_claim(s, (int)(((int64_t)c + j) % s.nrings));
             got = __shfl(got, 0);
             if (got >= 0) {
                 *bucket = (int64_t)c + j;
@@ -223,19 +245,26 @@ __device__ __forceinline__ int claim(const Sched& s, int64_t* bucket) {
             if (got == -2) return -2;
             continue;
         }
-        const int run0 = __shfl(run, 0);
-        if (run0 <= 0) {
+        if (__shfl(w, 0) == kCountBias) {
             // bucket `cur` drained: find the next non-empty bucket (full scan)
-            int32_t cf = 0;
-            if (lane < s.nrings) cf = (int32_t)ld_rlx(ring_count(s, r));
-            const unsigned long long m2 = __ballot(cf > 0) & ~1ull;
+            unsigned long long wf = kCountBias;
+            if (lane < s.nrings) wf = ld_cr(s, r);
+            const unsigned long long m2 = __ballot(cr_count(wf) > 0) & ~1ull;
             if (m2) {
                 const int j = __ffsll((long long)m2) - 1;
                 if (lane == 0) {
                     int32_t expect = c;
                     if (__hip_atomic_compare_exchange_strong(s.cur, &expect, c + j, __ATOMIC_RELAXED,
-                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                        __hip_atomic_fetch_add(s.counters + 11, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        const unsigned long long i = __hip_atomic_fetch_add(s.counters + 11, 1ull, __ATOMIC_RELAXED,
+                                                                            __HIP_MEMORY_SCOPE_AGENT);
+                        if (s.timeline && i < (unsigned long long)s.timeline_cap) {
+                            __hip_atomic_store(s.timeline + 2 + 2 * i, (unsigned long long)wall_clock64(),
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            __hip_atomic_store(s.timeline + 3 + 2 * i, (unsigned long long)(c + j),
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                    }
                 }
                 continue;
             }
@@ -261,18 +290,27 @@ __device__ __forceinline__ int claim(const Sched& s, int64_t* bucket) {
 //   nid[f]  its tile id, face[f] the priority key bits of the lowered values on
 //           face f (kInfBits: nothing lowered there),
 //   first   the run wrote this tile's interior for the first time (sets V).
-// Lanes 0..5 activate the neighbours in parallel; the block's pending count
-// changes once, by (#newly queued neighbours + requeue - 1), before any push
-// makes the new items claimable, so it never under-counts live work.
-__device__ __forceinline__ void publish(const Sched& s, uint64_t* tkey, uint32_t tile, int64_t bucket, bool first,
-                                        const uint32_t* nb, const uint32_t* nid,
-                                        const unsigned long long* face) {
+// First the tile's own state word drops R (and gains V); the RMW's return also
+// says whether the tile was activated during the run.  Then lanes 0..5
+// activate the neighbours in parallel.  The live-work count changes once, by
+// (#newly queued neighbours + requeue - 1), before any push makes new items
+// claimable, so it never under-counts.
+// With `cont`, the lowest-key newly activated neighbour that falls in this
+// run's own bucket is not pushed: it is returned (state Q, counted live and
+// counted running in `bucket`) for this workgroup to run next, which saves a
+// push, a poll and a claim on the front's critical path.  Returns that tile or
+// -1 (the run has then ended), uniform across the wave.
+__device__ __forceinline__ int publish(const Sched& s, uint64_t* tkey, uint32_t tile, int64_t bucket, bool first,
+                                       const uint32_t* nb, const uint32_t* nid,
+                                       const unsigned long long* face, bool cont = false) {
     const int lane = threadIdx.x & 63;
-    if (first) {
-        if (lane == 0)
-            __hip_atomic_fetch_or(s.tstate + tile, kV, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        stores_done();
-    }
+    uint32_t own = 0;
+    if (lane == 0)
+        own = __hip_atomic_fetch_xor(s.tstate + tile, kR | (first ? kV : 0u), __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+    // the RMW has returned, so V is visible before any neighbour is activated
+    own = __shfl(own, 0);
+    const bool requeue = (own & kQ) != 0;
     bool want = false;
     uint32_t n = 0;
     unsigned long long fk = kInfBits;
@@ -289,54 +327,45 @@ __device__ __forceinline__ void publish(const Sched& s, uint64_t* tkey, uint32_t
             }
         }
     }
-    const int k = __popcll(__ballot(want));
-    int requeue = 0;
-    double rkey = 0.0;
+    const unsigned long long wm = __ballot(want);
+    const int k = __popcll(wm);
+    int cl = -1;
+    if (cont && wm) {
+        const bool cand = want && push_bucket(s, as_f64(fk), bucket) == bucket;
+        unsigned long long key = cand ? fk : ~0ull;
+        // minimum over lanes 0..7 (the six face lanes)
+#pragma unroll
+        for (int off = 1; off < 8; off <<= 1) {
+            const unsigned long long o = __shfl_xor(key, off);
+            key = o < key ? o : key;
+        }
+        key = __shfl(key, 0);
+        const unsigned long long cm = __ballot(cand && fk == key);
+        if (cm) cl = __ffsll((long long)cm) - 1;
+    }
     if (lane == 0) {
-        uint32_t* w = s.tstate + tile;
-        uint32_t old = ld_rlx(w);
-        for (;;) {
-            uint32_t seen = old;
-            if (__hip_atomic_compare_exchange_strong(w, &seen, old & ~kR, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT))
-                break;
-            old = seen;
-        }
-        if (old & kQ) {
-            requeue = 1;
-            uint64_t kb = __hip_atomic_exchange((unsigned long long*)(tkey + tile), kInfBits,
-                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            rkey = kb == kInfBits ? 0.0 : as_f64(kb);
-        }
-        const int delta = k + requeue - 1;
+        const int delta = k + (requeue ? 1 : 0) - 1;
         if (delta != 0)
             __hip_atomic_fetch_add(s.pending, delta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (want) push_tile(s, n, as_f64(fk), bucket);
-    if (lane == 0 && requeue) push_tile(s, tile, rkey, bucket);
-    // this run's own pushes are queued: the bucket it came from may now drain
-    stores_done();
-    if (lane == 0)
-        __hip_atomic_fetch_sub(ring_run(s, (int)(bucket % s.nrings)), 1u, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+    if (want && lane != cl) push_tile(s, n, as_f64(fk), bucket);
+    if (lane == 0 && requeue) {
+        uint64_t kb = __hip_atomic_exchange((unsigned long long*)(tkey + tile), kInfBits, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+        push_tile(s, tile, kb == kInfBits ? 0.0 : as_f64(kb), bucket);
+    }
+    if (cl >= 0) return (int)__shfl(n, cl);
+    // this run's own pushes are counted: the bucket it came from may now drain
+    if (lane == 0) end_run(s, bucket);
+    return -1;
 }
 
 // Drop a claimed tile without running it (visit cap reached).  Lane 0.
 __device__ __forceinline__ void drop_run(const Sched& s, uint32_t tile, int64_t bucket) {
-    uint32_t* w = s.tstate + tile;
-    uint32_t old = ld_rlx(w);
-    for (;;) {
-        uint32_t seen = old;
-        if (__hip_atomic_compare_exchange_strong(w, &seen, old & ~kR, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT))
-            break;
-        old = seen;
-    }
+    const uint32_t old = __hip_atomic_fetch_xor(s.tstate + tile, kR, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (old & kQ) push_tile(s, tile, 0.0, bucket);
     else __hip_atomic_fetch_sub(s.pending, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    stores_done();
-    __hip_atomic_fetch_sub(ring_run(s, (int)(bucket % s.nrings)), 1u, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+    end_run(s, bucket);
 }
 
 }  // namespace eik
