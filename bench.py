@@ -90,7 +90,8 @@ def bench_single(args, torch, eik, W) -> dict:
     f = torch.from_numpy(p.field).cuda()
     src = torch.as_tensor(p.src).cuda()
     out = torch.empty_like(f)
-    kw = dict(delta=args.delta, tile=args.tile, out=out, check_status=False)
+    kw = dict(delta=args.delta, tile=args.tile, grid_blocks=args.grid_blocks, horizon=args.horizon, out=out,
+              check_status=False)
     for _ in range(args.warmup):
         eik.solve(f, p.h, src, **kw)
     eik.status()
@@ -140,13 +141,15 @@ def bench_tomography(args, torch, eik, W) -> dict:
     srcs = [torch.tensor([int(s)]) for s in case.sources]
     rec = torch.as_tensor(case.receivers).cuda()
     obs = ShotBatch([s_true] * args.shots, case.h, srcs, [rec] * args.shots, kind="slowness",
-                    delta=args.tomo_delta)
+                    delta=args.tomo_delta, tile=args.tomo_tile, grid_blocks=args.tomo_grid_blocks,
+                    horizon=args.tomo_horizon)
     obs.step()
     obs.sync()
     eik.status(obs.stream)
     t_obs = [v.reshape(-1).index_select(0, rec) for v in obs.shot_views(obs.t)]
     sb = ShotBatch([s0] * args.shots, case.h, srcs, [rec] * args.shots, t_obs=t_obs, kind="slowness",
-                   delta=args.tomo_delta)
+                   delta=args.tomo_delta, tile=args.tomo_tile, grid_blocks=args.tomo_grid_blocks,
+                   horizon=args.tomo_horizon)
     sb.capture()
     reps = max(args.steps // 4, 2)
     for _ in range(2):
@@ -199,13 +202,15 @@ def bench_uneven(args, torch, eik, W) -> dict:
         RX, RY = np.meshgrid(rx, ry, indexing="xy")
         recs.append(torch.as_tensor(W.flat_index(RX.ravel(), RY.ravel(), 0, p.nx, p.ny)).cuda())
     npts = sum(p.npts for p in shots)
-    obs = ShotBatch(fields_true, 10.0, srcs, recs, kind="slowness", delta=args.tomo_delta)
+    obs = ShotBatch(fields_true, 10.0, srcs, recs, kind="slowness", delta=args.tomo_delta, tile=args.tomo_tile,
+                    grid_blocks=args.tomo_grid_blocks, horizon=args.tomo_horizon)
     obs.step()
     obs.sync()
     eik.status(obs.stream)
     t_obs = [v.reshape(-1).index_select(0, r) for v, r in zip(obs.shot_views(obs.t), recs)]
     del obs
-    sb = ShotBatch(fields, 10.0, srcs, recs, t_obs=t_obs, kind="slowness", delta=args.tomo_delta)
+    sb = ShotBatch(fields, 10.0, srcs, recs, t_obs=t_obs, kind="slowness", delta=args.tomo_delta,
+                   tile=args.tomo_tile, grid_blocks=args.tomo_grid_blocks, horizon=args.tomo_horizon)
     sb.capture()
     reps = max(args.steps // 8, 2)
     sb.replay()
@@ -234,6 +239,37 @@ def bench_uneven(args, torch, eik, W) -> dict:
             "bitwise_equal_grad": bool(torch.equal(g_plain, sb.grad))}
 
 
+def bench_ablation(args, torch, eik, W) -> dict:
+    """Precision ablation in 2D (the paper's Table "tab:error" question on the
+    GPU): the exact monotone operator and the two explicit formulas under the
+    same asynchronous kernel and five schedules (tile shape, bucket width, grid
+    size).  Reports the residual (points the operator would still change) of
+    each result and how many points differ from the first schedule's result."""
+    p = W.blocky_2d(1024, nsrc=16, seed=3)
+    f = torch.from_numpy(p.field[0]).cuda()
+    src = torch.as_tensor(p.src).cuda()
+    schedules = [dict(tile=(32, 32), delta=0.0), dict(tile=(16, 16), delta=4.0),
+                 dict(tile=(64, 16), delta=16.0), dict(tile=(128, 8), delta=0.0, grid_blocks=64),
+                 dict(tile=(32, 32), delta=2.0, grid_blocks=16)]
+    out = {"workload": "2D 1024x1024 blocky speeds {0.5,1,2,5} in 64-cell blocks, 16 sources, h=1",
+           "schedules": [{k: (list(v) if isinstance(v, tuple) else v) for k, v in s.items()} for s in schedules]}
+    for op in ("dbar", "dhat", "dtilde"):
+        ts, res = [], []
+        for sch in schedules:
+            t = eik.solve(f, p.h, src, op=op, check_status=False, **sch)
+            eik.status()
+            ts.append(t.clone())
+            res.append(eik.residual(f, p.h, src, t, op=op))
+        distinct = []
+        for t in ts:
+            if not any(torch.equal(t, u) for u in distinct):
+                distinct.append(t)
+        out[op] = {"residual_points": [r[0] for r in res], "residual_max_rel": [r[1] for r in res],
+                   "points_differing_from_first": [int((t != ts[0]).sum()) for t in ts],
+                   "distinct_results": len(distinct)}
+    return out
+
+
 def profile_mode(args, torch, eik, W) -> None:
     """A short run for rocprofv3: a plain 1 GiB device copy (counter
     calibration), then a few solves of the headline workload."""
@@ -246,7 +282,8 @@ def profile_mode(args, torch, eik, W) -> None:
     f = torch.from_numpy(p.field).cuda()
     src = torch.as_tensor(p.src).cuda()
     for i in range(args.steps):
-        eik.solve(f, p.h, src, delta=args.delta, tile=args.tile, check_status=False)
+        eik.solve(f, p.h, src, delta=args.delta, tile=args.tile, grid_blocks=args.grid_blocks,
+                  horizon=args.horizon, check_status=False)
         torch.cuda.synchronize()
         log(f"profile solve {i} done")
     eik.status()
@@ -261,13 +298,17 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--delta", type=float, default=None, help="bucket width (s); default from the tuning cache")
     ap.add_argument("--tile", type=str, default=None, help="e.g. 32x8x4; default from the tuning cache")
-    ap.add_argument("--tomo-delta", type=float, default=0.05)
+    ap.add_argument("--grid-blocks", type=int, default=None, help="persistent workgroups; default from the tuning cache")
+    ap.add_argument("--horizon", type=int, default=None, help="bucket horizon 0..4; default from the tuning cache")
+    ap.add_argument("--tomo-delta", type=float, default=None, help="default from the tuning cache")
+    ap.add_argument("--tomo-tile", type=str, default=None, help="default from the tuning cache")
     ap.add_argument("--shots", type=int, default=32)
     ap.add_argument("--uneven-shots", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--parents", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--profile-mode", action="store_true")
     args = ap.parse_args()
 
@@ -289,9 +330,22 @@ def main() -> int:
         args.tile = tuple(int(x) for x in args.tile.lower().split("x"))
     cfg = autotune.lookup((256, 512, 512), "speed")
     if args.delta is None:
-        args.delta = cfg["delta"] if cfg else 0.05
+        args.delta = cfg["delta"] if cfg else 0.04
     if args.tile is None:
-        args.tile = tuple(cfg["tile"]) if cfg else (32, 8, 4)
+        args.tile = tuple(cfg["tile"]) if cfg else (16, 8, 8)
+    if args.grid_blocks is None:
+        args.grid_blocks = int(cfg.get("grid_blocks", 0)) if cfg else 0
+    if args.horizon is None:
+        args.horizon = int(cfg.get("horizon", 0)) if cfg else 0
+    tcfg = autotune.lookup((128, 256, 256), "slowness")
+    if args.tomo_tile is not None:
+        args.tomo_tile = tuple(int(x) for x in args.tomo_tile.lower().split("x"))
+    else:
+        args.tomo_tile = tuple(tcfg["tile"]) if tcfg else (16, 8, 8)
+    if args.tomo_delta is None:
+        args.tomo_delta = tcfg["delta"] if tcfg else 0.02
+    args.tomo_grid_blocks = int(tcfg.get("grid_blocks", 0)) if tcfg else 0
+    args.tomo_horizon = int(tcfg.get("horizon", 0)) if tcfg else 0
 
     if args.profile_mode:
         profile_mode(args, torch, eik, W)
@@ -309,6 +363,10 @@ def main() -> int:
         log("uneven batch")
         extra["uneven_64"] = bench_uneven(args, torch, eik, W)
         log(json.dumps(extra["uneven_64"]))
+    if not args.no_ablation:
+        log("precision ablation")
+        extra["ablation_2d"] = bench_ablation(args, torch, eik, W)
+        log(json.dumps(extra["ablation_2d"]))
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
@@ -320,7 +378,9 @@ def main() -> int:
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "3D 512x512x256 layered+noise speed (h=10 m, 1500-6000 m/s, 8 layers, "
                                "seed 2), one surface-centre source, single forward solve",
-                   "delta": args.delta, "tile": list(args.tile), "points": single["npts"]},
+                   "delta": args.delta, "tile": list(args.tile), "grid_blocks": args.grid_blocks,
+                   "horizon": args.horizon,
+                   "points": single["npts"]},
         "roofline": single["roofline"],
         "cpu_baseline": cpu,
         "extra": extra,

@@ -62,6 +62,11 @@ extern "C" {
 #define EIK_FLAG_TIMELINE 4u      /* eik_opts.flags: record when the lowest open priority bucket
                                      moves on (read back with eik_timeline) */
 
+#define EIK_OP_DBAR 0     /* eik_opts.op: smallest double with S(r) >= c (section "Achieving
+                             Exact Monotonicity with Finite Precision Arithmetic") */
+#define EIK_OP_DHAT 1     /* the reordered explicit formula of Table "tab:prec_2" */
+#define EIK_OP_DTILDE 2   /* the textbook explicit formula of Table "tab:prec_1" */
+
 #define EIK_SPEED 0       /* field holds speed v:    q = h / v */
 #define EIK_SLOWNESS 1    /* field holds slowness s: q = h * s */
 
@@ -74,8 +79,9 @@ typedef struct {
 
 typedef struct {
     double delta;            /* priority bucket width in time units; 0 => one bucket (FIFO) */
-    int32_t tile[3];         /* tile shape (x, y, z); zeros => default for ndim.  Supported:
-                                3D 32x8x4, 16x8x8, 8x8x8, 64x4x4; 2D 32x32, 64x16, 128x8, 16x16 */
+    int32_t tile[3];         /* tile shape (x, y, z); zeros => default for ndim (3D 16x8x8,
+                                2D 32x32).  Supported: 3D 32x8x4, 16x8x8, 8x8x8, 64x4x4;
+                                2D 32x32, 64x16, 128x8, 16x16 */
     int32_t grid_blocks;     /* persistent workgroups; 0 => fill the device */
     int64_t max_tile_visits; /* 0 => unlimited; else stop after this many tile visits (ELIMIT) */
     uint32_t flags;          /* 0 or EIK_FLAG_TIME_KERNELS: record HIP events around the
@@ -84,6 +90,13 @@ typedef struct {
                                 previous eik_status (at most 4096 launches in between) */
     int32_t lookahead;       /* 0..8: work may be taken from the lowest non-drained bucket
                                 and this many buckets above it (0 = strict bucket order) */
+    int32_t horizon;         /* 0 => off; k in 1..4: a run of a tile claimed from bucket b
+                                settles only values r with floor(r / delta) < b + k and requeues
+                                the tile for the rest (no effect when delta == 0) */
+    int32_t op;              /* update operator: EIK_OP_DBAR (0, the exact monotone rounding;
+                                the only one with a schedule-independent result), or, for 2D
+                                grids and block tiles only (precision ablation), EIK_OP_DHAT /
+                                EIK_OP_DTILDE, the paper's explicit formulas */
 } eik_opts;
 
 typedef struct {
@@ -181,6 +194,17 @@ int64_t eik_num_tiles(const eik_grid* g, const eik_opts* opts);
 /* Synchronises `stream`, copies the device status of the last call on it into
  * *out_host (may be NULL) and returns its EIK_* code. */
 int eik_status(void* stream, eik_stats* out_host);
+
+/* Residual of a solution, the error metric of Table "tab:error": applies the
+ * operator `op` (EIK_OP_*; the explicit formulas for 2D grids only) once at
+ * every point that is not one of the nsrc sources (device src_idx), using the
+ * neighbours' values in t (device, C-order), and counts the points whose value
+ * would change (*count_host) and the largest relative change |r - t| / |t|
+ * (*maxrel_host; either pointer may be NULL).  0 for every d-bar solution of
+ * eik_solve.  Synchronises `stream`.  EIK_EDOMAIN if a field value is not
+ * positive and finite. */
+int eik_residual(const eik_grid* g, const double* field, int64_t nsrc, const int64_t* src_idx,
+                 const double* t, int32_t op, int64_t* count_host, double* maxrel_host, void* stream);
 
 /* Schedule record of the last persistent launch on `stream` that ran with
  * EIK_FLAG_TIMELINE (the soft-priority bucket order of the section "The

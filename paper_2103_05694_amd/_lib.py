@@ -26,11 +26,14 @@ EIK_SLOWNESS = 1
 EIK_FLAG_TIME_KERNELS = 1
 EIK_FLAG_WAVE_TILES = 2
 EIK_FLAG_TIMELINE = 4
+EIK_OP_DBAR = 0
+EIK_OP_DHAT = 1
+EIK_OP_DTILDE = 2
 
 EXPORTED = (
     "eik_solve", "eik_parents", "eik_adjoint", "eik_solve_batched", "eik_adjoint_batched",
     "eik_reserve", "eik_num_tiles", "eik_status", "eik_strerror", "eik_last_error",
-    "eik_release", "eik_version", "eik_timeline",
+    "eik_release", "eik_version", "eik_timeline", "eik_residual",
 )
 
 
@@ -42,7 +45,8 @@ class eik_grid(ctypes.Structure):
 class eik_opts(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_double), ("tile", ctypes.c_int32 * 3),
                 ("grid_blocks", ctypes.c_int32), ("max_tile_visits", ctypes.c_int64),
-                ("flags", ctypes.c_uint32), ("lookahead", ctypes.c_int32)]
+                ("flags", ctypes.c_uint32), ("lookahead", ctypes.c_int32), ("horizon", ctypes.c_int32),
+                ("op", ctypes.c_int32)]
 
 
 class eik_stats(ctypes.Structure):
@@ -97,6 +101,9 @@ def load() -> ctypes.CDLL:
     L.eik_num_tiles.argtypes = [_gp, _op]
     L.eik_status.restype = _i32
     L.eik_status.argtypes = [_vp, ctypes.POINTER(eik_stats)]
+    L.eik_residual.restype = _i32
+    L.eik_residual.argtypes = [_gp, _vp, _i64, _vp, _vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
+                               _vp]
     L.eik_timeline.restype = _i32
     L.eik_timeline.argtypes = [_vp, _i32, _vp, _vp, _vp]
     L.eik_strerror.restype = ctypes.c_char_p

@@ -39,7 +39,8 @@ def _grid_of(shape: Sequence[int], h: float, kind: str) -> eik_grid:
 
 def make_opts(delta: float = 0.0, tile: Optional[Sequence[int]] = None, grid_blocks: int = 0,
               max_tile_visits: int = 0, time_kernels: bool = False, lookahead: int = 0,
-              wave_tiles: bool = False, timeline: bool = False) -> eik_opts:
+              wave_tiles: bool = False, timeline: bool = False, op: str = "dbar",
+              horizon: int = 0) -> eik_opts:
     o = eik_opts()
     o.delta = float(delta)
     t = tuple(tile) if tile else (0, 0, 0)
@@ -52,7 +53,18 @@ def make_opts(delta: float = 0.0, tile: Optional[Sequence[int]] = None, grid_blo
     o.flags = (_lib.EIK_FLAG_TIME_KERNELS if time_kernels else 0) | \
         (_lib.EIK_FLAG_WAVE_TILES if wave_tiles else 0) | (_lib.EIK_FLAG_TIMELINE if timeline else 0)
     o.lookahead = int(lookahead)
+    o.horizon = int(horizon)
+    o.op = _op_code(op)
     return o
+
+
+_OPS = {"dbar": _lib.EIK_OP_DBAR, "dhat": _lib.EIK_OP_DHAT, "dtilde": _lib.EIK_OP_DTILDE}
+
+
+def _op_code(op: str) -> int:
+    if op not in _OPS:
+        raise ValueError(f"op must be one of {sorted(_OPS)}")
+    return _OPS[op]
 
 
 def _check_field(field: torch.Tensor) -> None:
@@ -101,6 +113,26 @@ def status(stream=None, raise_on_error: bool = True) -> eik_stats:
     return st
 
 
+def residual(field: torch.Tensor, h: float, sources, t: torch.Tensor, kind: str = "speed",
+             op: str = "dbar", stream=None):
+    """(points the operator would still change, largest relative change) for
+    the times `t` -- the error metric of the paper's Table "tab:error"."""
+    _check_field(field)
+    _check_field(t)
+    if t.shape != field.shape:
+        raise ValueError("t must have the field's shape")
+    L = _lib.load()
+    g = _grid_of(field.shape, h, kind)
+    src = source_indices(sources, field.shape, field.device)
+    cnt = ctypes.c_int64(0)
+    worst = ctypes.c_double(0.0)
+    rc = L.eik_residual(ctypes.byref(g), field.data_ptr(), src.numel(), src.data_ptr(), t.data_ptr(),
+                        _op_code(op), ctypes.byref(cnt), ctypes.byref(worst),
+                        ctypes.c_void_p(_stream_handle(stream)))
+    check(rc)
+    return int(cnt.value), float(worst.value)
+
+
 def timeline(stream=None, cap: int = 1 << 16):
     """Bucket advances of the last launch run with timeline=True: (times in us
     since its reset, bucket moved to, span in us of the whole launch)."""
@@ -121,7 +153,7 @@ def solve(field: torch.Tensor, h: float, sources, t0: Optional[torch.Tensor] = N
           tile: Optional[Sequence[int]] = None, grid_blocks: int = 0, max_tile_visits: int = 0,
           out: Optional[torch.Tensor] = None, parents_out: Optional[torch.Tensor] = None,
           check_status: bool = True, stream=None, time_kernels: bool = False, lookahead: int = 0,
-          wave_tiles: bool = False, timeline: bool = False):
+          wave_tiles: bool = False, timeline: bool = False, op: str = "dbar", horizon: int = 0):
     """First-arrival times; returns t, or (t, parents) when parents=True.  `wave_tiles`
     selects the one-tile-per-wave solver (tile shapes 3D 8x8x4, 16x8x4, 8x8x8,
     16x4x4; 2D 16x16, 32x16, 32x8)."""
@@ -139,7 +171,8 @@ def solve(field: torch.Tensor, h: float, sources, t0: Optional[torch.Tensor] = N
     if parents:
         par = parents_out if parents_out is not None else torch.empty(field.shape, dtype=torch.uint8,
                                                                        device=field.device)
-    o = make_opts(delta, tile, grid_blocks, max_tile_visits, time_kernels, lookahead, wave_tiles, timeline)
+    o = make_opts(delta, tile, grid_blocks, max_tile_visits, time_kernels, lookahead, wave_tiles, timeline, op,
+                  horizon)
     rc = L.eik_solve(ctypes.byref(g), field.data_ptr(), src.numel(), src.data_ptr(),
                      t0d.data_ptr() if t0d is not None else None, t.data_ptr(),
                      par.data_ptr() if par is not None else None, ctypes.byref(o),
@@ -280,10 +313,11 @@ def pack(fields: Sequence[torch.Tensor], hs: Union[float, Sequence[float]], sour
 
 def solve_packed(b: Batch, t_packed: torch.Tensor, par_packed: Optional[torch.Tensor] = None,
                  delta: float = 0.0, tile=None, grid_blocks: int = 0, stream=None,
-                 time_kernels: bool = False, lookahead: int = 0, wave_tiles: bool = False) -> None:
+                 time_kernels: bool = False, lookahead: int = 0, wave_tiles: bool = False,
+                 horizon: int = 0) -> None:
     """Enqueue one batched forward launch (no host synchronisation)."""
     L = _lib.load()
-    o = make_opts(delta, tile, grid_blocks, 0, time_kernels, lookahead, wave_tiles)
+    o = make_opts(delta, tile, grid_blocks, 0, time_kernels, lookahead, wave_tiles, horizon=horizon)
     check(L.eik_solve_batched(b.nprob, b.grids, b.offsets, b.field.data_ptr(), b.src_off,
                               b.src.data_ptr(), b.t0.data_ptr() if b.t0 is not None else None,
                               t_packed.data_ptr(), par_packed.data_ptr() if par_packed is not None else None,
@@ -303,12 +337,13 @@ def adjoint_packed(b: Batch, t_packed: torch.Tensor, par_packed: torch.Tensor, g
 
 
 def solve_batched(fields: Sequence[torch.Tensor], h, sources, kind: str = "speed", parents: bool = False,
-                  delta: float = 0.0, tile=None, check_status: bool = True):
+                  delta: float = 0.0, tile=None, check_status: bool = True, grid_blocks: int = 0,
+                  horizon: int = 0):
     """Solve independent problems (uneven sizes allowed) in one persistent launch."""
     b = pack(fields, h, sources, kind)
     t = torch.empty(b.npts, dtype=torch.float64, device=b.field.device)
     par = torch.empty(b.npts, dtype=torch.uint8, device=b.field.device) if parents else None
-    solve_packed(b, t, par, delta, tile)
+    solve_packed(b, t, par, delta, tile, grid_blocks=grid_blocks, horizon=horizon)
     if check_status:
         status()
     ts = b.views(t)

@@ -27,9 +27,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuned.json")
 ARCH = "gfx950"
 
-TILES = {3: [(32, 8, 4), (16, 8, 8), (8, 8, 8), (64, 4, 4)],
-         2: [(64, 16), (32, 32), (128, 8), (16, 16)]}
-DELTA_FACTORS = (0.0, 0.5, 1.0, 2.0, 4.0, 8.0)
+TILES = {3: [(16, 8, 8), (8, 8, 8), (32, 8, 4)],
+         2: [(32, 32), (16, 16), (64, 16)]}
+DELTA_FACTORS = (0.0, 0.25, 0.5, 1.0, 2.0, 4.0, 8.0)
+GRID_BLOCKS = (0, 512)   # 0 = as many workgroups as fit on the device
+HORIZONS = (0, 1, 2)     # 0 = off; k = settle values below (bucket + k) only
 
 
 def _key(shape: Sequence[int], kind: str) -> str:
@@ -59,9 +61,11 @@ def _time(fn, reps: int) -> float:
 
 def tune(field: torch.Tensor, h: float, sources, kind: str = "speed",
          tiles: Optional[Iterable[Tuple[int, ...]]] = None,
-         delta_factors: Sequence[float] = DELTA_FACTORS, reps: int = 5,
+         delta_factors: Sequence[float] = DELTA_FACTORS, reps: int = 3,
+         grid_blocks: Sequence[int] = GRID_BLOCKS, horizons: Sequence[int] = HORIZONS,
          save: bool = True, log=print) -> dict:
-    """Time every (tile, delta) candidate on this problem; all must agree bitwise."""
+    """Time every (tile, delta, grid size) candidate on this problem; all must
+    agree bitwise."""
     nd = field.dim()
     tiles = list(tiles) if tiles is not None else TILES[nd]
     f64 = field.to(torch.float64)
@@ -74,22 +78,27 @@ def tune(field: torch.Tensor, h: float, sources, kind: str = "speed",
         edge = min(tile[:nd])
         for fac in delta_factors:
             delta = fac * qmed * edge
-            fn = lambda: api.solve(field, h, sources, kind=kind, delta=delta, tile=tile, out=out,
-                                   check_status=False)
-            fn()
-            api.status()
-            t = out.clone()
-            if ref is None:
-                ref = t
-            elif not torch.equal(ref, t):
-                raise RuntimeError(f"candidate tile={tile} delta={delta} changed the result")
-            sec = _time(fn, reps)
-            api.status()
-            results.append({"tile": list(tile), "delta": delta, "delta_factor": fac, "ms": sec * 1e3})
-            log(f"  tile {tile} delta {delta:.4g} ({fac} x qmed x edge): {sec * 1e3:.3f} ms")
+            for hz in (horizons if fac > 0 else (0,)):
+                for gb in grid_blocks:
+                    fn = lambda: api.solve(field, h, sources, kind=kind, delta=delta, tile=tile, out=out,
+                                           grid_blocks=gb, horizon=hz, check_status=False)
+                    fn()
+                    api.status()
+                    t = out.clone()
+                    if ref is None:
+                        ref = t
+                    elif not torch.equal(ref, t):
+                        raise RuntimeError(f"candidate tile={tile} delta={delta} grid={gb} horizon={hz} "
+                                           "changed the result")
+                    sec = _time(fn, reps)
+                    api.status()
+                    results.append({"tile": list(tile), "delta": delta, "delta_factor": fac, "grid_blocks": gb,
+                                    "horizon": hz, "ms": sec * 1e3})
+                    log(f"  tile {tile} delta {delta:.4g} ({fac} x qmed x edge) grid {gb} horizon {hz}: "
+                        f"{sec * 1e3:.3f} ms")
     best = min(results, key=lambda r: r["ms"])
-    entry = {"tile": best["tile"], "delta": best["delta"], "ms": best["ms"], "qmed": qmed,
-             "candidates": results}
+    entry = {"tile": best["tile"], "delta": best["delta"], "grid_blocks": best["grid_blocks"],
+             "horizon": best["horizon"], "ms": best["ms"], "qmed": qmed, "candidates": results}
     if save:
         cache = _load()
         cache[_key(field.shape, kind)] = entry
@@ -108,6 +117,14 @@ def _main(argv: List[str]) -> int:
             p = W.layered_3d()
         elif name == "layered256":
             p = W.layered_3d(256, 256, 128)
+        elif name == "tomo256":
+            c = W.tomography(256, 256, 128, nshots=1, seed=5)
+            f = torch.from_numpy(c.s0).cuda()
+            print("tuning tomography slowness model (one shot)", flush=True)
+            e = tune(f, c.h, torch.tensor([int(c.sources[0])]), kind="slowness",
+                     log=lambda s: print(s, flush=True))
+            print(json.dumps({k: v for k, v in e.items() if k != "candidates"}), flush=True)
+            continue
         elif name == "blocky4096":
             p = W.blocky_2d()
         else:

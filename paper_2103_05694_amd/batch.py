@@ -24,10 +24,13 @@ from . import api
 class ShotBatch:
     def __init__(self, fields: Sequence[torch.Tensor], h, sources: Sequence, receivers: Sequence,
                  t_obs: Optional[Sequence[torch.Tensor]] = None, kind: str = "slowness",
-                 delta: float = 0.0, tile=None, stream: Optional[torch.cuda.Stream] = None):
+                 delta: float = 0.0, tile=None, stream: Optional[torch.cuda.Stream] = None,
+                 grid_blocks: int = 0, horizon: int = 0):
         self.kind = kind
         self.delta = delta
         self.tile = tile
+        self.grid_blocks = grid_blocks
+        self.horizon = horizon
         self.fields = list(fields)
         self.nshots = len(self.fields)
         self.hs = [float(h)] * self.nshots if isinstance(h, (int, float)) else [float(x) for x in h]
@@ -54,11 +57,12 @@ class ShotBatch:
 
     # -- one batched step: 2 persistent launches for all shots ----------------
     def _enqueue(self) -> None:
-        api.solve_packed(self.b, self.t, self.par, self.delta, self.tile, stream=self.stream)
+        api.solve_packed(self.b, self.t, self.par, self.delta, self.tile, grid_blocks=self.grid_blocks,
+                         stream=self.stream, horizon=self.horizon)
         self.g.zero_()
         self.g.index_copy_(0, self.rec, self.t.index_select(0, self.rec) - self.t_obs)
         api.adjoint_packed(self.b, self.t, self.par, self.g, self.grad, self.mu, self.delta, self.tile,
-                           stream=self.stream)
+                           grid_blocks=self.grid_blocks, stream=self.stream)
 
     def step(self) -> None:
         """Enqueue one batched forward + adjoint (eager launches)."""
@@ -103,13 +107,14 @@ class ShotBatch:
         rec_off = 0
         for i in range(self.nshots):
             t, par = api.solve(self.fields[i], self.hs[i], self.sources[i], kind=self.kind, parents=True,
-                               delta=self.delta, tile=self.tile, out=tv[i], check_status=False)
+                               delta=self.delta, tile=self.tile, grid_blocks=self.grid_blocks,
+                               horizon=self.horizon, out=tv[i], check_status=False)
             r = self.rec_local[i]
             nr = r.numel()
             gvv[i].view(-1).index_copy_(0, r, t.view(-1).index_select(0, r) - self.t_obs[rec_off:rec_off + nr])
             rec_off += nr
             api.adjoint(self.fields[i], self.hs[i], t, par, gvv[i], kind=self.kind, delta=self.delta,
-                        tile=self.tile, out=gv[i], check_status=False)
+                        tile=self.tile, grid_blocks=self.grid_blocks, out=gv[i], check_status=False)
 
     def shot_views(self, packed: torch.Tensor) -> List[torch.Tensor]:
         return self.b.views(packed)

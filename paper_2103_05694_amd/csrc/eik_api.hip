@@ -45,6 +45,8 @@ struct Workspace {
     // scheduler
     uint64_t* items = nullptr;
     uint32_t* ctr = nullptr;
+    uint8_t* mask = nullptr;       // per-point byte mask (residual: fixed points)
+    int64_t mask_cap = 0;
     unsigned long long* timeline = nullptr;  // bucket advance record (EIK_FLAG_TIMELINE)
     uint32_t* tstate = nullptr;
     uint64_t* tkey = nullptr;
@@ -263,8 +265,8 @@ bool wave_mode(const eik_opts* o) { return o && (o->flags & EIK_FLAG_WAVE_TILES)
 TileShape pick_tile(int ndim, const eik_opts* o) {
     if (o && (o->tile[0] || o->tile[1] || o->tile[2])) return {o->tile[0], o->tile[1], o->tile[2]};
     if (wave_mode(o)) return ndim == 3 ? TileShape{8, 8, 4} : TileShape{16, 16, 1};
-    if (ndim == 3) return {32, 8, 4};
-    return {64, 16, 1};
+    if (ndim == 3) return {16, 8, 8};
+    return {32, 32, 1};
 }
 
 int check_grid(const eik_grid* g) {
@@ -287,6 +289,10 @@ int check_opts(const eik_opts* o) {
     if (o->flags & ~(EIK_FLAG_TIME_KERNELS | EIK_FLAG_WAVE_TILES | EIK_FLAG_TIMELINE))
         return fail(EIK_EINVAL, "unknown flags");
     if (o->lookahead < 0 || o->lookahead > 8) return fail(EIK_EINVAL, "lookahead must be in 0..8");
+    if (o->op < EIK_OP_DBAR || o->op > EIK_OP_DTILDE) return fail(EIK_EINVAL, "unknown operator");
+    if (o->horizon < 0 || o->horizon > 4) return fail(EIK_EINVAL, "horizon must be in 0..4");
+    if (o->op != EIK_OP_DBAR && wave_mode(o))
+        return fail(EIK_ENOTSUP, "the ablation operators run with block tiles only");
     return EIK_OK;
 }
 
@@ -323,6 +329,7 @@ Sched make_sched(Workspace& w, const eik_opts* o) {
     s.inv_delta = (d > 0.0 && std::isfinite(d)) ? 1.0 / d : 0.0;
     s.max_visits = o ? (long long)o->max_tile_visits : 0;
     s.lookahead = o ? o->lookahead : 0;
+    s.horizon = o ? o->horizon : 0;
     const bool tl = o && (o->flags & EIK_FLAG_TIMELINE);
     s.timeline = tl ? w.timeline : nullptr;
     s.timeline_cap = tl ? kTimelineCap : 0;
@@ -358,7 +365,7 @@ int blocks_for(int64_t n, int threads, int cap = 65536) {
 }
 
 // The full forward sequence for one tile shape.
-template <int TX, int TY, int TZ, bool WAVE>
+template <int TX, int TY, int TZ, bool WAVE, int OP = 0>
 int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int64_t>& src_off,
             int64_t ntiles, int64_t npts_total, const double* field, const int64_t* src_idx,
             const double* src_t0, double* t, uint8_t* par, const eik_opts* o) {
@@ -400,12 +407,12 @@ int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int6
         if ((rc = timing_begin(w, o))) return rc;
         hipLaunchKernelGGL((k_solve_w<TX, TY, TZ, kWavesPerBlock>), dim3(grid), dim3(nt), 0, st, a);
     } else {
-        if ((rc = occupancy_grid(k_solve<TX, TY, TZ, kThreads>, kThreads, &grid))) return rc;
+        if ((rc = occupancy_grid(k_solve<TX, TY, TZ, kThreads, OP>, kThreads, &grid))) return rc;
         if (o && o->grid_blocks > 0) grid = std::min(grid, o->grid_blocks);
         if ((int64_t)grid > ntiles) grid = (int)ntiles;
         if (grid < 1) grid = 1;
         if ((rc = timing_begin(w, o))) return rc;
-        hipLaunchKernelGGL((k_solve<TX, TY, TZ, kThreads>), dim3(grid), dim3(kThreads), 0, st, a);
+        hipLaunchKernelGGL((k_solve<TX, TY, TZ, kThreads, OP>), dim3(grid), dim3(kThreads), 0, st, a);
     }
     HIP_TRY(hipGetLastError());
     if ((rc = timing_end(w, o))) return rc;
@@ -431,7 +438,18 @@ int dispatch_forward(TileShape ts, Workspace& w, const std::vector<Prob>& probs,
 #define EIK_WCASE(a, b, c)                                                                     \
     if (ts.x == a && ts.y == b && ts.z == c)                                                   \
         return forward<a, b, c, true>(w, probs, src_off, ntiles, npts, field, src_idx, src_t0, t, par, o);
-    if (wave_mode(o)) {
+#define EIK_HCASE(a, b, c)                                                                     \
+    if (ts.x == a && ts.y == b && ts.z == c)                                                   \
+        return forward<a, b, c, false, 1>(w, probs, src_off, ntiles, npts, field, src_idx, src_t0, t, par, o);
+#define EIK_TCASE(a, b, c)                                                                     \
+    if (ts.x == a && ts.y == b && ts.z == c)                                                   \
+        return forward<a, b, c, false, 2>(w, probs, src_off, ntiles, npts, field, src_idx, src_t0, t, par, o);
+    const int op = o ? o->op : EIK_OP_DBAR;
+    if (op == EIK_OP_DHAT) {
+        EIK_TILES_2D(EIK_HCASE)
+    } else if (op == EIK_OP_DTILDE) {
+        EIK_TILES_2D(EIK_TCASE)
+    } else if (wave_mode(o)) {
         EIK_WTILES_3D(EIK_WCASE)
         EIK_WTILES_2D(EIK_WCASE)
     } else {
@@ -440,6 +458,8 @@ int dispatch_forward(TileShape ts, Workspace& w, const std::vector<Prob>& probs,
     }
 #undef EIK_CASE
 #undef EIK_WCASE
+#undef EIK_HCASE
+#undef EIK_TCASE
     return fail(EIK_ENOTSUP, "unsupported tile shape");
 }
 
@@ -574,6 +594,8 @@ int eik_solve_batched(int32_t nprob, const eik_grid* grids_host, const int64_t* 
     TileShape ts = pick_tile(grids_host[0].ndim, opts);
     if (!tile_supported(grids_host[0].ndim, ts.x, ts.y, ts.z, wave_mode(opts)))
         return fail(EIK_ENOTSUP, "unsupported tile shape for this ndim");
+    if (opts && opts->op != EIK_OP_DBAR && grids_host[0].ndim != 2)
+        return fail(EIK_ENOTSUP, "the ablation operators are two-dimensional");
     std::vector<Prob> probs;
     int64_t ntiles = 0, npts = 0;
     if ((rc = build_problems(nprob, grids_host, offsets_host, ts, &probs, &ntiles, &npts))) return rc;
@@ -615,6 +637,48 @@ int eik_parents(const eik_grid* g, const double* t, int64_t nsrc, const int64_t*
         hipLaunchKernelGGL(k_parents_mark_src, dim3(blocks_for(nsrc, kThreads)), dim3(kThreads), 0, st,
                            T, src_idx, (long long)nsrc, parents_out);
     HIP_TRY(hipGetLastError());
+    return EIK_OK;
+}
+
+int eik_residual(const eik_grid* g, const double* field, int64_t nsrc, const int64_t* src_idx, const double* t,
+                 int32_t op, int64_t* count_host, double* maxrel_host, void* stream) {
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!field || !t || (nsrc > 0 && !src_idx)) return fail(EIK_EINVAL, "NULL device pointer");
+    if (nsrc < 0) return fail(EIK_EINVAL, "nsrc must be >= 0");
+    if (op < EIK_OP_DBAR || op > EIK_OP_DTILDE) return fail(EIK_EINVAL, "unknown operator");
+    if (op != EIK_OP_DBAR && g->ndim != 2) return fail(EIK_ENOTSUP, "the ablation operators are two-dimensional");
+    Workspace* w = nullptr;
+    if ((rc = get_ws((hipStream_t)stream, &w))) return rc;
+    const int64_t n = (int64_t)g->nx * g->ny * g->nz;
+    if ((rc = grow(&w->mask, &w->mask_cap, n, w->stream))) return rc;
+    hipStream_t st = w->stream;
+    const Prob P = make_prob(*g, pick_tile(g->ndim, nullptr), 0, 0);
+    unsigned long long* out = w->counters + 13;  // [13] count, [14] max rel bits, [15] flags
+    uint32_t* flags = (uint32_t*)(w->counters + 15);
+    hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for(n, kThreads, 8192)), dim3(kThreads), 0, st, (long long)n,
+                       w->mask, (uint8_t)0);
+    hipLaunchKernelGGL(k_clear_residual, dim3(1), dim3(64), 0, st, out);
+    if (nsrc > 0)
+        hipLaunchKernelGGL(k_mark_points, dim3(blocks_for(nsrc, kThreads)), dim3(kThreads), 0, st, src_idx,
+                           (long long)nsrc, (long long)n, w->mask);
+    const dim3 gr(blocks_for(n, kThreads, 8192)), bl(kThreads);
+    if (op == EIK_OP_DHAT) hipLaunchKernelGGL(k_residual<1>, gr, bl, 0, st, P, field, t, w->mask, out, flags);
+    else if (op == EIK_OP_DTILDE) hipLaunchKernelGGL(k_residual<2>, gr, bl, 0, st, P, field, t, w->mask, out, flags);
+    else hipLaunchKernelGGL(k_residual<0>, gr, bl, 0, st, P, field, t, w->mask, out, flags);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    unsigned long long res[2];
+    uint32_t fl = 0;
+    HIP_TRY(hipMemcpy(res, out, sizeof(res), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&fl, flags, sizeof(fl), hipMemcpyDeviceToHost));
+    if (fl & kFlagDomain) return fail(EIK_EDOMAIN, "field value not positive and finite");
+    if (count_host) *count_host = (int64_t)res[0];
+    if (maxrel_host) {
+        double d;
+        std::memcpy(&d, &res[1], sizeof(d));
+        *maxrel_host = d;
+    }
     return EIK_OK;
 }
 
@@ -736,6 +800,7 @@ void eik_release(void) {
         (void)hipFree(w->items);
         (void)hipFree(w->ctr);
         (void)hipFree(w->timeline);
+        (void)hipFree(w->mask);
         (void)hipFree(w->tstate);
         (void)hipFree(w->tkey);
         (void)hipFree(w->scal);

@@ -248,7 +248,9 @@ __device__ __forceinline__ void st_flags(uint8_t* f, uint32_t v) {
     else *f = (uint8_t)v;
 }
 
-template <int TX, int TY, int TZ, int NT>
+// OP selects the operator: 0 the exact monotone d-bar (the solver), 1 d-hat,
+// 2 d-tilde (two-dimensional precision ablation only; see apply_op).
+template <int TX, int TY, int TZ, int NT, int OP = 0>
 __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
     using C = TileCfg<TX, TY, TZ, NT>;
     constexpr int NPT = C::NPT;
@@ -266,6 +268,7 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
     __shared__ uint32_t s_nid[6];
     __shared__ unsigned long long s_face[6];
     __shared__ unsigned int s_upd;
+    __shared__ unsigned long long s_pend;  // smallest value left beyond the bucket (bits)
     __shared__ int s_next;  // tile handed on by the previous run's publish, or -1
 
     const int tid = threadIdx.x;
@@ -349,9 +352,18 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
         }
         if (tid == 0) {
             s_upd = 0u;
+            s_pend = kInfBits;
             s_cnt[0] = 0;
             s_cnt[1] = 0;
         }
+        // Optional bucket horizon (k = S.horizon > 0): a run settles only
+        // values with floor(r / delta) < b + k, b its bucket (with k = 1 the
+        // bucket discipline of delta-stepping).  A lower value never depends on
+        // a higher one (the operator is causal), so nothing below the horizon
+        // is lost; larger candidates are left for a later run of this tile,
+        // keyed by the smallest of them, instead of being written and
+        // propagated now as provisional values.
+        const double hz = S.horizon > 0 ? (double)(s_bucket + S.horizon) : inf64();
 
         // ---- stage the tile and its halo in LDS ----------------------------
         // t starts at +inf everywhere, so every in-grid value read here is a
@@ -426,6 +438,7 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
         // monotone updates is valid).
         int cb = 0;
         int passes = 0;
+        double pend = inf64();
         for (;;) {
             {
                 uint8_t* df = sDirty[cb] + tid * NPT;
@@ -471,19 +484,31 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
                 const double ay = fmin(sT[L - C::SY], sT[L + C::SY]);
                 const double az = C::D3 ? fmin(sT[L - C::SZ], sT[L + C::SZ]) : inf64();
                 bool ch;
-                const double r = update(ax, ay, az, q, q * q, tc, ch);
+                double r;
+                if constexpr (OP == 0) {
+                    r = update(ax, ay, az, q, q * q, tc, ch);
+                    if (ch && !(r * S.inv_delta < hz)) {
+                        pend = fmin(pend, r);
+                        ch = false;
+                    }
+                } else {
+                    r = apply_op<OP>(ax, ay, az, q);
+                    ch = r < tc;
+                }
                 if (ch) {
                     sT[L] = r;
-                    // only neighbours above the new value can depend on it
-                    // (the operator is causal), so only they need another look
+                    // with d-bar only neighbours above the new value can depend
+                    // on it (the operator is causal), so only they need another
+                    // look; the ablation operators mark every neighbour
+                    constexpr bool kAll = OP != 0;
                     uint8_t* nd = sDirty[cb ^ 1];
-                    if (lx > 0 && sT[L - 1] > r) nd[didx<NT, NPT>(p - 1)] = 1;
-                    if (lx < TX - 1 && sT[L + 1] > r) nd[didx<NT, NPT>(p + 1)] = 1;
-                    if (ly > 0 && sT[L - C::SY] > r) nd[didx<NT, NPT>(p - TX)] = 1;
-                    if (ly < TY - 1 && sT[L + C::SY] > r) nd[didx<NT, NPT>(p + TX)] = 1;
+                    if (lx > 0 && (kAll || sT[L - 1] > r)) nd[didx<NT, NPT>(p - 1)] = 1;
+                    if (lx < TX - 1 && (kAll || sT[L + 1] > r)) nd[didx<NT, NPT>(p + 1)] = 1;
+                    if (ly > 0 && (kAll || sT[L - C::SY] > r)) nd[didx<NT, NPT>(p - TX)] = 1;
+                    if (ly < TY - 1 && (kAll || sT[L + C::SY] > r)) nd[didx<NT, NPT>(p + TX)] = 1;
                     if (C::D3) {
-                        if (lz > 0 && sT[L - C::SZ] > r) nd[didx<NT, NPT>(p - TX * TY)] = 1;
-                        if (lz < TZ - 1 && sT[L + C::SZ] > r) nd[didx<NT, NPT>(p + TX * TY)] = 1;
+                        if (lz > 0 && (kAll || sT[L - C::SZ] > r)) nd[didx<NT, NPT>(p - TX * TY)] = 1;
+                        if (lz < TZ - 1 && (kAll || sT[L + C::SZ] > r)) nd[didx<NT, NPT>(p + TX * TY)] = 1;
                     }
                 }
             }
@@ -531,6 +556,7 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
             if (fmin_[f] < inf64()) atomicMin(&s_face[f], (unsigned long long)as_u64(fmin_[f]));
         }
         if (nchg) atomicAdd(&s_upd, nchg);
+        if (pend < inf64()) atomicMin(&s_pend, (unsigned long long)as_u64(pend));
         // every wave's stores complete before the block hands the tile's faces
         // to the neighbours
         stores_done();
@@ -538,7 +564,8 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
 
         // ---- publish: activate neighbours, end the run or hand on ----------
         if (tid < 64) {
-            const int nxt = publish(S, A.tkey, (uint32_t)tile, s_bucket, !visited, s_nb, s_nid, s_face, true);
+            const int nxt = publish(S, A.tkey, (uint32_t)tile, s_bucket, !visited, s_nb, s_nid, s_face, true,
+                                    s_pend);
             if (tid == 0) s_next = nxt;
         }
         if (tid == 0) {
@@ -564,6 +591,70 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
         __hip_atomic_fetch_add(S.counters + 1, my_updates, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(S.counters + 2, my_passes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+}
+
+// ---------------------------------------------------------------------------
+// residual of a solution (the error metric of Table "tab:error")
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill_u8(long long n, uint8_t* a, uint8_t v) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) a[i] = v;
+}
+
+// Clears the residual accumulators: out[0] count, out[1] max, out[2] flags.
+__global__ void k_clear_residual(unsigned long long* out) {
+    if (threadIdx.x < 3) out[threadIdx.x] = 0ull;
+}
+
+__global__ void k_mark_points(const int64_t* idx, long long n, long long npts, uint8_t* mask) {
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    const int64_t i = idx[g];
+    if (i >= 0 && i < npts) mask[i] = 1;
+}
+
+// Counts the non-source points whose time differs from the operator applied
+// to their final neighbours, and the largest relative difference (bits of a
+// non-negative double, atomic max): out[0] count, out[1] max.  Field values
+// that are not positive and finite raise the domain flag.
+template <int OP>
+__global__ void k_residual(Prob P, const double* field, const double* t, const uint8_t* fixed,
+                           unsigned long long* out, uint32_t* flags) {
+    const long long n = (long long)P.nx * P.ny * P.nz;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    unsigned long long cnt = 0, worst = 0;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        if (fixed[i]) continue;
+        bool ok;
+        const double q = field_q(field[i], P.h, P.kind, ok);
+        if (!ok) {
+            __hip_atomic_fetch_or(flags, kFlagDomain, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            continue;
+        }
+        const long long x = i % P.nx, y = (i / P.nx) % P.ny, z = i / ((long long)P.nx * P.ny);
+        const long long sy = P.nx, sz = (long long)P.nx * P.ny;
+        double lo = x > 0 ? t[i - 1] : inf64(), hi = x < P.nx - 1 ? t[i + 1] : inf64();
+        const double ax = lo < hi ? lo : hi;
+        lo = y > 0 ? t[i - sy] : inf64();
+        hi = y < P.ny - 1 ? t[i + sy] : inf64();
+        const double ay = lo < hi ? lo : hi;
+        double az = inf64();
+        if (P.nz > 1) {
+            lo = z > 0 ? t[i - sz] : inf64();
+            hi = z < P.nz - 1 ? t[i + sz] : inf64();
+            az = lo < hi ? lo : hi;
+        }
+        const double r = apply_op<OP>(ax, ay, az, q);
+        const double ti = t[i];
+        if (r != ti) {
+            ++cnt;
+            const unsigned long long rb = as_u64(fabs(r - ti) / fabs(ti)) & ~kSignBit;
+            if (rb > worst) worst = rb;
+        }
+    }
+    if (cnt) __hip_atomic_fetch_add(out, cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (worst) __hip_atomic_fetch_max(out + 1, worst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------

@@ -165,4 +165,40 @@ __device__ __forceinline__ double update(double x, double y, double z, double q,
     return as_f64(G + 2 - (uint64_t)cnt);
 }
 
+// The paper's two explicit two-dimensional formulas (the d-tilde and d-hat
+// columns of Tables "tab:prec_1" and "tab:prec_2"), kept for the precision
+// ablation: they are not monotone in floating point, so an asynchronous solve
+// with them can end in different states for different schedules.  tH, tV are
+// the x- and y-axis minima; q = h/v, c = fl(q*q).
+//   d-tilde: 1/2 (s + sqrt(s^2 - 2 (tH^2 + tV^2 - c))), s = tH + tV;
+//   d-hat:   1/2 ((tH + tV) + sqrt(2c - (tH - tV)^2));
+// both fall back to min(tH, tV) + q when |tH - tV| >= q.
+__device__ __forceinline__ double op_dtilde(double tH, double tV, double q, double c) {
+    if (!(tH < inf64()) && !(tV < inf64())) return inf64();
+    if (fabs(tH - tV) >= q) return (tH < tV ? tH : tV) + q;
+    const double s = tH + tV;
+    const double inner = s * s - 2.0 * ((tH * tH + tV * tV) - c);
+    return 0.5 * (s + __builtin_sqrt(inner));
+}
+__device__ __forceinline__ double op_dhat(double tH, double tV, double q, double c) {
+    if (!(tH < inf64()) && !(tV < inf64())) return inf64();
+    if (fabs(tH - tV) >= q) return (tH < tV ? tH : tV) + q;
+    const double d = tH - tV;
+    const double inner = 2.0 * c - d * d;
+    return 0.5 * ((tH + tV) + __builtin_sqrt(inner));
+}
+
+// Operator selector: 0 exact monotone d-bar (the solver's operator), 1 d-hat,
+// 2 d-tilde.  Returns the value the operator gives from the axis minima.
+template <int OP>
+__device__ __forceinline__ double apply_op(double ax, double ay, double az, double q) {
+    const double c = q * q;
+    if constexpr (OP == 1) return op_dhat(ax, ay, q, c);
+    else if constexpr (OP == 2) return op_dtilde(ax, ay, q, c);
+    else {
+        bool ch;
+        return update(ax, ay, az, q, c, inf64(), ch);
+    }
+}
+
 }  // namespace eik

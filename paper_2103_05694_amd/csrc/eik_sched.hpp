@@ -93,6 +93,7 @@ struct Sched {
     double inv_delta;    // 1/delta, 0 => single bucket
     long long max_visits;  // 0 => unlimited
     int lookahead;       // claims may come from buckets cur .. cur + lookahead
+    int horizon;         // 0, or k: a run settles only values below bucket (its bucket + k)
     unsigned long long* timeline;  // NULL, or [0] start, [1] end, then (time, bucket) per advance
     int timeline_cap;    // advances the timeline can hold
 };
@@ -295,6 +296,9 @@ __device__ __forceinline__ int claim(const Sched& s, int64_t* bucket) {
 // activate the neighbours in parallel.  The live-work count changes once, by
 // (#newly queued neighbours + requeue - 1), before any push makes new items
 // claimable, so it never under-counts.
+// `self_key` (bits of a time, kInfBits for none) requeues the tile itself with
+// at most that key: the run left points whose new values lie beyond its
+// bucket.
 // With `cont`, the lowest-key newly activated neighbour that falls in this
 // run's own bucket is not pushed: it is returned (state Q, counted live and
 // counted running in `bucket`) for this workgroup to run next, which saves a
@@ -302,12 +306,18 @@ __device__ __forceinline__ int claim(const Sched& s, int64_t* bucket) {
 // -1 (the run has then ended), uniform across the wave.
 __device__ __forceinline__ int publish(const Sched& s, uint64_t* tkey, uint32_t tile, int64_t bucket, bool first,
                                        const uint32_t* nb, const uint32_t* nid,
-                                       const unsigned long long* face, bool cont = false) {
+                                       const unsigned long long* face, bool cont = false,
+                                       unsigned long long self_key = kInfBits) {
     const int lane = threadIdx.x & 63;
     uint32_t own = 0;
-    if (lane == 0)
+    if (lane == 0) {
+        // work of this tile left for a later bucket: activate the tile itself
+        // while R still keeps everyone else from pushing it
+        if (self_key != kInfBits)
+            __hip_atomic_fetch_or(s.tstate + tile, kQ, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         own = __hip_atomic_fetch_xor(s.tstate + tile, kR | (first ? kV : 0u), __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_AGENT);
+    }
     // the RMW has returned, so V is visible before any neighbour is activated
     own = __shfl(own, 0);
     const bool requeue = (own & kQ) != 0;
@@ -352,6 +362,7 @@ __device__ __forceinline__ int publish(const Sched& s, uint64_t* tkey, uint32_t 
     if (lane == 0 && requeue) {
         uint64_t kb = __hip_atomic_exchange((unsigned long long*)(tkey + tile), kInfBits, __ATOMIC_RELAXED,
                                             __HIP_MEMORY_SCOPE_AGENT);
+        if (self_key < kb) kb = self_key;
         push_tile(s, tile, kb == kInfBits ? 0.0 : as_f64(kb), bucket);
     }
     if (cl >= 0) return (int)__shfl(n, cl);

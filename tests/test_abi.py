@@ -83,6 +83,30 @@ def test_solve_rejects_bad_counts_and_options(L):
     o = eik_opts()
     o.flags = 8
     assert L.eik_solve(ctypes.byref(g), dummy, 1, dummy, None, dummy, None, ctypes.byref(o), None) == -1
+    o = eik_opts()
+    o.horizon = 5
+    assert L.eik_solve(ctypes.byref(g), dummy, 1, dummy, None, dummy, None, ctypes.byref(o), None) == -1
+    o = eik_opts()
+    o.op = 3                                       # no such operator
+    assert L.eik_solve(ctypes.byref(g), dummy, 1, dummy, None, dummy, None, ctypes.byref(o), None) == -1
+    o = eik_opts()
+    o.op = 1                                       # the explicit formulas are 2D only
+    assert L.eik_solve(ctypes.byref(g), dummy, 1, dummy, None, dummy, None, ctypes.byref(o), None) == -6
+    o = eik_opts()
+    o.op = 2
+    o.flags = 2                                    # ... and block tiles only
+    g2 = _grid(ndim=2, nx=64, ny=64, nz=1)
+    assert L.eik_solve(ctypes.byref(g2), dummy, 1, dummy, None, dummy, None, ctypes.byref(o), None) == -6
+
+
+def test_residual_rejects_bad_arguments(L):
+    g = _grid()
+    dummy = ctypes.c_void_p(16)
+    cnt = ctypes.c_int64(0)
+    assert L.eik_residual(ctypes.byref(g), dummy, 1, dummy, dummy, 5, ctypes.byref(cnt), None, None) == -1
+    assert L.eik_residual(ctypes.byref(g), dummy, 1, dummy, dummy, 1, ctypes.byref(cnt), None, None) == -6
+    assert L.eik_residual(ctypes.byref(g), None, 1, dummy, dummy, 0, ctypes.byref(cnt), None, None) == -1
+    assert L.eik_residual(ctypes.byref(g), dummy, -1, dummy, dummy, 0, ctypes.byref(cnt), None, None) == -1
 
 
 def test_batched_rejects_inconsistent_packing(L):
@@ -104,13 +128,15 @@ def test_batched_rejects_inconsistent_packing(L):
 def test_num_tiles_host_only(L):
     from paper_2103_05694_amd._lib import eik_opts
     g = _grid(nx=512, ny=512, nz=256)
-    assert L.eik_num_tiles(ctypes.byref(g), None) == (512 // 32) * (512 // 8) * (256 // 4)
+    assert L.eik_num_tiles(ctypes.byref(g), None) == (512 // 16) * (512 // 8) * (256 // 8)  # default 16x8x8
     o = eik_opts()
     o.tile[0], o.tile[1], o.tile[2] = 8, 8, 8
     g2 = _grid(nx=33, ny=9, nz=8)
     assert L.eik_num_tiles(ctypes.byref(g2), ctypes.byref(o)) == 5 * 2 * 1
     g3 = _grid(ndim=2, nx=4096, ny=4096, nz=1)
-    assert L.eik_num_tiles(ctypes.byref(g3), None) == (4096 // 64) * (4096 // 16)
+    assert L.eik_num_tiles(ctypes.byref(g3), None) == (4096 // 32) * (4096 // 32)  # default 32x32
+    g4 = _grid(ndim=2, nx=100, ny=33, nz=1)
+    assert L.eik_num_tiles(ctypes.byref(g4), None) == 4 * 2
 
 
 def test_missing_library_fails_loudly(monkeypatch):

@@ -89,9 +89,9 @@ def test_ragged_and_degenerate_shapes(gpu, O, case):
     ref = O.fmm(f, h, src, t0)
     tiles = TILES_2D if f.shape[0] == 1 else TILES_3D
     for tile in tiles:
-        for delta, la in ((0.0, 0), (0.5, 0), (0.25, 3)):
-            t = gpu_solve(gpu, f, h, src, t0, tile=tile, delta=delta, lookahead=la)
-            assert_bitwise(t, ref, f"{name} tile {tile} delta {delta} lookahead {la}")
+        for delta, la, hz in ((0.0, 0, 0), (0.5, 0, 0), (0.25, 3, 0), (0.25, 0, 1), (0.5, 2, 2)):
+            t = gpu_solve(gpu, f, h, src, t0, tile=tile, delta=delta, lookahead=la, horizon=hz)
+            assert_bitwise(t, ref, f"{name} tile {tile} delta {delta} lookahead {la} horizon {hz}")
 
 
 WTILES_3D = [(8, 8, 4), (16, 8, 4), (8, 8, 8), (16, 4, 4)]
@@ -256,3 +256,20 @@ def test_visit_cap_gives_upper_bound(gpu, O):
     assert np.all(t >= ref)
     assert np.isinf(t).any()
     assert t.reshape(-1)[p.src[0]] == 0.0
+
+
+@pytest.mark.parametrize("horizon", [1, 2, 4])
+def test_bucket_horizon(gpu, O, layered_small, horizon):
+    """A run that settles only values below (its bucket + k) and requeues the
+    tile for the rest reaches the same bits for any k and bucket width."""
+    p = layered_small
+    ref = O.fmm(p.field, p.h, p.src)
+    for tile in ((16, 8, 8), (8, 8, 8)):
+        for delta in (0.005, 0.02, 0.1):
+            t = gpu_solve(gpu, p.field, p.h, p.src, tile=tile, delta=delta, horizon=horizon)
+            assert_bitwise(t, ref, f"horizon {horizon} tile {tile} delta {delta}")
+    b = W.blocky_2d(512, nsrc=6, seed=7)
+    refb = O.fmm(b.field, b.h, b.src)
+    for delta in (1.0, 8.0):
+        t = gpu_solve(gpu, b.field, b.h, b.src, tile=(32, 32), delta=delta, horizon=horizon)
+        assert_bitwise(t, refb, f"blocky horizon {horizon} delta {delta}")
