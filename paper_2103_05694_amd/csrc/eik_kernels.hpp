@@ -396,7 +396,6 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
             sQ[p] = q;
             t_in[j] = tv;
         }
-        st_flags<NPT>(sDirty[0] + tid * NPT, kAllDirty);
         st_flags<NPT>(sDirty[1] + tid * NPT, 0u);
         {
             constexpr int NXF = 2 * TY * TZ, NYF = 2 * TX * TZ, NZF = C::D3 ? 2 * TX * TY : 0;
@@ -420,6 +419,36 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
             }
         }
         __syncthreads();
+        // First pass: every point on a first run, in a tile holding a source
+        // (placed before its first run, which already counts as visited) and
+        // with a horizon (points left beyond it last time); otherwise the
+        // interior is still at the fixed point its last run left given the old
+        // halo, so only boundary points next to a halo value below their own
+        // can improve.
+        {
+            uint32_t seed = 0;
+            if (!visited || (st & kS) || S.horizon > 0) {
+                seed = kAllDirty;
+            } else {
+#pragma unroll
+                for (int j = 0; j < NPT; ++j) {
+                    const int p = tid + j * NT;
+                    const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+                    const int L = C::lds(lx, ly, lz);
+                    double hm = inf64();
+                    if (lx == 0) hm = fmin(hm, sT[L - 1]);
+                    if (lx == TX - 1) hm = fmin(hm, sT[L + 1]);
+                    if (ly == 0) hm = fmin(hm, sT[L - C::SY]);
+                    if (ly == TY - 1) hm = fmin(hm, sT[L + C::SY]);
+                    if (C::D3) {
+                        if (lz == 0) hm = fmin(hm, sT[L - C::SZ]);
+                        if (lz == TZ - 1) hm = fmin(hm, sT[L + C::SZ]);
+                    }
+                    if (hm < sT[L]) seed |= 1u << (8 * j);
+                }
+            }
+            st_flags<NPT>(sDirty[0] + tid * NPT, seed);
+        }
         if (tid == 0) {
             const unsigned long long now = wall_clock64();
             ph[1] += now - tm;
@@ -540,13 +569,18 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
                 if (v < t_in[j]) {
                     tstore(A.t + P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x, v);
                     ++nchg;
-                    if (lx == 0) fmin_[0] = fmin(fmin_[0], v);
-                    if (lx == TX - 1) fmin_[1] = fmin(fmin_[1], v);
-                    if (ly == 0) fmin_[2] = fmin(fmin_[2], v);
-                    if (ly == TY - 1) fmin_[3] = fmin(fmin_[3], v);
+                    // a lowered face value matters to the neighbour only where
+                    // it is below the neighbour's own value there (its halo
+                    // cell here, as staged; values only decrease): the
+                    // operator ignores a neighbour above the point it updates
+                    const int L = C::lds(lx, ly, lz);
+                    if (lx == 0 && v < sT[L - 1]) fmin_[0] = fmin(fmin_[0], v);
+                    if (lx == TX - 1 && v < sT[L + 1]) fmin_[1] = fmin(fmin_[1], v);
+                    if (ly == 0 && v < sT[L - C::SY]) fmin_[2] = fmin(fmin_[2], v);
+                    if (ly == TY - 1 && v < sT[L + C::SY]) fmin_[3] = fmin(fmin_[3], v);
                     if (C::D3) {
-                        if (lz == 0) fmin_[4] = fmin(fmin_[4], v);
-                        if (lz == TZ - 1) fmin_[5] = fmin(fmin_[5], v);
+                        if (lz == 0 && v < sT[L - C::SZ]) fmin_[4] = fmin(fmin_[4], v);
+                        if (lz == TZ - 1 && v < sT[L + C::SZ]) fmin_[5] = fmin(fmin_[5], v);
                     }
                 }
             }
