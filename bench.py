@@ -270,6 +270,39 @@ def bench_ablation(args, torch, eik, W) -> dict:
     return out
 
 
+def bench_schedules(args, torch, eik, W) -> dict:
+    """Schedule comparison in one kernel (the paper's work-efficiency view):
+    one bucket (a plain FIFO worklist, the topology-driven extreme), narrow
+    buckets (close to fast marching's order) and the tuned width, on the
+    headline model.  Every operator evaluation is classified against the final
+    times: empty (no change), good (sets the final value), bad (lowers the
+    value to something that is lowered again later)."""
+    p = W.layered_3d(512, 512, 256, h=10.0, seed=2)
+    f = torch.from_numpy(p.field).cuda()
+    src = torch.as_tensor(p.src).cuda()
+    kw = dict(tile=args.tile, grid_blocks=args.grid_blocks, check_status=False)
+    ref = eik.solve(f, p.h, src, delta=args.delta, horizon=args.horizon, **kw)
+    eik.status()
+    out = {"workload": "3D 512x512x256 layered model (the headline solve)", "tile": list(args.tile), "rows": []}
+    for name, delta, hz in (("one bucket (FIFO)", 0.0, 0), ("narrow buckets", args.delta / 8.0, 0),
+                            ("tuned", args.delta, args.horizon)):
+        t = torch.empty_like(f)
+        eik.solve(f, p.h, src, delta=delta, horizon=hz, out=t, **kw)
+        eik.status()
+        torch.cuda.synchronize()
+        eik.solve(f, p.h, src, delta=delta, horizon=hz, out=t, time_kernels=True, **kw)
+        ms = eik.status().kernel_ms
+        eik.solve(f, p.h, src, delta=delta, horizon=hz, out=t, work_ref=ref, **kw)
+        st = eik.status()
+        ev, imp, good = st.evaluations, st.improving, st.final_updates
+        out["rows"].append({"schedule": name, "delta": delta, "horizon": hz, "kernel_ms": ms,
+                            "visits_per_tile": st.tile_visits / max(st.ntiles, 1),
+                            "evaluations_per_point": ev / p.npts, "empty": (ev - imp) / max(ev, 1),
+                            "good": good / max(ev, 1), "bad": (imp - good) / max(ev, 1),
+                            "bitwise_equal": bool(torch.equal(t, ref))})
+    return out
+
+
 def profile_mode(args, torch, eik, W) -> None:
     """A short run for rocprofv3: a plain 1 GiB device copy (counter
     calibration), then a few solves of the headline workload."""
@@ -309,6 +342,7 @@ def main() -> int:
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--parents", action="store_true")
     ap.add_argument("--no-ablation", action="store_true")
+    ap.add_argument("--no-schedules", action="store_true")
     ap.add_argument("--profile-mode", action="store_true")
     args = ap.parse_args()
 
@@ -363,6 +397,10 @@ def main() -> int:
         log("uneven batch")
         extra["uneven_64"] = bench_uneven(args, torch, eik, W)
         log(json.dumps(extra["uneven_64"]))
+    if not args.no_schedules:
+        log("schedule comparison")
+        extra["schedules"] = bench_schedules(args, torch, eik, W)
+        log(json.dumps(extra["schedules"]))
     if not args.no_ablation:
         log("precision ablation")
         extra["ablation_2d"] = bench_ablation(args, torch, eik, W)

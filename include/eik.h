@@ -80,8 +80,8 @@ typedef struct {
 typedef struct {
     double delta;            /* priority bucket width in time units; 0 => one bucket (FIFO) */
     int32_t tile[3];         /* tile shape (x, y, z); zeros => default for ndim (3D 16x8x8,
-                                2D 32x32).  Supported: 3D 32x8x4, 16x8x8, 8x8x8, 64x4x4;
-                                2D 32x32, 64x16, 128x8, 16x16 */
+                                2D 32x32).  Supported: 3D 32x8x4, 16x8x8, 8x8x8, 64x4x4,
+                                16x8x4, 8x8x4, 8x4x4; 2D 32x32, 64x16, 128x8, 16x16, 16x8 */
     int32_t grid_blocks;     /* persistent workgroups; 0 => fill the device */
     int64_t max_tile_visits; /* 0 => unlimited; else stop after this many tile visits (ELIMIT) */
     uint32_t flags;          /* 0 or EIK_FLAG_TIME_KERNELS: record HIP events around the
@@ -97,6 +97,11 @@ typedef struct {
                                 the only one with a schedule-independent result), or, for 2D
                                 grids and block tiles only (precision ablation), EIK_OP_DHAT /
                                 EIK_OP_DTILDE, the paper's explicit formulas */
+    const double* work_ref;  /* NULL, or (device, block tiles) the final times of this very
+                                solve: every operator evaluation is then classified as empty
+                                (no change), good (sets the final value) or bad (lowers the
+                                value to something not yet final), the update classes of the
+                                paper's work-efficiency analysis; see eik_stats */
 } eik_opts;
 
 typedef struct {
@@ -115,6 +120,9 @@ typedef struct {
     int64_t workgroups;      /* persistent workgroups of the last forward launch */
     int64_t bucket_advances; /* times the lowest open priority bucket moved on */
     int64_t handoffs;        /* runs that started on a neighbour handed on by the previous run */
+    int64_t evaluations;     /* with eik_opts.work_ref: operator evaluations in the solve */
+    int64_t improving;       /*   ... of which lowered the value (the rest were empty) */
+    int64_t final_updates;   /*   ... of which set the final value (good; the rest were bad) */
 } eik_stats;
 
 /* Forward solve.

@@ -46,7 +46,7 @@ class eik_opts(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_double), ("tile", ctypes.c_int32 * 3),
                 ("grid_blocks", ctypes.c_int32), ("max_tile_visits", ctypes.c_int64),
                 ("flags", ctypes.c_uint32), ("lookahead", ctypes.c_int32), ("horizon", ctypes.c_int32),
-                ("op", ctypes.c_int32)]
+                ("op", ctypes.c_int32), ("work_ref", ctypes.c_void_p)]
 
 
 class eik_stats(ctypes.Structure):
@@ -56,7 +56,8 @@ class eik_stats(ctypes.Structure):
                 ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_int64),
                 ("phase_us", ctypes.c_double * 4), ("process_us", ctypes.c_double),
                 ("workgroups", ctypes.c_int64), ("bucket_advances", ctypes.c_int64),
-                ("handoffs", ctypes.c_int64)]
+                ("handoffs", ctypes.c_int64), ("evaluations", ctypes.c_int64), ("improving", ctypes.c_int64),
+                ("final_updates", ctypes.c_int64)]
 
 
 class EikError(RuntimeError):

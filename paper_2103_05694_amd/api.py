@@ -40,7 +40,7 @@ def _grid_of(shape: Sequence[int], h: float, kind: str) -> eik_grid:
 def make_opts(delta: float = 0.0, tile: Optional[Sequence[int]] = None, grid_blocks: int = 0,
               max_tile_visits: int = 0, time_kernels: bool = False, lookahead: int = 0,
               wave_tiles: bool = False, timeline: bool = False, op: str = "dbar",
-              horizon: int = 0) -> eik_opts:
+              horizon: int = 0, work_ref: Optional[torch.Tensor] = None) -> eik_opts:
     o = eik_opts()
     o.delta = float(delta)
     t = tuple(tile) if tile else (0, 0, 0)
@@ -55,6 +55,7 @@ def make_opts(delta: float = 0.0, tile: Optional[Sequence[int]] = None, grid_blo
     o.lookahead = int(lookahead)
     o.horizon = int(horizon)
     o.op = _op_code(op)
+    o.work_ref = work_ref.data_ptr() if work_ref is not None else None
     return o
 
 
@@ -153,7 +154,8 @@ def solve(field: torch.Tensor, h: float, sources, t0: Optional[torch.Tensor] = N
           tile: Optional[Sequence[int]] = None, grid_blocks: int = 0, max_tile_visits: int = 0,
           out: Optional[torch.Tensor] = None, parents_out: Optional[torch.Tensor] = None,
           check_status: bool = True, stream=None, time_kernels: bool = False, lookahead: int = 0,
-          wave_tiles: bool = False, timeline: bool = False, op: str = "dbar", horizon: int = 0):
+          wave_tiles: bool = False, timeline: bool = False, op: str = "dbar", horizon: int = 0,
+          work_ref: Optional[torch.Tensor] = None):
     """First-arrival times; returns t, or (t, parents) when parents=True.  `wave_tiles`
     selects the one-tile-per-wave solver (tile shapes 3D 8x8x4, 16x8x4, 8x8x8,
     16x4x4; 2D 16x16, 32x16, 32x8)."""
@@ -171,8 +173,12 @@ def solve(field: torch.Tensor, h: float, sources, t0: Optional[torch.Tensor] = N
     if parents:
         par = parents_out if parents_out is not None else torch.empty(field.shape, dtype=torch.uint8,
                                                                        device=field.device)
+    if work_ref is not None:
+        _check_field(work_ref)
+        if work_ref.shape != field.shape:
+            raise ValueError("work_ref must have the field's shape")
     o = make_opts(delta, tile, grid_blocks, max_tile_visits, time_kernels, lookahead, wave_tiles, timeline, op,
-                  horizon)
+                  horizon, work_ref)
     rc = L.eik_solve(ctypes.byref(g), field.data_ptr(), src.numel(), src.data_ptr(),
                      t0d.data_ptr() if t0d is not None else None, t.data_ptr(),
                      par.data_ptr() if par is not None else None, ctypes.byref(o),

@@ -34,6 +34,10 @@ int fail(int code, const std::string& msg) {
     } while (0)
 
 constexpr int kThreads = 256;
+// Workgroup size of the persistent tile kernels: one thread per point up to
+// 256 (tiles of 64 or 128 points run as one or two waves).
+template <int TX, int TY, int TZ>
+constexpr int tile_threads() { return TX * TY * TZ < kThreads ? TX * TY * TZ : kThreads; }
 constexpr int kRings = 32;
 constexpr int kScalWords = 192;
 constexpr int kTimelineCap = 1 << 16;
@@ -131,7 +135,7 @@ int get_ws(hipStream_t st, Workspace** out) {
     w->device = dev;
     w->stream = st;
     hipError_t e = hipMalloc((void**)&w->scal, kScalWords * sizeof(int32_t));
-    if (e == hipSuccess) e = hipMalloc((void**)&w->counters, 16 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc((void**)&w->counters, kCounters * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMalloc((void**)&w->ctr, sizeof(uint32_t) * kRings * kCtrStride);
     if (e == hipSuccess) e = hipMalloc((void**)&w->timeline, sizeof(unsigned long long) * (2 + 2 * kTimelineCap));
     if (e != hipSuccess) {
@@ -142,7 +146,7 @@ int get_ws(hipStream_t st, Workspace** out) {
     init[kSPoisoned] = 1;  // the first reset initialises the rings
     HIP_TRY(hipMemcpy(w->scal, init, sizeof(init), hipMemcpyHostToDevice));
     HIP_TRY(hipMemset(w->ctr, 0, sizeof(uint32_t) * kRings * kCtrStride));
-    HIP_TRY(hipMemset(w->counters, 0, 16 * sizeof(unsigned long long)));
+    HIP_TRY(hipMemset(w->counters, 0, kCounters * sizeof(unsigned long long)));
     HIP_TRY(hipMemset(w->timeline, 0, sizeof(unsigned long long) * (2 + 2 * kTimelineCap)));
     g_ws[key] = w;
     *out = w;
@@ -239,8 +243,8 @@ struct TileShape {
     int x, y, z;
 };
 
-#define EIK_TILES_3D(X) X(32, 8, 4) X(16, 8, 8) X(8, 8, 8) X(64, 4, 4)
-#define EIK_TILES_2D(X) X(32, 32, 1) X(64, 16, 1) X(128, 8, 1) X(16, 16, 1)
+#define EIK_TILES_3D(X) X(32, 8, 4) X(16, 8, 8) X(8, 8, 8) X(64, 4, 4) X(16, 8, 4) X(8, 8, 4) X(8, 4, 4)
+#define EIK_TILES_2D(X) X(32, 32, 1) X(64, 16, 1) X(128, 8, 1) X(16, 16, 1) X(16, 8, 1)
 // one tile per wave (EIK_FLAG_WAVE_TILES)
 #define EIK_WTILES_3D(X) X(8, 8, 4) X(16, 8, 4) X(8, 8, 8) X(16, 4, 4)
 #define EIK_WTILES_2D(X) X(16, 16, 1) X(32, 16, 1) X(32, 8, 1)
@@ -291,6 +295,8 @@ int check_opts(const eik_opts* o) {
     if (o->lookahead < 0 || o->lookahead > 8) return fail(EIK_EINVAL, "lookahead must be in 0..8");
     if (o->op < EIK_OP_DBAR || o->op > EIK_OP_DTILDE) return fail(EIK_EINVAL, "unknown operator");
     if (o->horizon < 0 || o->horizon > 4) return fail(EIK_EINVAL, "horizon must be in 0..4");
+    if (o->work_ref && (wave_mode(o) || o->op != EIK_OP_DBAR))
+        return fail(EIK_ENOTSUP, "work classification runs with block tiles and d-bar only");
     if (o->op != EIK_OP_DBAR && wave_mode(o))
         return fail(EIK_ENOTSUP, "the ablation operators run with block tiles only");
     return EIK_OK;
@@ -395,6 +401,7 @@ int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int6
     a.field = field;
     a.t = t;
     a.tkey = w.tkey;
+    a.work_ref = o ? o->work_ref : nullptr;
     a.s = s;
     int grid = 0;
     if constexpr (WAVE) {
@@ -407,12 +414,27 @@ int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int6
         if ((rc = timing_begin(w, o))) return rc;
         hipLaunchKernelGGL((k_solve_w<TX, TY, TZ, kWavesPerBlock>), dim3(grid), dim3(nt), 0, st, a);
     } else {
-        if ((rc = occupancy_grid(k_solve<TX, TY, TZ, kThreads, OP>, kThreads, &grid))) return rc;
+        constexpr int nt = tile_threads<TX, TY, TZ>();
+        const bool count = a.work_ref != nullptr;
+        if constexpr (OP == EIK_OP_DBAR) {
+            if (count) {
+                if ((rc = occupancy_grid(k_solve<TX, TY, TZ, nt, OP, true>, nt, &grid))) return rc;
+            } else {
+                if ((rc = occupancy_grid(k_solve<TX, TY, TZ, nt, OP>, nt, &grid))) return rc;
+            }
+        } else {
+            if ((rc = occupancy_grid(k_solve<TX, TY, TZ, nt, OP>, nt, &grid))) return rc;
+        }
         if (o && o->grid_blocks > 0) grid = std::min(grid, o->grid_blocks);
         if ((int64_t)grid > ntiles) grid = (int)ntiles;
         if (grid < 1) grid = 1;
         if ((rc = timing_begin(w, o))) return rc;
-        hipLaunchKernelGGL((k_solve<TX, TY, TZ, kThreads, OP>), dim3(grid), dim3(kThreads), 0, st, a);
+        if constexpr (OP == EIK_OP_DBAR) {
+            if (count) hipLaunchKernelGGL((k_solve<TX, TY, TZ, nt, OP, true>), dim3(grid), dim3(nt), 0, st, a);
+            else hipLaunchKernelGGL((k_solve<TX, TY, TZ, nt, OP>), dim3(grid), dim3(nt), 0, st, a);
+        } else {
+            hipLaunchKernelGGL((k_solve<TX, TY, TZ, nt, OP>), dim3(grid), dim3(nt), 0, st, a);
+        }
     }
     HIP_TRY(hipGetLastError());
     if ((rc = timing_end(w, o))) return rc;
@@ -499,12 +521,13 @@ int adjoint(Workspace& w, const std::vector<Prob>& probs, int64_t ntiles, int64_
     a.tref_bits = tref;
     a.s = s;
     int grid = 0;
-    if ((rc = occupancy_grid(k_adjoint<TX, TY, TZ, kThreads>, kThreads, &grid))) return rc;
+    constexpr int nt = tile_threads<TX, TY, TZ>();
+    if ((rc = occupancy_grid(k_adjoint<TX, TY, TZ, nt>, nt, &grid))) return rc;
     if (o && o->grid_blocks > 0) grid = std::min(grid, o->grid_blocks);
     if ((int64_t)grid > ntiles) grid = (int)ntiles;
     if (grid < 1) grid = 1;
     if ((rc = timing_begin(w, o))) return rc;
-    hipLaunchKernelGGL((k_adjoint<TX, TY, TZ, kThreads>), dim3(grid), dim3(kThreads), 0, st, a);
+    hipLaunchKernelGGL((k_adjoint<TX, TY, TZ, nt>), dim3(grid), dim3(nt), 0, st, a);
     HIP_TRY(hipGetLastError());
     if ((rc = timing_end(w, o))) return rc;
     w.last_kind = 2;
@@ -730,7 +753,7 @@ int eik_status(void* stream, eik_stats* out) {
     if ((rc = get_ws((hipStream_t)stream, &w))) return rc;
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
     int32_t sc[kScalWords];
-    unsigned long long ctr[16];
+    unsigned long long ctr[kCounters];
     HIP_TRY(hipMemcpy(sc, w->scal, sizeof(sc), hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(ctr, w->counters, sizeof(ctr), hipMemcpyDeviceToHost));
     uint32_t flags = (uint32_t)sc[kSFlags];
@@ -753,6 +776,9 @@ int eik_status(void* stream, eik_stats* out) {
         out->workgroups = (int64_t)ctr[10];
         out->bucket_advances = (int64_t)ctr[11];
         out->handoffs = (int64_t)ctr[12];
+        out->evaluations = (int64_t)ctr[16];
+        out->improving = (int64_t)ctr[17];
+        out->final_updates = (int64_t)ctr[18];
         if (w->ev_used) {
             double sum = 0.0;
             for (size_t i = 0; i < w->ev_used; ++i) {
@@ -774,7 +800,7 @@ int eik_timeline(void* stream, int32_t cap, double* t_us_host, int64_t* bucket_h
     int rc;
     if ((rc = get_ws((hipStream_t)stream, &w))) return rc;
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
-    unsigned long long ctr[16];
+    unsigned long long ctr[kCounters];
     HIP_TRY(hipMemcpy(ctr, w->counters, sizeof(ctr), hipMemcpyDeviceToHost));
     const int64_t n = std::min<int64_t>((int64_t)ctr[11], kTimelineCap);
     std::vector<unsigned long long> tl((size_t)(2 + 2 * n));

@@ -46,6 +46,7 @@ struct SolveArgs {
     const double* field;
     double* t;
     uint64_t* tkey;          // [ntiles] pending requeue key (bits of a positive double)
+    const double* work_ref;  // NULL, or the final times: classify every evaluation
     Sched s;
 };
 
@@ -118,7 +119,7 @@ __global__ void k_reset(Sched s, uint64_t* tkey, int ntiles, int32_t* srclist_co
         *s.cur = 0;
         *s.pending = 0;
         *s.flags = 0u;
-        for (int i = 0; i < 16; ++i) s.counters[i] = 0ull;
+        for (int i = 0; i < kCounters; ++i) s.counters[i] = 0ull;
         *srclist_count = 0;
     }
 }
@@ -250,7 +251,8 @@ __device__ __forceinline__ void st_flags(uint8_t* f, uint32_t v) {
 
 // OP selects the operator: 0 the exact monotone d-bar (the solver), 1 d-hat,
 // 2 d-tilde (two-dimensional precision ablation only; see apply_op).
-template <int TX, int TY, int TZ, int NT, int OP = 0>
+// COUNT adds the work classification (A.work_ref must then be set).
+template <int TX, int TY, int TZ, int NT, int OP = 0, bool COUNT = false>
 __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
     using C = TileCfg<TX, TY, TZ, NT>;
     constexpr int NPT = C::NPT;
@@ -279,6 +281,9 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
     // 100 MHz wall clock: [0] claim, [1] stage, [2] relax, [3] write + publish
     unsigned long long my_visits = 0, my_updates = 0, my_passes = 0, my_cont = 0;
     unsigned long long ph[6] = {0, 0, 0, 0, 0, 0};
+    // per-wave work classification (with A.work_ref): operator evaluations,
+    // those that lowered the value, those that set the final value
+    unsigned long long w_eval = 0, w_imp = 0, w_good = 0;
     unsigned long long tm = wall_clock64();
     if (tid == 0) {
         s_next = -1;
@@ -524,6 +529,16 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
                     r = apply_op<OP>(ax, ay, az, q);
                     ch = r < tc;
                 }
+                if constexpr (COUNT) {
+                    bool good = false;
+                    if (ch) {
+                        const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+                        good = r == A.work_ref[P.pt_off + ((int64_t)gz * P.ny + gy) * P.nx + gx];
+                    }
+                    w_eval += __popcll(__ballot(true));
+                    w_imp += __popcll(__ballot(ch));
+                    w_good += __popcll(__ballot(good));
+                }
                 if (ch) {
                     sT[L] = r;
                     // with d-bar only neighbours above the new value can depend
@@ -610,6 +625,11 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
             tm = now;
         }
         __syncthreads();
+    }
+    if (COUNT && lane == 0) {
+        __hip_atomic_fetch_add(S.counters + 16, w_eval, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(S.counters + 17, w_imp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(S.counters + 18, w_good, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (tid == 0) {
         ph[0] += wall_clock64() - tm;

@@ -113,3 +113,31 @@ def test_ablation_schedules(gpu, O):
             # against the exact solution: within the operators' rounding
             rel = np.max(np.abs(tn - ref[0]) / np.maximum(ref[0], 1.0))
             assert rel < 1e-12, (op, sch, rel)
+
+
+@pytest.mark.parametrize("delta,horizon", [(0.0, 0), (0.005, 0), (0.05, 0), (0.02, 1)])
+def test_work_classification(gpu, O, delta, horizon):
+    """Every non-source point receives its final value exactly once (a later
+    evaluation cannot lower it further), so the good updates count the
+    non-source points; empty and bad updates are the rest."""
+    p = W.layered_3d(70, 50, 40, h=10.0, seed=3, sigma=3.0)
+    f = torch.from_numpy(p.field).cuda()
+    src = torch.as_tensor(p.src)
+    ref = gpu.solve(f, p.h, src, delta=0.02, tile=(16, 8, 8))
+    for tile in ((16, 8, 8), (8, 8, 8), (8, 4, 4)):
+        t = gpu.solve(f, p.h, src, delta=delta, horizon=horizon, tile=tile, work_ref=ref, check_status=False)
+        st = gpu.status()
+        assert torch.equal(t, ref)
+        assert st.final_updates == p.npts - len(p.src)
+        assert st.evaluations >= st.improving >= st.final_updates
+    fo = torch.from_numpy(O.fmm(p.field, p.h, p.src)).cuda()
+    assert torch.equal(ref, fo)
+
+
+def test_work_classification_needs_block_tiles_and_dbar(gpu):
+    f = torch.ones(64, 64, dtype=torch.float64, device="cuda")
+    ref = gpu.solve(f, 1.0, torch.tensor([0]))
+    with pytest.raises(gpu.EikError):
+        gpu.solve(f, 1.0, torch.tensor([0]), op="dhat", work_ref=ref)
+    with pytest.raises(gpu.EikError):
+        gpu.solve(f, 1.0, torch.tensor([0]), wave_tiles=True, work_ref=ref)

@@ -16,8 +16,8 @@ import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-TILES_3D = [(32, 8, 4), (16, 8, 8), (8, 8, 8), (64, 4, 4)]
-TILES_2D = [(64, 16), (32, 32), (128, 8), (16, 16)]
+TILES_3D = [(32, 8, 4), (16, 8, 8), (8, 8, 8), (64, 4, 4), (16, 8, 4), (8, 8, 4), (8, 4, 4)]
+TILES_2D = [(64, 16), (32, 32), (128, 8), (16, 16), (16, 8)]
 
 
 @pytest.fixture(scope="module")
