@@ -65,7 +65,10 @@ class ShotBatch:
                            grid_blocks=self.grid_blocks, stream=self.stream)
 
     def step(self) -> None:
-        """Enqueue one batched forward + adjoint (eager launches)."""
+        """Enqueue one batched forward + adjoint (eager launches).  The batch's
+        stream first waits for the caller's stream, so work the caller queued
+        on its outputs (copies, reads) finishes before they are overwritten."""
+        self.stream.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(self.stream):
             self._enqueue()
 
@@ -83,9 +86,11 @@ class ShotBatch:
         self.stream.synchronize()
 
     def replay(self) -> None:
-        """One launch of the captured step, on this batch's stream."""
+        """One launch of the captured step, on this batch's stream, after the
+        caller's stream (as in step)."""
         if self.graph is None:
             self.capture()
+        self.stream.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(self.stream):
             self.graph.replay()
 

