@@ -163,11 +163,11 @@ def bench_tomography(args, torch, eik, W) -> dict:
     eik.status(sb.stream)
     t_plain = torch.empty_like(sb.t)
     g_plain = torch.empty_like(sb.grad)
-    sb.plain_step(t_plain, g_plain)
+    sb.plain_step(t_plain, g_plain, **args.shot_cfg)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        sb.plain_step(t_plain, g_plain)
+        sb.plain_step(t_plain, g_plain, **args.shot_cfg)
     torch.cuda.synchronize()
     plain_s = (time.perf_counter() - t0) / reps
     eik.status()
@@ -175,7 +175,7 @@ def bench_tomography(args, torch, eik, W) -> dict:
     same_g = bool(torch.equal(g_plain, sb.grad))
     return {"workload": f"tomography {args.shots} shots on 256x256x128, 1024 surface receivers",
             "shots_per_s_batched_graph": args.shots / batched_s,
-            "shots_per_s_plain": args.shots / plain_s,
+            "shots_per_s_plain": args.shots / plain_s, "plain_config": "per shot, single-shot tuning",
             "speedup": plain_s / batched_s, "ms_per_batch_graph": batched_s * 1e3,
             "ms_per_batch_plain": plain_s * 1e3, "bitwise_equal_t": same_t,
             "bitwise_equal_grad": same_g, "loss": sb.loss()}
@@ -223,11 +223,11 @@ def bench_uneven(args, torch, eik, W) -> dict:
     eik.status(sb.stream)
     t_plain = torch.empty_like(sb.t)
     g_plain = torch.empty_like(sb.grad)
-    sb.plain_step(t_plain, g_plain)
+    sb.plain_step(t_plain, g_plain, **args.shot_cfg)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        sb.plain_step(t_plain, g_plain)
+        sb.plain_step(t_plain, g_plain, **args.shot_cfg)
     torch.cuda.synchronize()
     plain_s = (time.perf_counter() - t0) / reps
     eik.status()
@@ -371,7 +371,8 @@ def main() -> int:
         args.grid_blocks = int(cfg.get("grid_blocks", 0)) if cfg else 0
     if args.horizon is None:
         args.horizon = int(cfg.get("horizon", 0)) if cfg else 0
-    tcfg = autotune.lookup((128, 256, 256), "slowness")
+    tcfg = autotune.lookup_batch(args.shots, (128, 256, 256), "slowness") or \
+        autotune.lookup((128, 256, 256), "slowness")
     if args.tomo_tile is not None:
         args.tomo_tile = tuple(int(x) for x in args.tomo_tile.lower().split("x"))
     else:
@@ -380,6 +381,10 @@ def main() -> int:
         args.tomo_delta = tcfg["delta"] if tcfg else 0.02
     args.tomo_grid_blocks = int(tcfg.get("grid_blocks", 0)) if tcfg else 0
     args.tomo_horizon = int(tcfg.get("horizon", 0)) if tcfg else 0
+    # the per-shot baseline runs with the single-shot tuning (its best), not the batch's
+    scfg = autotune.lookup((128, 256, 256), "slowness")
+    args.shot_cfg = (dict(delta=scfg["delta"], tile=tuple(scfg["tile"]), grid_blocks=int(scfg.get("grid_blocks", 0)),
+                          horizon=int(scfg.get("horizon", 0))) if scfg else {})
 
     if args.profile_mode:
         profile_mode(args, torch, eik, W)

@@ -107,6 +107,66 @@ def tune(field: torch.Tensor, h: float, sources, kind: str = "speed",
     return entry
 
 
+def _batch_key(nshots: int, shape: Sequence[int], kind: str) -> str:
+    return f"{ARCH}:batch{int(nshots)}:{len(shape)}d:{'x'.join(str(int(s)) for s in shape)}:{kind}"
+
+
+def lookup_batch(nshots: int, shape: Sequence[int], kind: str = "slowness") -> Optional[dict]:
+    """Cached best configuration for a batch of `nshots` shots of this shape."""
+    return _load().get(_batch_key(nshots, shape, kind))
+
+
+def tune_batch(fields: Sequence[torch.Tensor], h: float, sources, receivers, kind: str = "slowness",
+               tiles: Optional[Iterable[Tuple[int, ...]]] = None,
+               delta_factors: Sequence[float] = (0.25, 0.5, 1.0, 2.0, 4.0),
+               grid_blocks: Sequence[int] = (0,), reps: int = 2, save: bool = True, log=print) -> dict:
+    """Time the whole batched step (forward with parents, misfit gradient,
+    adjoint) for every (tile, delta, grid size) candidate; a batch has many
+    times the parallel work of one shot, so its best trade-off differs.  All
+    candidates must agree bitwise (times and gradient)."""
+    from .batch import ShotBatch
+    nd = fields[0].dim()
+    tiles = list(tiles) if tiles is not None else TILES[nd]
+    f64 = fields[0].to(torch.float64)
+    q = (h / f64) if kind == "speed" else (h * f64)
+    qmed = float(q.flatten()[:: max(q.numel() // 100000, 1)].median())
+    ref = None
+    results: List[dict] = []
+    for tile in tiles:
+        edge = min(tile[:nd])
+        for fac in delta_factors:
+            delta = fac * qmed * edge
+            for gb in grid_blocks:
+                sb = ShotBatch(fields, h, sources, receivers, kind=kind, delta=delta, tile=tile, grid_blocks=gb)
+                sb.step()
+                sb.sync()
+                api.status(sb.stream)
+                if ref is None:
+                    ref = (sb.t.clone(), sb.grad.clone())
+                elif not (torch.equal(ref[0], sb.t) and torch.equal(ref[1], sb.grad)):
+                    raise RuntimeError(f"batch candidate tile={tile} delta={delta} grid={gb} changed the result")
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    sb.step()
+                sb.sync()
+                sec = (time.perf_counter() - t0) / reps
+                api.status(sb.stream)
+                results.append({"tile": list(tile), "delta": delta, "delta_factor": fac, "grid_blocks": gb,
+                                "horizon": 0, "ms": sec * 1e3})
+                log(f"  batch tile {tile} delta {delta:.4g} grid {gb}: {sec * 1e3:.2f} ms")
+                del sb
+    best = min(results, key=lambda r: r["ms"])
+    entry = {"tile": best["tile"], "delta": best["delta"], "grid_blocks": best["grid_blocks"], "horizon": 0,
+             "ms": best["ms"], "qmed": qmed, "candidates": results}
+    if save:
+        cache = _load()
+        cache[_batch_key(len(fields), fields[0].shape, kind)] = entry
+        with open(CACHE, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+    return entry
+
+
 def _main(argv: List[str]) -> int:
     root = os.path.dirname(HERE)
     sys.path.insert(0, root)
@@ -117,6 +177,15 @@ def _main(argv: List[str]) -> int:
             p = W.layered_3d()
         elif name == "layered256":
             p = W.layered_3d(256, 256, 128)
+        elif name == "tomo256x32":
+            c = W.tomography(256, 256, 128, nshots=32, seed=5)
+            f = torch.from_numpy(c.s0).cuda()
+            rec = torch.as_tensor(c.receivers).cuda()
+            print("tuning the 32-shot tomography batch (forward + adjoint)", flush=True)
+            e = tune_batch([f] * 32, c.h, [torch.tensor([int(s)]) for s in c.sources], [rec] * 32,
+                           log=lambda s: print(s, flush=True))
+            print(json.dumps({k: v for k, v in e.items() if k != "candidates"}), flush=True)
+            continue
         elif name == "tomo256":
             c = W.tomography(256, 256, 128, nshots=1, seed=5)
             f = torch.from_numpy(c.s0).cuda()

@@ -102,9 +102,16 @@ class ShotBatch:
         return 0.5 * float((r * r).sum())
 
     # -- reference: the same work one shot at a time ---------------------------
-    def plain_step(self, t_out: torch.Tensor, grad_out: torch.Tensor) -> None:
+    def plain_step(self, t_out: torch.Tensor, grad_out: torch.Tensor, delta: Optional[float] = None,
+                   tile=None, grid_blocks: Optional[int] = None, horizon: Optional[int] = None) -> None:
         """Per-shot eik_solve + eik_adjoint launches on the current stream,
-        writing into packed outputs."""
+        writing into packed outputs.  The launch parameters default to the
+        batch's; a single shot may prefer others (it has far less parallel
+        work), and none of them changes the results."""
+        delta = self.delta if delta is None else delta
+        tile = self.tile if tile is None else tile
+        grid_blocks = self.grid_blocks if grid_blocks is None else grid_blocks
+        horizon = self.horizon if horizon is None else horizon
         tv = self.b.views(t_out)
         gv = self.b.views(grad_out)
         g = torch.zeros_like(t_out)
@@ -112,14 +119,14 @@ class ShotBatch:
         rec_off = 0
         for i in range(self.nshots):
             t, par = api.solve(self.fields[i], self.hs[i], self.sources[i], kind=self.kind, parents=True,
-                               delta=self.delta, tile=self.tile, grid_blocks=self.grid_blocks,
-                               horizon=self.horizon, out=tv[i], check_status=False)
+                               delta=delta, tile=tile, grid_blocks=grid_blocks, horizon=horizon, out=tv[i],
+                               check_status=False)
             r = self.rec_local[i]
             nr = r.numel()
             gvv[i].view(-1).index_copy_(0, r, t.view(-1).index_select(0, r) - self.t_obs[rec_off:rec_off + nr])
             rec_off += nr
-            api.adjoint(self.fields[i], self.hs[i], t, par, gvv[i], kind=self.kind, delta=self.delta,
-                        tile=self.tile, grid_blocks=self.grid_blocks, out=gv[i], check_status=False)
+            api.adjoint(self.fields[i], self.hs[i], t, par, gvv[i], kind=self.kind, delta=delta,
+                        tile=tile, grid_blocks=grid_blocks, out=gv[i], check_status=False)
 
     def shot_views(self, packed: torch.Tensor) -> List[torch.Tensor]:
         return self.b.views(packed)

@@ -25,9 +25,9 @@ def O(oracle_lib):
     return oracle_lib
 
 
-def tuned(shape, kind, default_tile, default_delta):
+def tuned(shape, kind, default_tile, default_delta, nshots=32):
     from paper_2103_05694_amd import autotune
-    cfg = autotune.lookup(shape, kind)
+    cfg = autotune.lookup_batch(nshots, shape, kind) or autotune.lookup(shape, kind)
     if not cfg:
         return dict(tile=default_tile, delta=default_delta, grid_blocks=0, horizon=0)
     return dict(tile=tuple(cfg["tile"]), delta=cfg["delta"], grid_blocks=int(cfg.get("grid_blocks", 0)),
