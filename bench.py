@@ -142,14 +142,14 @@ def bench_tomography(args, torch, eik, W) -> dict:
     rec = torch.as_tensor(case.receivers).cuda()
     obs = ShotBatch([s_true] * args.shots, case.h, srcs, [rec] * args.shots, kind="slowness",
                     delta=args.tomo_delta, tile=args.tomo_tile, grid_blocks=args.tomo_grid_blocks,
-                    horizon=args.tomo_horizon)
+                    horizon=args.tomo_horizon, **args.adj_cfg)
     obs.step()
     obs.sync()
     eik.status(obs.stream)
     t_obs = [v.reshape(-1).index_select(0, rec) for v in obs.shot_views(obs.t)]
     sb = ShotBatch([s0] * args.shots, case.h, srcs, [rec] * args.shots, t_obs=t_obs, kind="slowness",
                    delta=args.tomo_delta, tile=args.tomo_tile, grid_blocks=args.tomo_grid_blocks,
-                   horizon=args.tomo_horizon)
+                   horizon=args.tomo_horizon, **args.adj_cfg)
     sb.capture()
     reps = max(args.steps // 4, 2)
     for _ in range(2):
@@ -203,14 +203,15 @@ def bench_uneven(args, torch, eik, W) -> dict:
         recs.append(torch.as_tensor(W.flat_index(RX.ravel(), RY.ravel(), 0, p.nx, p.ny)).cuda())
     npts = sum(p.npts for p in shots)
     obs = ShotBatch(fields_true, 10.0, srcs, recs, kind="slowness", delta=args.tomo_delta, tile=args.tomo_tile,
-                    grid_blocks=args.tomo_grid_blocks, horizon=args.tomo_horizon)
+                    grid_blocks=args.tomo_grid_blocks, horizon=args.tomo_horizon, **args.adj_cfg)
     obs.step()
     obs.sync()
     eik.status(obs.stream)
     t_obs = [v.reshape(-1).index_select(0, r) for v, r in zip(obs.shot_views(obs.t), recs)]
     del obs
     sb = ShotBatch(fields, 10.0, srcs, recs, t_obs=t_obs, kind="slowness", delta=args.tomo_delta,
-                   tile=args.tomo_tile, grid_blocks=args.tomo_grid_blocks, horizon=args.tomo_horizon)
+                   tile=args.tomo_tile, grid_blocks=args.tomo_grid_blocks, horizon=args.tomo_horizon,
+                   **args.adj_cfg)
     sb.capture()
     reps = max(args.steps // 8, 2)
     sb.replay()
@@ -381,10 +382,15 @@ def main() -> int:
         args.tomo_delta = tcfg["delta"] if tcfg else 0.02
     args.tomo_grid_blocks = int(tcfg.get("grid_blocks", 0)) if tcfg else 0
     args.tomo_horizon = int(tcfg.get("horizon", 0)) if tcfg else 0
+    args.adj_cfg = {}
+    if tcfg and "adj_delta" in tcfg:
+        args.adj_cfg = dict(adj_delta=tcfg["adj_delta"], adj_tile=tuple(tcfg["adj_tile"]),
+                            adj_grid_blocks=int(tcfg.get("adj_grid_blocks", 0)))
     # the per-shot baseline runs with the single-shot tuning (its best), not the batch's
     scfg = autotune.lookup((128, 256, 256), "slowness")
     args.shot_cfg = (dict(delta=scfg["delta"], tile=tuple(scfg["tile"]), grid_blocks=int(scfg.get("grid_blocks", 0)),
                           horizon=int(scfg.get("horizon", 0))) if scfg else {})
+    args.shot_cfg.update(args.adj_cfg)
 
     if args.profile_mode:
         profile_mode(args, torch, eik, W)

@@ -119,46 +119,71 @@ def lookup_batch(nshots: int, shape: Sequence[int], kind: str = "slowness") -> O
 def tune_batch(fields: Sequence[torch.Tensor], h: float, sources, receivers, kind: str = "slowness",
                tiles: Optional[Iterable[Tuple[int, ...]]] = None,
                delta_factors: Sequence[float] = (0.25, 0.5, 1.0, 2.0, 4.0),
+               adj_delta_factors: Sequence[float] = (0.0, 0.5, 1.0, 4.0),
                grid_blocks: Sequence[int] = (0,), reps: int = 2, save: bool = True, log=print) -> dict:
-    """Time the whole batched step (forward with parents, misfit gradient,
-    adjoint) for every (tile, delta, grid size) candidate; a batch has many
-    times the parallel work of one shot, so its best trade-off differs.  All
-    candidates must agree bitwise (times and gradient)."""
-    from .batch import ShotBatch
+    """Tune a batch of shots (forward with parents, then the adjoint) in one
+    persistent launch each: a batch has many times the parallel work of one
+    shot, so its best trade-off differs, and the readiness-driven adjoint is
+    tuned on its own.  All candidates must agree bitwise."""
     nd = fields[0].dim()
     tiles = list(tiles) if tiles is not None else TILES[nd]
     f64 = fields[0].to(torch.float64)
     q = (h / f64) if kind == "speed" else (h * f64)
     qmed = float(q.flatten()[:: max(q.numel() // 100000, 1)].median())
+    b = api.pack(fields, [h] * len(fields), sources, kind)
+    t = torch.empty(b.npts, dtype=torch.float64, device=b.field.device)
+    par = torch.empty(b.npts, dtype=torch.uint8, device=b.field.device)
+    g = torch.zeros_like(t)
+    offs = [int(b.offsets[i]) for i in range(len(fields))]
+    rec = torch.cat([torch.as_tensor(r, device=t.device).reshape(-1) + o for r, o in zip(receivers, offs)])
+    g[rec] = 1.0
+    grad = torch.empty_like(t)
+    fwd: List[dict] = []
     ref = None
-    results: List[dict] = []
     for tile in tiles:
         edge = min(tile[:nd])
         for fac in delta_factors:
             delta = fac * qmed * edge
             for gb in grid_blocks:
-                sb = ShotBatch(fields, h, sources, receivers, kind=kind, delta=delta, tile=tile, grid_blocks=gb)
-                sb.step()
-                sb.sync()
-                api.status(sb.stream)
+                fn = lambda: api.solve_packed(b, t, par, delta, tile, grid_blocks=gb)
+                fn()
+                api.status()
                 if ref is None:
-                    ref = (sb.t.clone(), sb.grad.clone())
-                elif not (torch.equal(ref[0], sb.t) and torch.equal(ref[1], sb.grad)):
-                    raise RuntimeError(f"batch candidate tile={tile} delta={delta} grid={gb} changed the result")
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                for _ in range(reps):
-                    sb.step()
-                sb.sync()
-                sec = (time.perf_counter() - t0) / reps
-                api.status(sb.stream)
-                results.append({"tile": list(tile), "delta": delta, "delta_factor": fac, "grid_blocks": gb,
-                                "horizon": 0, "ms": sec * 1e3})
-                log(f"  batch tile {tile} delta {delta:.4g} grid {gb}: {sec * 1e3:.2f} ms")
-                del sb
-    best = min(results, key=lambda r: r["ms"])
-    entry = {"tile": best["tile"], "delta": best["delta"], "grid_blocks": best["grid_blocks"], "horizon": 0,
-             "ms": best["ms"], "qmed": qmed, "candidates": results}
+                    ref = (t.clone(), par.clone())
+                elif not (torch.equal(ref[0], t) and torch.equal(ref[1], par)):
+                    raise RuntimeError(f"batch forward tile={tile} delta={delta} grid={gb} changed the result")
+                sec = _time(fn, reps)
+                api.status()
+                fwd.append({"tile": list(tile), "delta": delta, "delta_factor": fac, "grid_blocks": gb,
+                            "ms": sec * 1e3})
+                log(f"  batch forward tile {tile} delta {delta:.4g} grid {gb}: {sec * 1e3:.2f} ms")
+    t.copy_(ref[0])
+    par.copy_(ref[1])
+    adj: List[dict] = []
+    gref = None
+    for tile in tiles:
+        edge = min(tile[:nd])
+        for fac in adj_delta_factors:
+            delta = fac * qmed * edge
+            for gb in grid_blocks:
+                fn = lambda: api.adjoint_packed(b, t, par, g, grad, delta=delta, tile=tile, grid_blocks=gb)
+                fn()
+                api.status()
+                if gref is None:
+                    gref = grad.clone()
+                elif not torch.equal(gref, grad):
+                    raise RuntimeError(f"batch adjoint tile={tile} delta={delta} grid={gb} changed the result")
+                sec = _time(fn, reps)
+                api.status()
+                adj.append({"tile": list(tile), "delta": delta, "delta_factor": fac, "grid_blocks": gb,
+                            "ms": sec * 1e3})
+                log(f"  batch adjoint tile {tile} delta {delta:.4g} grid {gb}: {sec * 1e3:.2f} ms")
+    bf = min(fwd, key=lambda r: r["ms"])
+    ba = min(adj, key=lambda r: r["ms"])
+    entry = {"tile": bf["tile"], "delta": bf["delta"], "grid_blocks": bf["grid_blocks"], "horizon": 0,
+             "adj_tile": ba["tile"], "adj_delta": ba["delta"], "adj_grid_blocks": ba["grid_blocks"],
+             "ms": bf["ms"] + ba["ms"], "forward_ms": bf["ms"], "adjoint_ms": ba["ms"], "qmed": qmed,
+             "forward_candidates": fwd, "adjoint_candidates": adj}
     if save:
         cache = _load()
         cache[_batch_key(len(fields), fields[0].shape, kind)] = entry
@@ -184,7 +209,7 @@ def _main(argv: List[str]) -> int:
             print("tuning the 32-shot tomography batch (forward + adjoint)", flush=True)
             e = tune_batch([f] * 32, c.h, [torch.tensor([int(s)]) for s in c.sources], [rec] * 32,
                            log=lambda s: print(s, flush=True))
-            print(json.dumps({k: v for k, v in e.items() if k != "candidates"}), flush=True)
+            print(json.dumps({k: v for k, v in e.items() if not k.endswith("candidates")}), flush=True)
             continue
         elif name == "tomo256":
             c = W.tomography(256, 256, 128, nshots=1, seed=5)

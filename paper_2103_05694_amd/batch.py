@@ -25,12 +25,17 @@ class ShotBatch:
     def __init__(self, fields: Sequence[torch.Tensor], h, sources: Sequence, receivers: Sequence,
                  t_obs: Optional[Sequence[torch.Tensor]] = None, kind: str = "slowness",
                  delta: float = 0.0, tile=None, stream: Optional[torch.cuda.Stream] = None,
-                 grid_blocks: int = 0, horizon: int = 0):
+                 grid_blocks: int = 0, horizon: int = 0, adj_delta: Optional[float] = None,
+                 adj_tile=None, adj_grid_blocks: Optional[int] = None):
         self.kind = kind
         self.delta = delta
         self.tile = tile
         self.grid_blocks = grid_blocks
         self.horizon = horizon
+        # the adjoint is readiness-driven and may prefer other launch parameters
+        self.adj_delta = delta if adj_delta is None else adj_delta
+        self.adj_tile = tile if adj_tile is None else adj_tile
+        self.adj_grid_blocks = grid_blocks if adj_grid_blocks is None else adj_grid_blocks
         self.fields = list(fields)
         self.nshots = len(self.fields)
         self.hs = [float(h)] * self.nshots if isinstance(h, (int, float)) else [float(x) for x in h]
@@ -61,8 +66,8 @@ class ShotBatch:
                          stream=self.stream, horizon=self.horizon)
         self.g.zero_()
         self.g.index_copy_(0, self.rec, self.t.index_select(0, self.rec) - self.t_obs)
-        api.adjoint_packed(self.b, self.t, self.par, self.g, self.grad, self.mu, self.delta, self.tile,
-                           grid_blocks=self.grid_blocks, stream=self.stream)
+        api.adjoint_packed(self.b, self.t, self.par, self.g, self.grad, self.mu, self.adj_delta, self.adj_tile,
+                           grid_blocks=self.adj_grid_blocks, stream=self.stream)
 
     def step(self) -> None:
         """Enqueue one batched forward + adjoint (eager launches).  The batch's
@@ -103,7 +108,9 @@ class ShotBatch:
 
     # -- reference: the same work one shot at a time ---------------------------
     def plain_step(self, t_out: torch.Tensor, grad_out: torch.Tensor, delta: Optional[float] = None,
-                   tile=None, grid_blocks: Optional[int] = None, horizon: Optional[int] = None) -> None:
+                   tile=None, grid_blocks: Optional[int] = None, horizon: Optional[int] = None,
+                   adj_delta: Optional[float] = None, adj_tile=None,
+                   adj_grid_blocks: Optional[int] = None) -> None:
         """Per-shot eik_solve + eik_adjoint launches on the current stream,
         writing into packed outputs.  The launch parameters default to the
         batch's; a single shot may prefer others (it has far less parallel
@@ -112,6 +119,9 @@ class ShotBatch:
         tile = self.tile if tile is None else tile
         grid_blocks = self.grid_blocks if grid_blocks is None else grid_blocks
         horizon = self.horizon if horizon is None else horizon
+        adj_delta = self.adj_delta if adj_delta is None else adj_delta
+        adj_tile = self.adj_tile if adj_tile is None else adj_tile
+        adj_grid_blocks = self.adj_grid_blocks if adj_grid_blocks is None else adj_grid_blocks
         tv = self.b.views(t_out)
         gv = self.b.views(grad_out)
         g = torch.zeros_like(t_out)
@@ -125,8 +135,8 @@ class ShotBatch:
             nr = r.numel()
             gvv[i].view(-1).index_copy_(0, r, t.view(-1).index_select(0, r) - self.t_obs[rec_off:rec_off + nr])
             rec_off += nr
-            api.adjoint(self.fields[i], self.hs[i], t, par, gvv[i], kind=self.kind, delta=delta,
-                        tile=tile, grid_blocks=grid_blocks, out=gv[i], check_status=False)
+            api.adjoint(self.fields[i], self.hs[i], t, par, gvv[i], kind=self.kind, delta=adj_delta,
+                        tile=adj_tile, grid_blocks=adj_grid_blocks, out=gv[i], check_status=False)
 
     def shot_views(self, packed: torch.Tensor) -> List[torch.Tensor]:
         return self.b.views(packed)

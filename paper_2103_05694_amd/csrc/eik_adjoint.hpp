@@ -104,6 +104,7 @@ __global__ void __launch_bounds__(NT) k_adjoint(AdjArgs A) {
     __shared__ uint32_t s_nid[6];
     __shared__ unsigned long long s_face[6];
     __shared__ unsigned int s_done;
+    __shared__ int s_next;  // tile handed on by the previous run's publish, or -1
 
     const int tid = threadIdx.x;
     const Sched& S = A.s;
@@ -111,13 +112,20 @@ __global__ void __launch_bounds__(NT) k_adjoint(AdjArgs A) {
     constexpr int PSTEP[3] = {1, TX, TX * TY};
     constexpr int LSTEP[3] = {1, C::SY, C::SZ};
     constexpr int NAX = C::D3 ? 3 : 2;
-    unsigned long long my_visits = 0, my_done = 0;
+    unsigned long long my_visits = 0, my_done = 0, my_cont = 0;
+    if (tid == 0) {
+        s_next = -1;
+        s_bucket = 0;
+    }
 
     for (;;) {
         if (tid < 64) {
-            int64_t bucket = 0;
-            int tile = claim(S, &bucket);
+            int64_t bucket = s_bucket;
+            int tile = s_next;
+            if (tile < 0) tile = claim(S, &bucket);
+            else if (tid == 0) ++my_cont;
             if (tid == 0) {
+                s_next = -1;
                 s_tile = tile;
                 s_bucket = bucket;
                 if (tile >= 0) {
@@ -189,7 +197,12 @@ __global__ void __launch_bounds__(NT) k_adjoint(AdjArgs A) {
             gq[j] = q;
             gg[j] = gv;
             was_done[j] = !(mv != mv);
-            sDirty[0][p] = 1;
+            // first run: every point (leaves can sit anywhere); later runs:
+            // only boundary points, since nothing inside changed since the
+            // last run and readiness can only come from children across a face
+            const bool edge = lx == 0 || lx == TX - 1 || ly == 0 || ly == TY - 1 ||
+                              (C::D3 && (lz == 0 || lz == TZ - 1));
+            sDirty[0][p] = (!visited || edge) ? 1 : 0;
             sDirty[1][p] = 0;
         }
         __syncthreads();
@@ -343,13 +356,17 @@ __global__ void __launch_bounds__(NT) k_adjoint(AdjArgs A) {
         stores_done();
         __syncthreads();
 
-        if (tid < 64) publish(S, A.tkey, (uint32_t)tile, s_bucket, !visited, s_nb, s_nid, s_face);
+        if (tid < 64) {
+            const int nxt = publish(S, A.tkey, (uint32_t)tile, s_bucket, !visited, s_nb, s_nid, s_face, true);
+            if (tid == 0) s_next = nxt;
+        }
         if (tid == 0) my_done += s_done;
         __syncthreads();
     }
     if (tid == 0) {
         __hip_atomic_fetch_add(S.counters + 0, my_visits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(S.counters + 1, my_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(S.counters + 12, my_cont, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

@@ -30,8 +30,12 @@ def tuned(shape, kind, default_tile, default_delta, nshots=32):
     cfg = autotune.lookup_batch(nshots, shape, kind) or autotune.lookup(shape, kind)
     if not cfg:
         return dict(tile=default_tile, delta=default_delta, grid_blocks=0, horizon=0)
-    return dict(tile=tuple(cfg["tile"]), delta=cfg["delta"], grid_blocks=int(cfg.get("grid_blocks", 0)),
-                horizon=int(cfg.get("horizon", 0)))
+    out = dict(tile=tuple(cfg["tile"]), delta=cfg["delta"], grid_blocks=int(cfg.get("grid_blocks", 0)),
+               horizon=int(cfg.get("horizon", 0)))
+    if "adj_delta" in cfg:
+        out.update(adj_delta=cfg["adj_delta"], adj_tile=tuple(cfg["adj_tile"]),
+                   adj_grid_blocks=int(cfg.get("adj_grid_blocks", 0)))
+    return out
 
 
 def rel_err(a, b):
@@ -107,8 +111,8 @@ def test_uneven_full_batch(gpu, O):
         gs[i] = gi
         gv[i].copy_(torch.from_numpy(gi).reshape(gv[i].shape))
     grad = torch.empty_like(t)
-    gpu.adjoint_packed(b, t, par, g, grad, delta=cfg["delta"], tile=cfg["tile"],
-                       grid_blocks=cfg["grid_blocks"])
+    gpu.adjoint_packed(b, t, par, g, grad, delta=cfg.get("adj_delta", cfg["delta"]),
+                       tile=cfg.get("adj_tile", cfg["tile"]), grid_blocks=cfg.get("adj_grid_blocks", cfg["grid_blocks"]))
     gpu.status()
     tv, pv, grv = b.views(t), b.views(par), b.views(grad)
     for i in small:
