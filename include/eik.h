@@ -26,7 +26,8 @@
  *    their name ends in _host.  The caller owns every input and output buffer;
  *    the library only reads/writes them inside work enqueued on `stream`.
  *  - All work is enqueued on `stream` (a hipStream_t, NULL = default stream);
- *    no call synchronises the host except eik_status().
+ *    only eik_status(), eik_residual() and eik_timeline() synchronise the host
+ *    (and the first call of a given batch layout, which uploads its table).
  *  - The library owns a workspace per (device, stream) (tile states, priority
  *    queues, counters), allocated on first use, grown on demand and freed by
  *    eik_release().  Two calls on the same stream are ordered; calls on
@@ -84,10 +85,11 @@ typedef struct {
                                 16x8x4, 8x8x4, 8x4x4; 2D 32x32, 64x16, 128x8, 16x16, 16x8 */
     int32_t grid_blocks;     /* persistent workgroups; 0 => fill the device */
     int64_t max_tile_visits; /* 0 => unlimited; else stop after this many tile visits (ELIMIT) */
-    uint32_t flags;          /* 0 or EIK_FLAG_TIME_KERNELS: record HIP events around the
-                                persistent kernel (solve or adjoint) on `stream`; eik_status
-                                then reports the mean duration of the kernels timed since the
-                                previous eik_status (at most 4096 launches in between) */
+    uint32_t flags;          /* EIK_FLAG_* bits.  EIK_FLAG_TIME_KERNELS: record HIP events
+                                around the persistent kernel (solve or adjoint) on `stream`;
+                                eik_status then reports the mean duration of the kernels timed
+                                since the previous eik_status (at most 4096 launches in
+                                between).  EIK_FLAG_WAVE_TILES, EIK_FLAG_TIMELINE: above */
     int32_t lookahead;       /* 0..8: work may be taken from the lowest non-drained bucket
                                 and this many buckets above it (0 = strict bucket order) */
     int32_t horizon;         /* 0 => off; k in 1..4: a run of a tile claimed from bucket b
