@@ -304,6 +304,39 @@ def bench_schedules(args, torch, eik, W) -> dict:
     return out
 
 
+def bench_paper_scale(args, torch, eik, W) -> dict:
+    """The paper's grid shape: 2D 11204 x 54404 (609M points), a synthetic
+    folded-layer stand-in for its upsampled Marmousi model (spacing 0.3125 m,
+    source at the surface centre); one forward solve per step."""
+    from paper_2103_05694_amd import autotune
+    p = W.folded_layers_2d()
+    f = torch.from_numpy(p.field[0]).cuda()
+    src = torch.as_tensor(p.src).cuda()
+    cfg = autotune.lookup(tuple(f.shape), "speed")
+    tile = tuple(cfg["tile"]) if cfg else (32, 32)
+    delta = cfg["delta"] if cfg else 32 * p.h / 3000.0
+    gb = int(cfg.get("grid_blocks", 0)) if cfg else 0
+    hz = int(cfg.get("horizon", 0)) if cfg else 0
+    out = torch.empty_like(f)
+    kw = dict(tile=tile, delta=delta, grid_blocks=gb, horizon=hz, out=out, check_status=False)
+    eik.solve(f, p.h, src, **kw)
+    eik.status()
+    reps = 3
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        eik.solve(f, p.h, src, time_kernels=True, **kw)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    st = eik.status()
+    res = eik.residual(f, p.h, src, out)
+    return {"workload": "2D 11204x54404 folded layers (the paper's upsampled grid shape), h=0.3125 m",
+            "points": p.npts, "ms_per_solve": ms, "kernel_ms": st.kernel_ms,
+            "points_per_s": p.npts / (ms * 1e-3), "tile": list(tile), "delta": delta, "grid_blocks": gb,
+            "horizon": hz, "visits_per_tile": st.tile_visits / max(st.ntiles, 1),
+            "residual_points": res[0]}
+
+
 def profile_mode(args, torch, eik, W) -> None:
     """A short run for rocprofv3: a plain 1 GiB device copy (counter
     calibration), then a few solves of the headline workload."""
@@ -344,6 +377,7 @@ def main() -> int:
     ap.add_argument("--parents", action="store_true")
     ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--no-schedules", action="store_true")
+    ap.add_argument("--no-paper-scale", action="store_true")
     ap.add_argument("--profile-mode", action="store_true")
     args = ap.parse_args()
 
@@ -408,6 +442,10 @@ def main() -> int:
         log("uneven batch")
         extra["uneven_64"] = bench_uneven(args, torch, eik, W)
         log(json.dumps(extra["uneven_64"]))
+    if not args.no_paper_scale:
+        log("paper-scale 2D grid")
+        extra["paper_scale_2d"] = bench_paper_scale(args, torch, eik, W)
+        log(json.dumps(extra["paper_scale_2d"]))
     if not args.no_schedules:
         log("schedule comparison")
         extra["schedules"] = bench_schedules(args, torch, eik, W)

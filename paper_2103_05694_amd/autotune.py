@@ -202,6 +202,15 @@ def _main(argv: List[str]) -> int:
             p = W.layered_3d()
         elif name == "layered256":
             p = W.layered_3d(256, 256, 128)
+        elif name == "paper2d":
+            p = W.folded_layers_2d()
+            f = torch.from_numpy(p.field[0]).cuda()
+            print(f"tuning {p.name}", flush=True)
+            e = tune(f, p.h, torch.as_tensor(p.src), tiles=[(32, 32), (16, 16)],
+                     delta_factors=(0.5, 1.0, 2.0, 4.0), grid_blocks=(0,), horizons=(0,), reps=2,
+                     log=lambda s: print(s, flush=True))
+            print(json.dumps({k: v for k, v in e.items() if k != "candidates"}), flush=True)
+            continue
         elif name == "tomo256x32":
             c = W.tomography(256, 256, 128, nshots=32, seed=5)
             f = torch.from_numpy(c.s0).cuda()

@@ -613,8 +613,10 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
 
         // ---- publish: activate neighbours, end the run or hand on ----------
         if (tid < 64) {
+            // runs of this kernel read halos without looking at V (t starts at
+            // +inf), so V needs no ordering against the activations
             const int nxt = publish(S, A.tkey, (uint32_t)tile, s_bucket, !visited, s_nb, s_nid, s_face, true,
-                                    s_pend);
+                                    s_pend, false);
             if (tid == 0) s_next = nxt;
         }
         if (tid == 0) {

@@ -297,11 +297,11 @@ __device__ __forceinline__ int claim(const Sched& s, int64_t* bucket) {
 //   nid[f]  its tile id, face[f] the priority key bits of the lowered values on
 //           face f (kInfBits: nothing lowered there),
 //   first   the run wrote this tile's interior for the first time (sets V).
-// First the tile's own state word drops R (and gains V); the RMW's return also
-// says whether the tile was activated during the run.  Then lanes 0..5
-// activate the neighbours in parallel.  The live-work count changes once, by
-// (#newly queued neighbours + requeue - 1), before any push makes new items
-// claimable, so it never under-counts.
+// The tile's own state word drops R (and gains V); the RMW's return also says
+// whether the tile was activated during the run.  Lanes 0..5 activate the
+// neighbours in parallel, after that RMW when neighbours read V (order_v).
+// The live-work count changes once, by (#newly queued neighbours + requeue -
+// 1), before any push makes new items claimable, so it never under-counts.
 // `self_key` (bits of a time, kInfBits for none) requeues the tile itself with
 // at most that key: the run left points whose new values lie beyond its
 // bucket.
@@ -313,10 +313,14 @@ __device__ __forceinline__ int claim(const Sched& s, int64_t* bucket) {
 __device__ __forceinline__ int publish(const Sched& s, uint64_t* tkey, uint32_t tile, int64_t bucket, bool first,
                                        const uint32_t* nb, const uint32_t* nid,
                                        const unsigned long long* face, bool cont = false,
-                                       unsigned long long self_key = kInfBits) {
+                                       unsigned long long self_key = kInfBits, bool order_v = true) {
     const int lane = threadIdx.x & 63;
+    // lane 0 updates the tile's own word before the activations when readers
+    // of the neighbours rely on V (order_v); otherwise lane 6 does it
+    // alongside them
+    const int ol = order_v ? 0 : 6;
     uint32_t own = 0;
-    if (lane == 0) {
+    if (lane == ol) {
         // work of this tile left for a later bucket: activate the tile itself
         // while R still keeps everyone else from pushing it
         if (self_key != kInfBits)
@@ -324,9 +328,9 @@ __device__ __forceinline__ int publish(const Sched& s, uint64_t* tkey, uint32_t 
         own = __hip_atomic_fetch_xor(s.tstate + tile, kR | (first ? kV : 0u), __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_AGENT);
     }
-    // the RMW has returned, so V is visible before any neighbour is activated
-    own = __shfl(own, 0);
-    const bool requeue = (own & kQ) != 0;
+    // with order_v the RMW has returned here, so V is visible before any
+    // neighbour is activated
+    if (order_v) own = __shfl(own, 0);
     bool want = false;
     uint32_t n = 0;
     unsigned long long fk = kInfBits;
@@ -343,6 +347,8 @@ __device__ __forceinline__ int publish(const Sched& s, uint64_t* tkey, uint32_t 
             }
         }
     }
+    if (!order_v) own = __shfl(own, ol);
+    const bool requeue = (own & kQ) != 0;
     const unsigned long long wm = __ballot(want);
     const int k = __popcll(wm);
     int cl = -1;

@@ -10,6 +10,9 @@ sampled shots the oracle computes one by one.
 * Uneven batch: 64 shots of 128^3 .. 256x256x128 (343M points) in one
   persistent forward launch and one adjoint launch; two sampled shots checked
   the same way, and a property of every shot (zero residual).
+* The paper's grid shape, 2D 11204 x 54404 (609M points, folded layers): a
+  scaled-down version of the same recipe bitwise against the oracle, and the
+  full size through its residual (zero, hence the unique fixed point).
 """
 import numpy as np
 import pytest
@@ -130,3 +133,21 @@ def test_uneven_full_batch(gpu, O):
     # unique one), checked on the GPU against each shot's own field
     for i in range(0, 64, 9):
         assert gpu.residual(fields[i], 10.0, srcs[i], tv[i], kind="slowness") == (0, 0.0), f"shot {i}"
+
+
+def test_paper_scale_2d(gpu, O):
+    small = W.folded_layers_2d(nx=1701, nz=351, up=2)
+    ref = O.fmm(small.field, small.h, small.src)
+    fs = torch.from_numpy(small.field[0]).cuda()
+    for tile, delta in (((32, 32), 32 * small.h / 3000.0), ((16, 16), 0.0), ((64, 16), 0.05)):
+        t = gpu.solve(fs, small.h, torch.as_tensor(small.src), tile=tile, delta=delta)
+        assert np.array_equal(t.cpu().numpy(), ref[0]), f"scaled-down, tile {tile}"
+    p = W.folded_layers_2d()
+    assert p.shape == (1, 11204, 54404)
+    from paper_2103_05694_amd import autotune
+    cfg = autotune.lookup((11204, 54404), "speed") or {"tile": (32, 32), "delta": 32 * p.h / 3000.0}
+    f = torch.from_numpy(p.field[0]).cuda()
+    t = gpu.solve(f, p.h, torch.as_tensor(p.src), tile=tuple(cfg["tile"]), delta=cfg["delta"],
+                  grid_blocks=int(cfg.get("grid_blocks", 0)), horizon=int(cfg.get("horizon", 0)))
+    assert gpu.residual(f, p.h, torch.as_tensor(p.src), t) == (0, 0.0)
+    assert float(t.max()) < np.inf

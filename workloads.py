@@ -169,6 +169,57 @@ def blocky_2d(n: int = 4096, nsrc: int = 16, seed: int = 3, block: int = 64,
                    name=f"2d_{n}x{n}_blocky_{nsrc}src_seed{seed}")
 
 
+def folded_layers_2d(nx: int = 13601, nz: int = 2801, up: int = 4, h: float = 1.25, seed: int = 6,
+                     nlayers: int = 14, water_rows: Optional[int] = None, noise: float = 0.05,
+                     sigma: float = 8.0) -> Problem:
+    """Synthetic stand-in for the paper's upsampled Marmousi grid: a 2D model
+    of ``nz`` depth rows by ``nx`` columns (spacing ``h``), then repeated
+    ``up`` times along each axis (nearest-neighbour upsampling, spacing
+    h / up).  Structure: a water layer of ``water_rows`` rows (default about an
+    eighth of the depth) at 1500 m/s over
+    ``nlayers`` layers whose speeds rise from 1600 to 4700 m/s with seeded
+    jitter, bounded by folded interfaces (sums of three random sinusoids) that a
+    steep normal fault offsets in the middle third, times (1 + noise * g) with
+    g smoothed unit noise.  One source at the surface centre.  The result is a
+    2D Problem with ny = nz * up rows (depth) and nx * up columns."""
+    rng = np.random.default_rng(seed)
+    if water_rows is None:
+        water_rows = max(1, (nz * 9) // 70)
+    x = np.arange(nx, dtype=np.float64)
+    span = nz - water_rows
+    base = water_rows + span * (np.arange(1, nlayers) / nlayers)
+    fault_x = nx * (0.4 + 0.2 * rng.random())
+    throw = 0.04 * span
+    iface = []
+    for k in range(nlayers - 1):
+        amp = rng.uniform(0.01, 0.05, 3) * span
+        wav = rng.uniform(0.5, 4.0, 3) * 2.0 * np.pi / nx
+        ph = rng.uniform(0.0, 2.0 * np.pi, 3)
+        d = base[k] + (amp[:, None] * np.sin(wav[:, None] * x[None, :] + ph[:, None])).sum(0)
+        d = d + np.where(x > fault_x + 0.3 * (d - water_rows), throw, 0.0)
+        iface.append(np.clip(d, water_rows + 1, nz - 1))
+    speeds = np.concatenate([[1500.0], np.linspace(1600.0, 4700.0, nlayers) *
+                             (1.0 + 0.04 * rng.standard_normal(nlayers))])
+    z = np.arange(nz, dtype=np.float64)[:, None]
+    layer = np.zeros((nz, nx), dtype=np.int16)
+    for d in iface:
+        layer += (z >= d[None, :]).astype(np.int16)
+    layer = np.where(z < water_rows, 0, layer + 1)
+    v = speeds[layer]
+    if noise != 0.0:
+        g = smooth_unit_noise((nz, nx), rng, sigma)
+        v = np.where(z < water_rows, v, v * (1.0 + noise * g))
+    if up > 1:
+        v = np.repeat(np.repeat(v, up, axis=0), up, axis=1)
+    v = np.ascontiguousarray(v.reshape(1, nz * up, nx * up))
+    if not np.all(v > 0):
+        raise ValueError("folded-layer speed produced a non-positive value")
+    NX, NY = nx * up, nz * up
+    src = flat_index(NX // 2, 0, 0, NX, NY).reshape(1)
+    return Problem(2, NX, NY, 1, h / up, v, SPEED, src, None,
+                   name=f"2d_{NX}x{NY}_folded_layers_seed{seed}")
+
+
 BATCH_SIZES = ((128, 128, 128), (192, 192, 128), (256, 256, 128))
 
 
