@@ -38,6 +38,7 @@
 #define OP_DBAR 0   /* exact monotone rounding */
 #define OP_DHAT 1   /* reordered explicit formula (2D only) */
 #define OP_DTILDE 2 /* textbook explicit formula (2D only) */
+#define OP_NEWTON 3 /* Newton on the root function from the d-hat guess (2D only) */
 
 static uint64_t bits_of(double x) { uint64_t u; memcpy(&u, &x, 8); return u; }
 static double double_of(uint64_t u) { double x; memcpy(&x, &u, 8); return x; }
@@ -197,6 +198,30 @@ static void neighbour_minima(const grid_t *g, const double *t, int64_t i, double
     }
 }
 
+/* The Newton variant of the paper's precision section: Newton's method on
+ * alpha(t) = (t - tH)^2 + (t - tV)^2 - c, started from d-hat, on the two-sided
+ * branch (|tH - tV| < q); the one-sided branch is min(tH, tV) + q as for the
+ * explicit formulas.  Each step, in this order:
+ *   e0 = fl(t - tH), e1 = fl(t - tV),
+ *   a  = fl(fl(fl(e0*e0) + fl(e1*e1)) - c),  da = fl(2 * fl(e0 + e1)),
+ *   t' = fl(t - fl(a / da)),
+ * stopping when t' == t, da == 0, or after 8 steps (the paper fixes neither
+ * the count nor the stopping rule). */
+double orc_newton(double tH, double tV, double c, double q) {
+    if (fabs(tH - tV) >= q) return (tH < tV ? tH : tV) + q;
+    double t = orc_dhat(tH, tV, c, q);
+    for (int k = 0; k < 8; ++k) {
+        double e0 = t - tH, e1 = t - tV;
+        double a = (e0 * e0 + e1 * e1) - c;
+        double da = 2.0 * (e0 + e1);
+        if (da == 0.0) break;
+        double tn = t - a / da;
+        if (tn == t) break;
+        t = tn;
+    }
+    return t;
+}
+
 /* Apply the chosen operator at point i; returns the candidate value. */
 static double apply_op(const grid_t *g, const double *t, const double *q, int64_t i, int op) {
     double a[3];
@@ -207,6 +232,7 @@ static double apply_op(const grid_t *g, const double *t, const double *q, int64_
     double tH = a[0], tV = a[1];
     if (!(tH < INFINITY) && !(tV < INFINITY)) return INFINITY;
     if (op == OP_DHAT) return orc_dhat(tH, tV, c, qi);
+    if (op == OP_NEWTON) return orc_newton(tH, tV, c, qi);
     return orc_dtilde(tH, tV, c, qi);
 }
 

@@ -17,6 +17,8 @@ Each function cites the passage of the paper it follows:
   * ``residual``      -- the error metric of Table "tab:error".
   * ``dtilde``/``dhat`` -- the explicit formulas of Tables "tab:prec_1" and
                          "tab:prec_2".
+  * ``newton``        -- Newton's method on the root function from the d-hat
+                         guess (the precision section's practical variant).
   * ``parents``/``adjoint`` -- the paper is silent; implicit differentiation of
                          the discrete equations (Eq. "difference_as_root")
                          over the recorded upwind parents.
@@ -36,6 +38,7 @@ SLOWNESS = 1
 OP_DBAR = 0
 OP_DHAT = 1
 OP_DTILDE = 2
+OP_NEWTON = 3
 
 _lib = None
 
@@ -58,6 +61,8 @@ def lib():
         L.orc_dtilde.argtypes = [_d, _d, _d, _d]
         L.orc_dhat.restype = _d
         L.orc_dhat.argtypes = [_d, _d, _d, _d]
+        L.orc_newton.restype = _d
+        L.orc_newton.argtypes = [_d, _d, _d, _d]
         solve_args = [_int, _i64, _i64, _i64, _d, _ptr, _int, _i64, _ptr, _ptr, _int, _ptr, _ptr]
         for name in ("orc_fmm", "orc_sweep_all", "orc_fsm"):
             f = getattr(L, name)
@@ -133,6 +138,13 @@ def reaches(r: float, a, c: float) -> bool:
 def dtilde(tH: float, tV: float, v: float, h: float) -> float:
     q = h / v
     return lib().orc_dtilde(tH, tV, q * q, q)
+
+
+def newton(tH: float, tV: float, v: float, h: float) -> float:
+    """The Newton variant (precision section): Newton on alpha = 0 from the
+    d-hat guess, two-sided branch; q = fl(h/v), c = fl(q*q)."""
+    q = h / v
+    return lib().orc_newton(tH, tV, q * q, q)
 
 
 def dhat(tH: float, tV: float, v: float, h: float) -> float:

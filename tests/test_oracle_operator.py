@@ -16,6 +16,7 @@ import random
 import struct
 from decimal import Decimal, getcontext
 
+import numpy as np
 import pytest
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -257,3 +258,41 @@ def test_two_and_three_sided_unit_cases(O):
 
 def test_no_finite_neighbour_gives_inf(O):
     assert O.dbar([INF, INF, INF], 1.0) == INF
+
+
+def test_newton_repairs_the_table_prec_2_pair(O, tables):
+    """Newton's method from the d-hat guess (the precision section's practical
+    variant) on the pair where d-hat is not monotone: the smaller t_V must not
+    give the larger result, and both results sit within one ulp of d-bar."""
+    T = tables["tab_prec_2"]
+    rows = T["rows"]
+    a = O.newton(T["tH"], rows["A"]["tV"], T["v"], T["h"])
+    b = O.newton(T["tH"], rows["B"]["tV"], T["v"], T["h"])
+    assert rows["B"]["tV"] < rows["A"]["tV"]
+    assert b <= a
+    q = T["h"] / T["v"]
+    for tV, r in ((rows["A"]["tV"], a), (rows["B"]["tV"], b)):
+        d = O.dbar([T["tH"], tV, np.inf], q * q)
+        assert abs(int(np.float64(r).view(np.int64)) - int(np.float64(d).view(np.int64))) <= 1
+
+
+def test_newton_converges_to_the_root_of_alpha(O):
+    """On the two-sided branch Newton solves the same root problem as d-bar:
+    almost always within one ulp of d-bar, never far off; on the one-sided
+    branch it is min + q like the explicit formulas."""
+    rng = np.random.default_rng(0)
+    diffs = []
+    for _ in range(4000):
+        v = rng.uniform(0.5, 5.0)
+        h = rng.uniform(0.1, 10.0)
+        q = h / v
+        tH = rng.uniform(0.0, 100.0)
+        tV = tH + rng.uniform(-0.999, 0.999) * q
+        n = O.newton(tH, tV, v, h)
+        d = O.dbar([tH, tV, np.inf], q * q)
+        assert np.isfinite(n)
+        diffs.append(abs(int(np.float64(n).view(np.int64)) - int(np.float64(d).view(np.int64))))
+        assert O.newton(tH, tH + 1.5 * q, v, h) == tH + q
+    diffs = np.array(diffs)
+    assert np.mean(diffs <= 1) > 0.995
+    assert diffs.max() <= 16
