@@ -254,20 +254,23 @@ def bench_ablation(args, torch, eik, W) -> dict:
                  dict(tile=(32, 32), delta=2.0, grid_blocks=16)]
     out = {"workload": "2D 1024x1024 blocky speeds {0.5,1,2,5} in 64-cell blocks, 16 sources, h=1",
            "schedules": [{k: (list(v) if isinstance(v, tuple) else v) for k, v in s.items()} for s in schedules]}
-    for op in ("dbar", "dhat", "dtilde"):
-        ts, res = [], []
+    for name, op, track in (("dtilde", "dtilde", False), ("dhat", "dhat", False),
+                            ("dhat+change_tracking", "dhat", True), ("newton", "newton", False),
+                            ("dbar", "dbar", False)):
+        ts, res, ms = [], [], []
         for sch in schedules:
-            t = eik.solve(f, p.h, src, op=op, check_status=False, **sch)
-            eik.status()
+            t = eik.solve(f, p.h, src, op=op, track_change=track, check_status=False, time_kernels=True, **sch)
+            st = eik.status(raise_on_error=False)
+            ms.append(st.kernel_ms)
             ts.append(t.clone())
             res.append(eik.residual(f, p.h, src, t, op=op))
         distinct = []
         for t in ts:
             if not any(torch.equal(t, u) for u in distinct):
                 distinct.append(t)
-        out[op] = {"residual_points": [r[0] for r in res], "residual_max_rel": [r[1] for r in res],
-                   "points_differing_from_first": [int((t != ts[0]).sum()) for t in ts],
-                   "distinct_results": len(distinct)}
+        out[name] = {"residual_points": [r[0] for r in res], "residual_max_rel": [r[1] for r in res],
+                     "points_differing_from_first": [int((t != ts[0]).sum()) for t in ts],
+                     "distinct_results": len(distinct), "kernel_ms": ms}
     return out
 
 

@@ -62,11 +62,16 @@ extern "C" {
                                      3D 8x8x4, 16x8x4, 8x8x8, 16x4x4; 2D 16x16, 32x16, 32x8) */
 #define EIK_FLAG_TIMELINE 4u      /* eik_opts.flags: record when the lowest open priority bucket
                                      moves on (read back with eik_timeline) */
+#define EIK_FLAG_TRACK_CHANGE 8u  /* eik_opts.flags, ablation operators only: re-activate the
+                                     neighbours when a value changes, not only when it decreases
+                                     (the precision section's change tracking) */
 
 #define EIK_OP_DBAR 0     /* eik_opts.op: smallest double with S(r) >= c (section "Achieving
                              Exact Monotonicity with Finite Precision Arithmetic") */
 #define EIK_OP_DHAT 1     /* the reordered explicit formula of Table "tab:prec_2" */
 #define EIK_OP_DTILDE 2   /* the textbook explicit formula of Table "tab:prec_1" */
+#define EIK_OP_NEWTON 3   /* Newton's method on the root function from the d-hat guess (the
+                             precision section's practical variant; up to 8 steps) */
 
 #define EIK_SPEED 0       /* field holds speed v:    q = h / v */
 #define EIK_SLOWNESS 1    /* field holds slowness s: q = h * s */
@@ -98,7 +103,12 @@ typedef struct {
     int32_t op;              /* update operator: EIK_OP_DBAR (0, the exact monotone rounding;
                                 the only one with a schedule-independent result), or, for 2D
                                 grids and block tiles only (precision ablation), EIK_OP_DHAT /
-                                EIK_OP_DTILDE, the paper's explicit formulas */
+                                EIK_OP_DTILDE (the paper's explicit formulas) or EIK_OP_NEWTON.
+                                These assign the operator's value (it may rise: they are not
+                                monotone) and re-activate neighbours when it drops (or changes,
+                                with EIK_FLAG_TRACK_CHANGE); since termination is then not
+                                guaranteed, max_tile_visits == 0 means 256 runs per tile and a
+                                run stops after 65536 relaxation passes (both: EIK_ELIMIT) */
     const double* work_ref;  /* NULL, or (device, block tiles) the final times of this very
                                 solve: every operator evaluation is then classified as empty
                                 (no change), good (sets the final value) or bad (lowers the

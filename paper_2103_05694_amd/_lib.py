@@ -29,6 +29,8 @@ EIK_FLAG_TIMELINE = 4
 EIK_OP_DBAR = 0
 EIK_OP_DHAT = 1
 EIK_OP_DTILDE = 2
+EIK_OP_NEWTON = 3
+EIK_FLAG_TRACK_CHANGE = 8
 
 EXPORTED = (
     "eik_solve", "eik_parents", "eik_adjoint", "eik_solve_batched", "eik_adjoint_batched",

@@ -40,7 +40,8 @@ def _grid_of(shape: Sequence[int], h: float, kind: str) -> eik_grid:
 def make_opts(delta: float = 0.0, tile: Optional[Sequence[int]] = None, grid_blocks: int = 0,
               max_tile_visits: int = 0, time_kernels: bool = False, lookahead: int = 0,
               wave_tiles: bool = False, timeline: bool = False, op: str = "dbar",
-              horizon: int = 0, work_ref: Optional[torch.Tensor] = None) -> eik_opts:
+              horizon: int = 0, work_ref: Optional[torch.Tensor] = None,
+              track_change: bool = False) -> eik_opts:
     o = eik_opts()
     o.delta = float(delta)
     t = tuple(tile) if tile else (0, 0, 0)
@@ -51,7 +52,8 @@ def make_opts(delta: float = 0.0, tile: Optional[Sequence[int]] = None, grid_blo
     o.grid_blocks = int(grid_blocks)
     o.max_tile_visits = int(max_tile_visits)
     o.flags = (_lib.EIK_FLAG_TIME_KERNELS if time_kernels else 0) | \
-        (_lib.EIK_FLAG_WAVE_TILES if wave_tiles else 0) | (_lib.EIK_FLAG_TIMELINE if timeline else 0)
+        (_lib.EIK_FLAG_WAVE_TILES if wave_tiles else 0) | (_lib.EIK_FLAG_TIMELINE if timeline else 0) | \
+        (_lib.EIK_FLAG_TRACK_CHANGE if track_change else 0)
     o.lookahead = int(lookahead)
     o.horizon = int(horizon)
     o.op = _op_code(op)
@@ -59,7 +61,8 @@ def make_opts(delta: float = 0.0, tile: Optional[Sequence[int]] = None, grid_blo
     return o
 
 
-_OPS = {"dbar": _lib.EIK_OP_DBAR, "dhat": _lib.EIK_OP_DHAT, "dtilde": _lib.EIK_OP_DTILDE}
+_OPS = {"dbar": _lib.EIK_OP_DBAR, "dhat": _lib.EIK_OP_DHAT, "dtilde": _lib.EIK_OP_DTILDE,
+        "newton": _lib.EIK_OP_NEWTON}
 
 
 def _op_code(op: str) -> int:
@@ -155,7 +158,7 @@ def solve(field: torch.Tensor, h: float, sources, t0: Optional[torch.Tensor] = N
           out: Optional[torch.Tensor] = None, parents_out: Optional[torch.Tensor] = None,
           check_status: bool = True, stream=None, time_kernels: bool = False, lookahead: int = 0,
           wave_tiles: bool = False, timeline: bool = False, op: str = "dbar", horizon: int = 0,
-          work_ref: Optional[torch.Tensor] = None):
+          work_ref: Optional[torch.Tensor] = None, track_change: bool = False):
     """First-arrival times; returns t, or (t, parents) when parents=True.  `wave_tiles`
     selects the one-tile-per-wave solver (tile shapes 3D 8x8x4, 16x8x4, 8x8x8,
     16x4x4; 2D 16x16, 32x16, 32x8)."""
@@ -178,7 +181,7 @@ def solve(field: torch.Tensor, h: float, sources, t0: Optional[torch.Tensor] = N
         if work_ref.shape != field.shape:
             raise ValueError("work_ref must have the field's shape")
     o = make_opts(delta, tile, grid_blocks, max_tile_visits, time_kernels, lookahead, wave_tiles, timeline, op,
-                  horizon, work_ref)
+                  horizon, work_ref, track_change)
     rc = L.eik_solve(ctypes.byref(g), field.data_ptr(), src.numel(), src.data_ptr(),
                      t0d.data_ptr() if t0d is not None else None, t.data_ptr(),
                      par.data_ptr() if par is not None else None, ctypes.byref(o),

@@ -290,10 +290,12 @@ int check_opts(const eik_opts* o) {
     if (!(o->delta >= 0.0) || std::isnan(o->delta)) return fail(EIK_EINVAL, "delta must be >= 0");
     if (o->grid_blocks < 0) return fail(EIK_EINVAL, "grid_blocks must be >= 0");
     if (o->max_tile_visits < 0) return fail(EIK_EINVAL, "max_tile_visits must be >= 0");
-    if (o->flags & ~(EIK_FLAG_TIME_KERNELS | EIK_FLAG_WAVE_TILES | EIK_FLAG_TIMELINE))
+    if (o->flags & ~(EIK_FLAG_TIME_KERNELS | EIK_FLAG_WAVE_TILES | EIK_FLAG_TIMELINE | EIK_FLAG_TRACK_CHANGE))
         return fail(EIK_EINVAL, "unknown flags");
     if (o->lookahead < 0 || o->lookahead > 8) return fail(EIK_EINVAL, "lookahead must be in 0..8");
-    if (o->op < EIK_OP_DBAR || o->op > EIK_OP_DTILDE) return fail(EIK_EINVAL, "unknown operator");
+    if (o->op < EIK_OP_DBAR || o->op > EIK_OP_NEWTON) return fail(EIK_EINVAL, "unknown operator");
+    if ((o->flags & EIK_FLAG_TRACK_CHANGE) && o->op == EIK_OP_DBAR)
+        return fail(EIK_EINVAL, "change tracking applies to the ablation operators only");
     if (o->horizon < 0 || o->horizon > 4) return fail(EIK_EINVAL, "horizon must be in 0..4");
     if (o->work_ref && (wave_mode(o) || o->op != EIK_OP_DBAR))
         return fail(EIK_ENOTSUP, "work classification runs with block tiles and d-bar only");
@@ -336,6 +338,7 @@ Sched make_sched(Workspace& w, const eik_opts* o) {
     s.max_visits = o ? (long long)o->max_tile_visits : 0;
     s.lookahead = o ? o->lookahead : 0;
     s.horizon = o ? o->horizon : 0;
+    s.track = (o && (o->flags & EIK_FLAG_TRACK_CHANGE)) ? 1 : 0;
     const bool tl = o && (o->flags & EIK_FLAG_TIMELINE);
     s.timeline = tl ? w.timeline : nullptr;
     s.timeline_cap = tl ? kTimelineCap : 0;
@@ -383,6 +386,8 @@ int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int6
     if ((rc = make_table(w, probs, &src_off, &T))) return rc;
     hipStream_t st = w.stream;
     Sched s = make_sched(w, o);
+    // the ablation operators need not settle: cap the runs unless the caller did
+    if (OP != EIK_OP_DBAR && s.max_visits == 0) s.max_visits = 256 * (long long)ntiles;
     int32_t* srccnt = w.scal + kSSrcCount;
 
     hipLaunchKernelGGL(k_reset, dim3(blocks_for(std::max<int64_t>(ntiles, (int64_t)kRings * w.ring_cap), kThreads, 4096)),
@@ -466,11 +471,16 @@ int dispatch_forward(TileShape ts, Workspace& w, const std::vector<Prob>& probs,
 #define EIK_TCASE(a, b, c)                                                                     \
     if (ts.x == a && ts.y == b && ts.z == c)                                                   \
         return forward<a, b, c, false, 2>(w, probs, src_off, ntiles, npts, field, src_idx, src_t0, t, par, o);
+#define EIK_NCASE(a, b, c)                                                                     \
+    if (ts.x == a && ts.y == b && ts.z == c)                                                   \
+        return forward<a, b, c, false, 3>(w, probs, src_off, ntiles, npts, field, src_idx, src_t0, t, par, o);
     const int op = o ? o->op : EIK_OP_DBAR;
     if (op == EIK_OP_DHAT) {
         EIK_TILES_2D(EIK_HCASE)
     } else if (op == EIK_OP_DTILDE) {
         EIK_TILES_2D(EIK_TCASE)
+    } else if (op == EIK_OP_NEWTON) {
+        EIK_TILES_2D(EIK_NCASE)
     } else if (wave_mode(o)) {
         EIK_WTILES_3D(EIK_WCASE)
         EIK_WTILES_2D(EIK_WCASE)
@@ -482,6 +492,7 @@ int dispatch_forward(TileShape ts, Workspace& w, const std::vector<Prob>& probs,
 #undef EIK_WCASE
 #undef EIK_HCASE
 #undef EIK_TCASE
+#undef EIK_NCASE
     return fail(EIK_ENOTSUP, "unsupported tile shape");
 }
 
@@ -669,7 +680,7 @@ int eik_residual(const eik_grid* g, const double* field, int64_t nsrc, const int
     if (rc) return rc;
     if (!field || !t || (nsrc > 0 && !src_idx)) return fail(EIK_EINVAL, "NULL device pointer");
     if (nsrc < 0) return fail(EIK_EINVAL, "nsrc must be >= 0");
-    if (op < EIK_OP_DBAR || op > EIK_OP_DTILDE) return fail(EIK_EINVAL, "unknown operator");
+    if (op < EIK_OP_DBAR || op > EIK_OP_NEWTON) return fail(EIK_EINVAL, "unknown operator");
     if (op != EIK_OP_DBAR && g->ndim != 2) return fail(EIK_ENOTSUP, "the ablation operators are two-dimensional");
     Workspace* w = nullptr;
     if ((rc = get_ws((hipStream_t)stream, &w))) return rc;
@@ -688,6 +699,7 @@ int eik_residual(const eik_grid* g, const double* field, int64_t nsrc, const int
     const dim3 gr(blocks_for(n, kThreads, 8192)), bl(kThreads);
     if (op == EIK_OP_DHAT) hipLaunchKernelGGL(k_residual<1>, gr, bl, 0, st, P, field, t, w->mask, out, flags);
     else if (op == EIK_OP_DTILDE) hipLaunchKernelGGL(k_residual<2>, gr, bl, 0, st, P, field, t, w->mask, out, flags);
+    else if (op == EIK_OP_NEWTON) hipLaunchKernelGGL(k_residual<3>, gr, bl, 0, st, P, field, t, w->mask, out, flags);
     else hipLaunchKernelGGL(k_residual<0>, gr, bl, 0, st, P, field, t, w->mask, out, flags);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));

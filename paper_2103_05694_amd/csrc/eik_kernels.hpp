@@ -517,7 +517,7 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
                 const double ax = fmin(sT[L - 1], sT[L + 1]);
                 const double ay = fmin(sT[L - C::SY], sT[L + C::SY]);
                 const double az = C::D3 ? fmin(sT[L - C::SZ], sT[L + C::SZ]) : inf64();
-                bool ch;
+                bool ch, mark;
                 double r;
                 if constexpr (OP == 0) {
                     r = update(ax, ay, az, q, q * q, tc, ch);
@@ -525,9 +525,13 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
                         pend = fmin(pend, r);
                         ch = false;
                     }
+                    mark = ch;
                 } else {
+                    // the ablation operators assign (their value may rise) and
+                    // re-activate on a drop, or on any change when tracking
                     r = apply_op<OP>(ax, ay, az, q);
-                    ch = r < tc;
+                    ch = r != tc && r == r;
+                    mark = S.track ? ch : (ch && r < tc);
                 }
                 if constexpr (COUNT) {
                     bool good = false;
@@ -539,8 +543,8 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
                     w_imp += __popcll(__ballot(ch));
                     w_good += __popcll(__ballot(good));
                 }
-                if (ch) {
-                    sT[L] = r;
+                if (ch) sT[L] = r;
+                if (mark) {
                     // with d-bar only neighbours above the new value can depend
                     // on it (the operator is causal), so only they need another
                     // look; the ablation operators mark every neighbour
@@ -560,6 +564,10 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
             __syncthreads();
             if (tid == 0) ph[5] += wall_clock64() - tg;
             cb ^= 1;
+            if (OP != 0 && passes >= (1 << 16)) {  // an ablation operator may not settle
+                if (tid == 0) set_flag(S, kFlagLimit);
+                break;
+            }
             if (passes > (1 << 20)) {
                 if (tid == 0) set_flag(S, kFlagWatchdog);
                 break;
@@ -589,13 +597,25 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
                     // cell here, as staged; values only decrease): the
                     // operator ignores a neighbour above the point it updates
                     const int L = C::lds(lx, ly, lz);
-                    if (lx == 0 && v < sT[L - 1]) fmin_[0] = fmin(fmin_[0], v);
-                    if (lx == TX - 1 && v < sT[L + 1]) fmin_[1] = fmin(fmin_[1], v);
-                    if (ly == 0 && v < sT[L - C::SY]) fmin_[2] = fmin(fmin_[2], v);
-                    if (ly == TY - 1 && v < sT[L + C::SY]) fmin_[3] = fmin(fmin_[3], v);
+                    constexpr bool kAny = OP != 0;  // not causal: every lowered face value
+                    if (lx == 0 && (kAny || v < sT[L - 1])) fmin_[0] = fmin(fmin_[0], v);
+                    if (lx == TX - 1 && (kAny || v < sT[L + 1])) fmin_[1] = fmin(fmin_[1], v);
+                    if (ly == 0 && (kAny || v < sT[L - C::SY])) fmin_[2] = fmin(fmin_[2], v);
+                    if (ly == TY - 1 && (kAny || v < sT[L + C::SY])) fmin_[3] = fmin(fmin_[3], v);
                     if (C::D3) {
-                        if (lz == 0 && v < sT[L - C::SZ]) fmin_[4] = fmin(fmin_[4], v);
-                        if (lz == TZ - 1 && v < sT[L + C::SZ]) fmin_[5] = fmin(fmin_[5], v);
+                        if (lz == 0 && (kAny || v < sT[L - C::SZ])) fmin_[4] = fmin(fmin_[4], v);
+                        if (lz == TZ - 1 && (kAny || v < sT[L + C::SZ])) fmin_[5] = fmin(fmin_[5], v);
+                    }
+                } else if (OP != 0 && v != t_in[j]) {
+                    // an ablation operator raised the value: store it, and with
+                    // change tracking activate the neighbours across its faces
+                    tstore(A.t + P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x, v);
+                    ++nchg;
+                    if (S.track) {
+                        if (lx == 0) fmin_[0] = fmin(fmin_[0], v);
+                        if (lx == TX - 1) fmin_[1] = fmin(fmin_[1], v);
+                        if (ly == 0) fmin_[2] = fmin(fmin_[2], v);
+                        if (ly == TY - 1) fmin_[3] = fmin(fmin_[3], v);
                     }
                 }
             }

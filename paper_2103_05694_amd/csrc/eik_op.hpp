@@ -188,13 +188,36 @@ __device__ __forceinline__ double op_dhat(double tH, double tV, double q, double
     return 0.5 * ((tH + tV) + __builtin_sqrt(inner));
 }
 
+// The precision section's practical variant: Newton's method on
+// alpha(t) = (t - tH)^2 + (t - tV)^2 - c from the d-hat guess, on the
+// two-sided branch.  Each step: e0 = t - tH, e1 = t - tV,
+// a = fl(fl(e0^2) + fl(e1^2)) - c, da = 2 (e0 + e1), t' = t - a / da, all
+// separately rounded; it stops when t' == t, da == 0, or after 8 steps.
+__device__ __forceinline__ double op_newton(double tH, double tV, double q, double c) {
+    if (!(tH < inf64()) && !(tV < inf64())) return inf64();
+    if (fabs(tH - tV) >= q) return (tH < tV ? tH : tV) + q;
+    double t = op_dhat(tH, tV, q, c);
+    for (int k = 0; k < 8; ++k) {
+        const double e0 = t - tH, e1 = t - tV;
+        const double a = (e0 * e0 + e1 * e1) - c;
+        const double da = 2.0 * (e0 + e1);
+        if (da == 0.0) break;
+        const double tn = t - a / da;
+        if (tn == t) break;
+        t = tn;
+    }
+    return t;
+}
+
 // Operator selector: 0 exact monotone d-bar (the solver's operator), 1 d-hat,
-// 2 d-tilde.  Returns the value the operator gives from the axis minima.
+// 2 d-tilde, 3 Newton.  Returns the value the operator gives from the axis
+// minima.
 template <int OP>
 __device__ __forceinline__ double apply_op(double ax, double ay, double az, double q) {
     const double c = q * q;
     if constexpr (OP == 1) return op_dhat(ax, ay, q, c);
     else if constexpr (OP == 2) return op_dtilde(ax, ay, q, c);
+    else if constexpr (OP == 3) return op_newton(ax, ay, q, c);
     else {
         bool ch;
         return update(ax, ay, az, q, c, inf64(), ch);

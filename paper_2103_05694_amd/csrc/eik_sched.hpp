@@ -100,6 +100,7 @@ struct Sched {
     long long max_visits;  // 0 => unlimited
     int lookahead;       // claims may come from buckets cur .. cur + lookahead
     int horizon;         // 0, or k: a run settles only values below bucket (its bucket + k)
+    int track;           // ablation operators: re-activate on any change (else on decrease)
     unsigned long long* timeline;  // NULL, or [0] start, [1] end, then (time, bucket) per advance
     int timeline_cap;    // advances the timeline can hold
 };

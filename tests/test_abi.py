@@ -81,13 +81,19 @@ def test_solve_rejects_bad_counts_and_options(L):
     o.tile[0], o.tile[1], o.tile[2] = 32, 32, 1   # a 2D tile for a 3D grid
     assert L.eik_solve(ctypes.byref(g), dummy, 1, dummy, None, dummy, None, ctypes.byref(o), None) == -6
     o = eik_opts()
-    o.flags = 8
+    o.flags = 16                                   # no such flag
+    assert L.eik_solve(ctypes.byref(g), dummy, 1, dummy, None, dummy, None, ctypes.byref(o), None) == -1
+    o = eik_opts()
+    o.flags = 8                                    # change tracking needs an ablation operator
     assert L.eik_solve(ctypes.byref(g), dummy, 1, dummy, None, dummy, None, ctypes.byref(o), None) == -1
     o = eik_opts()
     o.horizon = 5
     assert L.eik_solve(ctypes.byref(g), dummy, 1, dummy, None, dummy, None, ctypes.byref(o), None) == -1
     o = eik_opts()
-    o.op = 3                                       # no such operator
+    o.op = 3                                       # Newton: 2D only
+    assert L.eik_solve(ctypes.byref(g), dummy, 1, dummy, None, dummy, None, ctypes.byref(o), None) == -6
+    o = eik_opts()
+    o.op = 4                                       # no such operator
     assert L.eik_solve(ctypes.byref(g), dummy, 1, dummy, None, dummy, None, ctypes.byref(o), None) == -1
     o = eik_opts()
     o.op = 1                                       # the explicit formulas are 2D only

@@ -16,7 +16,7 @@ import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-OPS = {"dbar": 0, "dhat": 1, "dtilde": 2}
+OPS = {"dbar": 0, "dhat": 1, "dtilde": 2, "newton": 3}
 
 
 @pytest.fixture(scope="module")
@@ -38,7 +38,7 @@ def blocky(n, seed, nsrc=3):
     return f, src
 
 
-@pytest.mark.parametrize("op", ["dbar", "dhat", "dtilde"])
+@pytest.mark.parametrize("op", ["dbar", "dhat", "dtilde", "newton"])
 def test_residual_matches_oracle_2d(gpu, O, op):
     f, src = blocky(96, 3)
     t = O.fmm(f, 1.0, src, op=OPS[op])
@@ -101,18 +101,18 @@ def test_ablation_schedules(gpu, O):
         t = gpu.solve(fg, 1.0, s, **sch)
         assert np.array_equal(t.cpu().numpy(), ref[0]), sch
         assert gpu.residual(fg, 1.0, s, t) == (0, 0.0)
-    for op in ("dhat", "dtilde"):
+    for op, track in (("dhat", False), ("dtilde", False), ("dhat", True), ("newton", False)):
         for sch in SCHEDULES:
-            t = gpu.solve(fg, 1.0, s, op=op, **sch)
+            t = gpu.solve(fg, 1.0, s, op=op, track_change=track, **sch)
             tn = t.cpu().numpy()
             assert np.all(np.isfinite(tn))
             assert np.all(tn.reshape(-1)[src] == 0.0)
             got = gpu.residual(fg, 1.0, s, t, op=op)
             want = O.residual(tn.reshape(f.shape), f, 1.0, src, op=OPS[op])
-            assert got == (want[0], want[1]), (op, sch)
+            assert got == (want[0], want[1]), (op, track, sch)
             # against the exact solution: within the operators' rounding
             rel = np.max(np.abs(tn - ref[0]) / np.maximum(ref[0], 1.0))
-            assert rel < 1e-12, (op, sch, rel)
+            assert rel < 1e-12, (op, track, sch, rel)
 
 
 @pytest.mark.parametrize("delta,horizon", [(0.0, 0), (0.005, 0), (0.05, 0), (0.02, 1)])
@@ -141,3 +141,5 @@ def test_work_classification_needs_block_tiles_and_dbar(gpu):
         gpu.solve(f, 1.0, torch.tensor([0]), op="dhat", work_ref=ref)
     with pytest.raises(gpu.EikError):
         gpu.solve(f, 1.0, torch.tensor([0]), wave_tiles=True, work_ref=ref)
+    with pytest.raises(gpu.EikError):
+        gpu.solve(f, 1.0, torch.tensor([0]), track_change=True)   # d-bar needs no tracking
