@@ -273,3 +273,31 @@ def test_bucket_horizon(gpu, O, layered_small, horizon):
     for delta in (1.0, 8.0):
         t = gpu_solve(gpu, b.field, b.h, b.src, tile=(32, 32), delta=delta, horizon=horizon)
         assert_bitwise(t, refb, f"blocky horizon {horizon} delta {delta}")
+
+
+def test_timeline_records_bucket_advances(gpu, layered_small):
+    """EIK_FLAG_TIMELINE: one entry per advance of the lowest open bucket, in
+    increasing bucket order and time, all within the launch's span."""
+    p = layered_small
+    f = torch.from_numpy(p.field).cuda()
+    gpu.solve(f, p.h, torch.as_tensor(p.src), tile=(8, 8, 8), delta=0.02, timeline=True)
+    st = gpu.status()
+    t, b, span = gpu.timeline()
+    assert len(t) == st.bucket_advances > 5
+    assert np.all(np.diff(b) > 0) and b[0] >= 1
+    assert np.all(np.diff(t) >= 0) and 0 < t[-1] <= span
+    # no bucket beyond the one holding the largest time is ever opened
+    tmax = float(gpu.solve(f, p.h, torch.as_tensor(p.src), tile=(8, 8, 8), delta=0.02).max())
+    assert b[-1] <= int(tmax * 50.0) + 1
+
+
+def test_autotune_candidates_agree(gpu, layered_small):
+    """The tuner times each candidate and refuses any that changes the bits."""
+    from paper_2103_05694_amd import autotune
+    p = W.layered_3d(40, 36, 28, h=10.0, seed=4, sigma=3.0)
+    f = torch.from_numpy(p.field).cuda()
+    e = autotune.tune(f, p.h, torch.as_tensor(p.src), tiles=[(8, 8, 8), (16, 8, 8)],
+                      delta_factors=(0.0, 1.0, 4.0), grid_blocks=(0, 64), horizons=(0, 1), reps=1,
+                      save=False, log=lambda s: None)
+    assert len(e["candidates"]) == 2 * (1 * 2 + 2 * 2 * 2)
+    assert tuple(e["tile"]) in ((8, 8, 8), (16, 8, 8))
