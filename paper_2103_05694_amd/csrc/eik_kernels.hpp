@@ -260,7 +260,9 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
     constexpr uint32_t kAllDirty = NPT == 4 ? 0x01010101u : (NPT == 2 ? 0x0101u : 0x01u);
     __shared__ double sT[C::NLDS];
     __shared__ double sQ[C::NP];
-    __shared__ __align__(4) uint8_t sDirty[2][C::NP];
+    // dirty flags; the NT bytes past the NP flags are per-thread sinks that
+    // let the marking below store without branching
+    __shared__ __align__(4) uint8_t sDirty[2][C::NP + NT];
     __shared__ uint16_t sList[C::NP];
     __shared__ int s_cnt[2];
     __shared__ int s_tile;
@@ -547,16 +549,19 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
                 if (mark) {
                     // with d-bar only neighbours above the new value can depend
                     // on it (the operator is causal), so only they need another
-                    // look; the ablation operators mark every neighbour
+                    // look; the ablation operators mark every neighbour.  Six
+                    // unconditional stores, unwanted ones into this thread's
+                    // sink byte (no divergent branches).
                     constexpr bool kAll = OP != 0;
                     uint8_t* nd = sDirty[cb ^ 1];
-                    if (lx > 0 && (kAll || sT[L - 1] > r)) nd[didx<NT, NPT>(p - 1)] = 1;
-                    if (lx < TX - 1 && (kAll || sT[L + 1] > r)) nd[didx<NT, NPT>(p + 1)] = 1;
-                    if (ly > 0 && (kAll || sT[L - C::SY] > r)) nd[didx<NT, NPT>(p - TX)] = 1;
-                    if (ly < TY - 1 && (kAll || sT[L + C::SY] > r)) nd[didx<NT, NPT>(p + TX)] = 1;
+                    const int sink = C::NP + tid;
+                    nd[(lx > 0 && (kAll || sT[L - 1] > r)) ? didx<NT, NPT>(p - 1) : sink] = 1;
+                    nd[(lx < TX - 1 && (kAll || sT[L + 1] > r)) ? didx<NT, NPT>(p + 1) : sink] = 1;
+                    nd[(ly > 0 && (kAll || sT[L - C::SY] > r)) ? didx<NT, NPT>(p - TX) : sink] = 1;
+                    nd[(ly < TY - 1 && (kAll || sT[L + C::SY] > r)) ? didx<NT, NPT>(p + TX) : sink] = 1;
                     if (C::D3) {
-                        if (lz > 0 && (kAll || sT[L - C::SZ] > r)) nd[didx<NT, NPT>(p - TX * TY)] = 1;
-                        if (lz < TZ - 1 && (kAll || sT[L + C::SZ] > r)) nd[didx<NT, NPT>(p + TX * TY)] = 1;
+                        nd[(lz > 0 && (kAll || sT[L - C::SZ] > r)) ? didx<NT, NPT>(p - TX * TY) : sink] = 1;
+                        nd[(lz < TZ - 1 && (kAll || sT[L + C::SZ] > r)) ? didx<NT, NPT>(p + TX * TY) : sink] = 1;
                     }
                 }
             }
