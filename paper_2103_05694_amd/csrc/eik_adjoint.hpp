@@ -89,8 +89,11 @@ struct AdjArgs {
     Sched s;
 };
 
+// Registers are capped for three waves per SIMD: with the staging loads all in
+// flight at once the largest tiles would otherwise drop to two, which costs
+// more than the few spills the cap brings.
 template <int TX, int TY, int TZ, int NT>
-__global__ void __launch_bounds__(NT) k_adjoint(AdjArgs A) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_adjoint(AdjArgs A) {
     using C = TileCfg<TX, TY, TZ, NT>;
     constexpr int NPT = C::NPT;
     __shared__ double sT[C::NLDS];
@@ -163,85 +166,144 @@ __global__ void __launch_bounds__(NT) k_adjoint(AdjArgs A) {
         }
         if (tid == 0) s_done = 0u;
 
-        // stage own points
+        // stage own points and the halo.  Loads go out in two rounds: first
+        // everything that needs no decision (own t, parents, field, dL/dt and
+        // own mu; halo t and parents), then the halo mu that the neighbour's
+        // visited bit allows, which is only known after the barrier.
+        constexpr int NXF = 2 * TY * TZ, NYF = 2 * TX * TZ, NZF = C::D3 ? 2 * TX * TY : 0;
+        constexpr int NH = NXF + NYF + NZF;
+        constexpr int HPT = (NH + NT - 1) / NT;  // halo cells per thread
+        // halo cell i: its LDS index, face and global index (-1 outside the grid)
+        auto halo_cell = [&](int i, int& L, int& f) -> int64_t {
+            int lx, ly, lz;
+            if (i < NXF) {
+                int side = i / (TY * TZ), r = i % (TY * TZ);
+                ly = r % TY; lz = r / TY; lx = side ? TX : -1; f = side;
+            } else if (i < NXF + NYF) {
+                int k2 = i - NXF, side = k2 / (TX * TZ), r = k2 % (TX * TZ);
+                lx = r % TX; lz = r / TX; ly = side ? TY : -1; f = 2 + side;
+            } else {
+                int k2 = i - NXF - NYF, side = k2 / (TX * TY), r = k2 % (TX * TY);
+                lx = r % TX; ly = r / TX; lz = side ? TZ : -1; f = 4 + side;
+            }
+            L = C::lds(lx, ly, lz);
+            const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+            if (x >= 0 && x < P.nx && y >= 0 && y < P.ny && z >= 0 && z < P.nz)
+                return P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x;
+            return -1;
+        };
         double gq[NPT];   // q_n, 0 when not an interior point
         double gg[NPT];   // dL/dt
         bool was_done[NPT];
-#pragma unroll
-        for (int j = 0; j < NPT; ++j) {
-            const int p = tid + j * NT;
-            const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
-            const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-            const int L = C::lds(lx, ly, lz);
-            double tv = inf64(), mv = 0.0, q = 0.0, gv = 0.0;
-            uint8_t pv = 0x80;  // outside points act as done sources
-            if (x < P.nx && y < P.ny && z < P.nz) {
-                const int64_t gi = P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x;
-                tv = A.t[gi];
-                pv = A.par[gi];
-                bool ok;
-                q = field_q(A.field[gi], P.h, P.kind, ok);
-                if (!ok) {
-                    set_flag(S, kFlagDomain);
-                    q = 0.0;
-                }
-                gv = A.g[gi];
-                if (pv & 0x80) mv = 0.0;
-                else mv = visited ? as_f64(__hip_atomic_load((const uint64_t*)(A.mu + gi), __ATOMIC_RELAXED,
-                                                             __HIP_MEMORY_SCOPE_AGENT))
-                                  : qnan64();
-            }
-            sT[L] = tv;
-            sP[L] = pv;
-            sM[L] = mv;
-            gq[j] = q;
-            gg[j] = gv;
-            was_done[j] = !(mv != mv);
-            // first run: every point (leaves can sit anywhere); later runs:
-            // only boundary points, since nothing inside changed since the
-            // last run and readiness can only come from children across a face
-            const bool edge = lx == 0 || lx == TX - 1 || ly == 0 || ly == TY - 1 ||
-                              (C::D3 && (lz == 0 || lz == TZ - 1));
-            sDirty[0][p] = (!visited || edge) ? 1 : 0;
-            sDirty[1][p] = 0;
-        }
-        __syncthreads();
-        // halo
         {
-            constexpr int NXF = 2 * TY * TZ, NYF = 2 * TX * TZ, NZF = C::D3 ? 2 * TX * TY : 0;
-            for (int i = tid; i < NXF + NYF + NZF; i += NT) {
-                int lx, ly, lz, f;
-                if (i < NXF) {
-                    int side = i / (TY * TZ), r = i % (TY * TZ);
-                    ly = r % TY; lz = r / TY; lx = side ? TX : -1; f = side;
-                } else if (i < NXF + NYF) {
-                    int k = i - NXF, side = k / (TX * TZ), r = k % (TX * TZ);
-                    lx = r % TX; lz = r / TX; ly = side ? TY : -1; f = 2 + side;
-                } else {
-                    int k = i - NXF - NYF, side = k / (TX * TY), r = k % (TX * TY);
-                    lx = r % TX; ly = r / TX; lz = side ? TZ : -1; f = 4 + side;
-                }
+            double tv[NPT], fv[NPT], gv[NPT], mv[NPT];
+            uint8_t pv[NPT];
+            double htv[HPT];
+            uint8_t hpv[HPT];
+            uint32_t inb = 0;
+#pragma unroll
+            for (int j = 0; j < NPT; ++j) {
+                const int p = tid + j * NT;
+                const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
                 const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-                const int L = C::lds(lx, ly, lz);
-                double tv = inf64(), mv = 0.0;
-                uint8_t pv = 0x80;
-                if (x >= 0 && x < P.nx && y >= 0 && y < P.ny && z >= 0 && z < P.nz) {
+                tv[j] = inf64();
+                fv[j] = 1.0;
+                gv[j] = 0.0;
+                mv[j] = qnan64();
+                pv[j] = 0x80;  // outside points act as done sources
+                if (x < P.nx && y < P.ny && z < P.nz) {
                     const int64_t gi = P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x;
-                    tv = A.t[gi];
-                    pv = A.par[gi];
-                    if (pv & 0x80) {
-                        mv = 0.0;
-                    } else if (s_nb[f] & kV) {
-                        mv = as_f64(__hip_atomic_load((const uint64_t*)(A.mu + gi), __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT));
-                    } else {
-                        mv = qnan64();
+                    tv[j] = A.t[gi];
+                    pv[j] = A.par[gi];
+                    fv[j] = A.field[gi];
+                    gv[j] = A.g[gi];
+                    if (visited)
+                        mv[j] = as_f64(__hip_atomic_load((const uint64_t*)(A.mu + gi), __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT));
+                    inb |= 1u << j;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < HPT; ++k) {
+                const int i = tid + k * NT;
+                htv[k] = inf64();
+                hpv[k] = 0x80;
+                if (i < NH) {
+                    int L, f;
+                    const int64_t gi = halo_cell(i, L, f);
+                    if (gi >= 0) {
+                        htv[k] = A.t[gi];
+                        hpv[k] = A.par[gi];
                     }
                 }
-                sT[L] = tv;
-                sP[L] = pv;
-                sM[L] = mv;
             }
+#pragma unroll
+            for (int j = 0; j < NPT; ++j) {
+                const int p = tid + j * NT;
+                const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+                const int L = C::lds(lx, ly, lz);
+                double q = 0.0, m = 0.0;
+                if ((inb >> j) & 1u) {
+                    bool ok;
+                    q = field_q(fv[j], P.h, P.kind, ok);
+                    if (!ok) {
+                        set_flag(S, kFlagDomain);
+                        q = 0.0;
+                    }
+                    m = (pv[j] & 0x80) ? 0.0 : mv[j];
+                }
+                sT[L] = tv[j];
+                sP[L] = pv[j];
+                sM[L] = m;
+                gq[j] = q;
+                gg[j] = (inb >> j) & 1u ? gv[j] : 0.0;
+                was_done[j] = !(m != m);
+                // first run: every point (leaves can sit anywhere); later runs:
+                // only boundary points, since nothing inside changed since the
+                // last run and readiness can only come from children across a face
+                const bool edge = lx == 0 || lx == TX - 1 || ly == 0 || ly == TY - 1 ||
+                                  (C::D3 && (lz == 0 || lz == TZ - 1));
+                sDirty[0][p] = (!visited || edge) ? 1 : 0;
+                sDirty[1][p] = 0;
+            }
+#pragma unroll
+            for (int k = 0; k < HPT; ++k) {
+                const int i = tid + k * NT;
+                if (i < NH) {
+                    int L, f;
+                    (void)halo_cell(i, L, f);
+                    sT[L] = htv[k];
+                    sP[L] = hpv[k];
+                }
+            }
+        }
+        __syncthreads();
+        // halo mu: readable only where the neighbour tile has run (V), which
+        // it had before s_nb was read; sources and outside cells count as done
+        {
+            double hmv[HPT];
+            int hl[HPT];
+#pragma unroll
+            for (int k = 0; k < HPT; ++k) {
+                const int i = tid + k * NT;
+                hl[k] = -1;
+                hmv[k] = 0.0;
+                if (i < NH) {
+                    int L, f;
+                    const int64_t gi = halo_cell(i, L, f);
+                    hl[k] = L;
+                    if (gi >= 0 && !(sP[L] & 0x80)) {
+                        if (s_nb[f] & kV)
+                            hmv[k] = as_f64(__hip_atomic_load((const uint64_t*)(A.mu + gi), __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_AGENT));
+                        else
+                            hmv[k] = qnan64();
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < HPT; ++k)
+                if (hl[k] >= 0) sM[hl[k]] = hmv[k];
         }
         __syncthreads();
 

@@ -252,8 +252,10 @@ __device__ __forceinline__ void st_flags(uint8_t* f, uint32_t v) {
 // OP selects the operator: 0 the exact monotone d-bar (the solver), 1 d-hat,
 // 2 d-tilde (two-dimensional precision ablation only; see apply_op).
 // COUNT adds the work classification (A.work_ref must then be set).
+// Registers are capped for three waves per SIMD (three 256-thread blocks per
+// compute unit): the largest tiles would otherwise drop to two.
 template <int TX, int TY, int TZ, int NT, int OP = 0, bool COUNT = false>
-__global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_solve(SolveArgs A) {
     using C = TileCfg<TX, TY, TZ, NT>;
     constexpr int NPT = C::NPT;
     static_assert(NPT == 1 || NPT == 2 || NPT == 4, "1, 2 or 4 points per thread");
@@ -374,57 +376,88 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs A) {
 
         // ---- stage the tile and its halo in LDS ----------------------------
         // t starts at +inf everywhere, so every in-grid value read here is a
-        // valid upper bound: interior and halo loads go out together.
+        // valid upper bound.  Every load of the stage (field and t of the
+        // thread's points, its halo cells) is issued before any is used, so the
+        // stage costs one memory round trip rather than one per load.
         double t_in[NPT];
         uint32_t live = 0;  // bit j: point j is in the grid and not a source
-#pragma unroll
-        for (int j = 0; j < NPT; ++j) {
-            const int p = tid + j * NT;
-            const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
-            const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-            double tv = inf64(), q = 0.0;
-            if (x < P.nx && y < P.ny && z < P.nz) {
-                const int64_t gi = P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x;
-                bool ok;
-                q = field_q(A.field[gi], P.h, P.kind, ok);
-                if (!ok) {
-                    set_flag(S, kFlagDomain);
-                    q = 0.0;
-                }
-                tv = as_f64(__hip_atomic_load((const uint64_t*)(A.t + gi), __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT));
-                if (signbit(tv)) {  // a source: fixed
-                    tv = fabs(tv);
-                    q = 0.0;
-                }
-            }
-            if (q > 0.0) live |= 1u << j;
-            sT[C::lds(lx, ly, lz)] = tv;
-            sQ[p] = q;
-            t_in[j] = tv;
-        }
-        st_flags<NPT>(sDirty[1] + tid * NPT, 0u);
         {
             constexpr int NXF = 2 * TY * TZ, NYF = 2 * TX * TZ, NZF = C::D3 ? 2 * TX * TY : 0;
-            for (int i = tid; i < NXF + NYF + NZF; i += NT) {
-                int lx, ly, lz;
-                if (i < NXF) {
-                    int side = i / (TY * TZ), r = i % (TY * TZ);
-                    ly = r % TY; lz = r / TY; lx = side ? TX : -1;
-                } else if (i < NXF + NYF) {
-                    int k = i - NXF, side = k / (TX * TZ), r = k % (TX * TZ);
-                    lx = r % TX; lz = r / TX; ly = side ? TY : -1;
-                } else {
-                    int k = i - NXF - NYF, side = k / (TX * TY), r = k % (TX * TY);
-                    lx = r % TX; ly = r / TX; lz = side ? TZ : -1;
-                }
+            constexpr int NH = NXF + NYF + NZF;
+            constexpr int HPT = (NH + NT - 1) / NT;  // halo cells per thread
+            double fv[NPT], tv[NPT], hv[HPT];
+            int hl[HPT];
+            uint32_t inb = 0;
+#pragma unroll
+            for (int j = 0; j < NPT; ++j) {
+                const int p = tid + j * NT;
+                const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
                 const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-                double v = inf64();
-                if (x >= 0 && x < P.nx && y >= 0 && y < P.ny && z >= 0 && z < P.nz)
-                    v = hload(A.t + P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x);
-                sT[C::lds(lx, ly, lz)] = v;
+                fv[j] = 0.0;
+                tv[j] = inf64();
+                if (x < P.nx && y < P.ny && z < P.nz) {
+                    const int64_t gi = P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x;
+                    fv[j] = A.field[gi];
+                    tv[j] = as_f64(__hip_atomic_load((const uint64_t*)(A.t + gi), __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT));
+                    inb |= 1u << j;
+                }
             }
+#pragma unroll
+            for (int k = 0; k < HPT; ++k) {
+                const int i = tid + k * NT;
+                hl[k] = -1;
+                hv[k] = inf64();
+                if (i < NH) {
+                    int lx, ly, lz;
+                    if (i < NXF) {
+                        int side = i / (TY * TZ), r = i % (TY * TZ);
+                        ly = r % TY; lz = r / TY; lx = side ? TX : -1;
+                    } else if (i < NXF + NYF) {
+                        int k2 = i - NXF, side = k2 / (TX * TZ), r = k2 % (TX * TZ);
+                        lx = r % TX; lz = r / TX; ly = side ? TY : -1;
+                    } else {
+                        int k2 = i - NXF - NYF, side = k2 / (TX * TY), r = k2 % (TX * TY);
+                        lx = r % TX; ly = r / TX; lz = side ? TZ : -1;
+                    }
+                    hl[k] = C::lds(lx, ly, lz);
+                    const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+                    // the sign (a source) is dropped after all loads are out:
+                    // an operation on the loaded value inside this branch
+                    // would wait for it here
+                    if (x >= 0 && x < P.nx && y >= 0 && y < P.ny && z >= 0 && z < P.nz)
+                        hv[k] = as_f64(__hip_atomic_load((const uint64_t*)(A.t + P.pt_off +
+                                                                           ((int64_t)z * P.ny + y) * P.nx + x),
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < NPT; ++j) {
+                const int p = tid + j * NT;
+                const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+                double tvj = tv[j], q = 0.0;
+                if ((inb >> j) & 1u) {
+                    bool ok;
+                    q = field_q(fv[j], P.h, P.kind, ok);
+                    if (!ok) {
+                        set_flag(S, kFlagDomain);
+                        q = 0.0;
+                    }
+                    if (signbit(tvj)) {  // a source: fixed
+                        tvj = fabs(tvj);
+                        q = 0.0;
+                    }
+                }
+                if (q > 0.0) live |= 1u << j;
+                sT[C::lds(lx, ly, lz)] = tvj;
+                sQ[p] = q;
+                t_in[j] = tvj;
+            }
+#pragma unroll
+            for (int k = 0; k < HPT; ++k)
+                if (hl[k] >= 0) sT[hl[k]] = fabs(hv[k]);
         }
+        st_flags<NPT>(sDirty[1] + tid * NPT, 0u);
         __syncthreads();
         // First pass: every point on a first run, in a tile holding a source
         // (placed before its first run, which already counts as visited) and
