@@ -120,16 +120,18 @@ typedef struct {
     int64_t tile_visits;     /* tiles claimed and processed by the persistent solve */
     int64_t point_updates;   /* points whose value decreased, summed over visits */
     int64_t ntiles;          /* tiles in the problem(s) */
-    int64_t relax_passes;    /* in-tile relaxation passes, summed over visits */
+    int64_t relax_passes;    /* in-tile relaxation passes (adjoint: readiness passes), summed
+                                over visits */
     uint32_t flags;          /* raw device flags (bit0 domain, bit1 limit, bit2 bad source, bit3 watchdog) */
     int32_t status;          /* the EIK_* code these flags map to */
     double kernel_ms;        /* mean duration of the timed persistent kernels, or -1 */
     int64_t kernel_launches; /* how many launches kernel_ms averages */
-    double phase_us[4];      /* forward solve, summed over workgroups (microseconds of wall
-                                clock): [0] claiming / waiting for work, [1] staging a tile
-                                and its halo in LDS, [2] relaxing, [3] write-back + publish */
+    double phase_us[4];      /* last solve or adjoint, summed over workgroups (microseconds of
+                                wall clock): [0] claiming / waiting for work, [1] staging a
+                                tile and its halo in LDS, [2] relaxing (adjoint: readiness
+                                passes), [3] write-back + publish */
     double process_us;       /* part of phase_us[2] spent applying the operator to the pass lists */
-    int64_t workgroups;      /* persistent workgroups of the last forward launch */
+    int64_t workgroups;      /* persistent workgroups of the last launch */
     int64_t bucket_advances; /* times the lowest open priority bucket moved on */
     int64_t handoffs;        /* runs that started on a neighbour handed on by the previous run */
     int64_t evaluations;     /* with eik_opts.work_ref: operator evaluations in the solve */

@@ -99,7 +99,10 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
     __shared__ double sT[C::NLDS];
     __shared__ double sM[C::NLDS];
     __shared__ uint8_t sP[C::NLDS];
-    __shared__ uint8_t sDirty[2][C::NP];
+    __shared__ double sG[C::NP];               // dL/dt of the tile's points
+    __shared__ uint16_t sList[C::NP];          // the pass's dirty points, compacted
+    __shared__ __align__(4) uint8_t sDirty[2][C::NP];  // layout of didx()
+    __shared__ int s_cnt[2];
     __shared__ int s_tile;
     __shared__ int64_t s_bucket;
     __shared__ uint32_t s_state;
@@ -110,12 +113,18 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
     __shared__ int s_next;  // tile handed on by the previous run's publish, or -1
 
     const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const unsigned long long lanes_below = (1ull << lane) - 1ull;
     const Sched& S = A.s;
     const double tref = as_f64(*A.tref_bits);
     constexpr int PSTEP[3] = {1, TX, TX * TY};
     constexpr int LSTEP[3] = {1, C::SY, C::SZ};
     constexpr int NAX = C::D3 ? 3 : 2;
-    unsigned long long my_visits = 0, my_done = 0, my_cont = 0;
+    unsigned long long my_visits = 0, my_done = 0, my_cont = 0, my_passes = 0;
+    // phase times on the 100 MHz wall clock, as in the forward solver:
+    // [0] claim, [1] stage, [2] readiness passes, [3] write + publish
+    unsigned long long ph[4] = {0, 0, 0, 0};
+    unsigned long long tm = wall_clock64();
     if (tid == 0) {
         s_next = -1;
         s_bucket = 0;
@@ -146,6 +155,11 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
         const uint32_t st = s_state;
         const bool visited = (st & kV) != 0;
         const Prob P = prob_of_tile(A.pt, tile);
+        if (tid == 0) {
+            const unsigned long long now = wall_clock64();
+            ph[0] += now - tm;
+            tm = now;
+        }
         const int tl = tile - P.tile_off;
         const int tx = tl % P.ntx, ty = (tl / P.ntx) % P.nty, tz = tl / (P.ntx * P.nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
@@ -164,7 +178,11 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
             s_nid[tid] = nid;
             s_face[tid] = kInfBits;
         }
-        if (tid == 0) s_done = 0u;
+        if (tid == 0) {
+            s_done = 0u;
+            s_cnt[0] = 0;
+            s_cnt[1] = 0;
+        }
 
         // stage own points and the halo.  Loads go out in two rounds: first
         // everything that needs no decision (own t, parents, field, dL/dt and
@@ -192,15 +210,15 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
                 return P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x;
             return -1;
         };
-        double gq[NPT];   // q_n, 0 when not an interior point
-        double gg[NPT];   // dL/dt
+        double gq[NPT];     // q_n, 0 when not an interior point
         bool was_done[NPT];
+        uint32_t live = 0;  // bit j: point j is in the grid, not a source, not yet done
         {
             double tv[NPT], fv[NPT], gv[NPT], mv[NPT];
             uint8_t pv[NPT];
             double htv[HPT];
             uint8_t hpv[HPT];
-            uint32_t inb = 0;
+            uint32_t inb = 0, seed = 0;
 #pragma unroll
             for (int j = 0; j < NPT; ++j) {
                 const int p = tid + j * NT;
@@ -255,17 +273,19 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
                 sT[L] = tv[j];
                 sP[L] = pv[j];
                 sM[L] = m;
+                sG[p] = (inb >> j) & 1u ? gv[j] : 0.0;
                 gq[j] = q;
-                gg[j] = (inb >> j) & 1u ? gv[j] : 0.0;
                 was_done[j] = !(m != m);
+                if (((inb >> j) & 1u) && !(pv[j] & 0x80) && !was_done[j]) live |= 1u << j;
                 // first run: every point (leaves can sit anywhere); later runs:
                 // only boundary points, since nothing inside changed since the
                 // last run and readiness can only come from children across a face
                 const bool edge = lx == 0 || lx == TX - 1 || ly == 0 || ly == TY - 1 ||
                                   (C::D3 && (lz == 0 || lz == TZ - 1));
-                sDirty[0][p] = (!visited || edge) ? 1 : 0;
-                sDirty[1][p] = 0;
+                if (!visited || edge) seed |= 1u << (8 * j);
             }
+            st_flags<NPT>(sDirty[0] + tid * NPT, seed);
+            st_flags<NPT>(sDirty[1] + tid * NPT, 0u);
 #pragma unroll
             for (int k = 0; k < HPT; ++k) {
                 const int i = tid + k * NT;
@@ -306,40 +326,93 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
                 if (hl[k] >= 0) sM[hl[k]] = hmv[k];
         }
         __syncthreads();
+        if (tid == 0) {
+            const unsigned long long now = wall_clock64();
+            ph[1] += now - tm;
+            tm = now;
+        }
 
-        // evaluate points whose children are all done, until nothing changes
+        // Evaluate points whose children are all done, until no point is left
+        // to look at.  As in the forward solver, each pass first compacts the
+        // points marked dirty into a list (per-point ballots place them, one
+        // LDS atomic per wave reserves the wave's segment), so a lane evaluates
+        // at most one point per round instead of walking all its own points.
+        // A point that becomes done marks its in-tile parents for the next
+        // pass; a point that is not ready yet is marked again by the child
+        // that completes it.
         int cb = 0;
-        for (int pass = 0;; ++pass) {
-            bool any = false;
+        int passes = 0;
+        for (;;) {
+            {
+                uint8_t* df = sDirty[cb] + tid * NPT;
+                const uint32_t fl = ld_flags<NPT>(df);
+                if (fl) st_flags<NPT>(df, 0u);
+                uint32_t m = 0;
 #pragma unroll
-            for (int j = 0; j < NPT; ++j) {
-                const int p = tid + j * NT;
-                if (!sDirty[cb][p]) continue;
-                sDirty[cb][p] = 0;
+                for (int j = 0; j < NPT; ++j) m |= ((fl >> (8 * j)) & 1u) << j;
+                m &= live;
+                unsigned long long B[NPT];
+                int tot = 0;
+#pragma unroll
+                for (int j = 0; j < NPT; ++j) {
+                    B[j] = __ballot((m >> j) & 1u);
+                    tot += __popcll(B[j]);
+                }
+                if (tot) {
+                    int base = 0;
+                    if (lane == 0) base = atomicAdd(&s_cnt[cb], tot);
+                    base = __shfl(base, 0);
+#pragma unroll
+                    for (int j = 0; j < NPT; ++j) {
+                        if ((m >> j) & 1u) sList[base + __popcll(B[j] & lanes_below)] = (uint16_t)(tid + j * NT);
+                        base += __popcll(B[j]);
+                    }
+                }
+            }
+            __syncthreads();
+            const int n = s_cnt[cb];
+            if (n == 0) break;
+            // the other counter was last read before the previous barrier and is
+            // next filled after the coming one
+            if (tid == 0) s_cnt[cb ^ 1] = 0;
+            for (int i = tid; i < n; i += NT) {
+                const int p = sList[i];
                 const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
                 const int L = C::lds(lx, ly, lz);
+                // every LDS read of the point and its neighbours goes out at once
                 const uint8_t pn = sP[L];
-                if (pn & 0x80) continue;
-                if (!(sM[L] != sM[L])) continue;  // already done
+                const double mself = sM[L];
                 const double tn = sT[L];
-                bool ready = true;
-                double lam = gg[j];
-                // children in neighbour order x-, x+, y-, y+, z-, z+
+                uint8_t pm[2 * NAX];
+                double mm[2 * NAX], tm[2 * NAX];
 #pragma unroll
                 for (int k = 0; k < NAX; ++k) {
 #pragma unroll
                     for (int side = 0; side < 2; ++side) {
                         const int Lm = side ? L + LSTEP[k] : L - LSTEP[k];
-                        const uint8_t pm = sP[Lm];
+                        pm[2 * k + side] = sP[Lm];
+                        mm[2 * k + side] = sM[Lm];
+                        tm[2 * k + side] = sT[Lm];
+                    }
+                }
+                if (!(mself != mself)) continue;  // already done
+                bool ready = true;
+                double lam = sG[p];
+                // children in neighbour order x-, x+, y-, y+, z-, z+
+#pragma unroll
+                for (int k = 0; k < NAX; ++k) {
+#pragma unroll
+                    for (int side = 0; side < 2; ++side) {
+                        const uint8_t pmk = pm[2 * k + side];
                         // the minus-side neighbour is a child if its plus-side parent is n
                         const uint32_t want = side ? 1u : 2u;
-                        if (!(pm & 0x80) && ((pm >> (2 * k)) & 3u) == want) {
-                            const double mm = sM[Lm];
-                            if (mm != mm) {
+                        if (!(pmk & 0x80) && ((pmk >> (2 * k)) & 3u) == want) {
+                            const double mmk = mm[2 * k + side];
+                            if (mmk != mmk) {
                                 ready = false;
                             } else {
-                                double w = sT[Lm] - tn;
-                                lam = lam + mm * w;
+                                double w = tm[2 * k + side] - tn;
+                                lam = lam + mmk * w;
                             }
                         }
                     }
@@ -349,14 +422,13 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
 #pragma unroll
                 for (int k = 0; k < NAX; ++k) {
                     const uint32_t code = (pn >> (2 * k)) & 3u;
-                    if (code == 1u) wk[k] = tn - sT[L - LSTEP[k]];
-                    else if (code == 2u) wk[k] = tn - sT[L + LSTEP[k]];
+                    if (code == 1u) wk[k] = tn - tm[2 * k];
+                    else if (code == 2u) wk[k] = tn - tm[2 * k + 1];
                 }
                 double W = wk[0] + wk[1];
                 W = W + wk[2];
                 const double mun = lam / W;
                 sM[L] = mun;
-                any = true;
                 // parents inside the tile may now be ready
                 uint8_t* nd = sDirty[cb ^ 1];
 #pragma unroll
@@ -364,18 +436,25 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
                     const uint32_t code = (pn >> (2 * k)) & 3u;
                     const int c = k == 0 ? lx : (k == 1 ? ly : lz);
                     const int lim = k == 0 ? TX : (k == 1 ? TY : TZ);
-                    if (code == 1u && c > 0) nd[p - PSTEP[k]] = 1;
-                    if (code == 2u && c < lim - 1) nd[p + PSTEP[k]] = 1;
+                    if (code == 1u && c > 0) nd[didx<NT, NPT>(p - PSTEP[k])] = 1;
+                    if (code == 2u && c < lim - 1) nd[didx<NT, NPT>(p + PSTEP[k])] = 1;
                 }
             }
-            if (!__syncthreads_or(any)) break;
+            ++passes;
+            __syncthreads();
             cb ^= 1;
-            if (pass > (1 << 20)) {
+            if (passes > (1 << 20)) {
                 if (tid == 0) set_flag(S, kFlagWatchdog);
                 break;
             }
         }
 
+        my_passes += (unsigned long long)passes;
+        if (tid == 0) {
+            const unsigned long long now = wall_clock64();
+            ph[2] += now - tm;
+            tm = now;
+        }
         // write back newly done points (first visit: every point, NaN = not done)
         unsigned int ndone = 0;
         double fkey[6] = {inf64(), inf64(), inf64(), inf64(), inf64(), inf64()};
@@ -422,10 +501,20 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
             const int nxt = publish(S, A.tkey, (uint32_t)tile, s_bucket, !visited, s_nb, s_nid, s_face, true);
             if (tid == 0) s_next = nxt;
         }
-        if (tid == 0) my_done += s_done;
+        if (tid == 0) {
+            my_done += s_done;
+            const unsigned long long now = wall_clock64();
+            ph[3] += now - tm;
+            tm = now;
+        }
         __syncthreads();
     }
     if (tid == 0) {
+        ph[0] += wall_clock64() - tm;
+        for (int i = 0; i < 4; ++i)
+            __hip_atomic_fetch_add(S.counters + 5 + i, ph[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(S.counters + 2, my_passes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(S.counters + 10, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(S.counters + 0, my_visits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(S.counters + 1, my_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(S.counters + 12, my_cont, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

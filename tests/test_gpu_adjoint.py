@@ -58,7 +58,7 @@ def test_adjoint_matches_oracle(gpu, O, case):
     tobs = t.reshape(-1)[rec] * (1 + 0.01 * rng.standard_normal(rec.size))
     g = receiver_grad(t, rec, tobs)
     ref_grad, ref_mu = O.adjoint(t, par, f, h, g, return_mu=True)
-    tiles = [(64, 16), (32, 32), (16, 16)] if f.shape[0] == 1 else [(32, 8, 4), (8, 8, 8), (64, 4, 4)]
+    tiles = [(64, 16), (32, 32), (16, 16)] if f.shape[0] == 1 else [(32, 8, 4), (8, 8, 8), (64, 4, 4), (16, 8, 8)]
     for tile in tiles:
         for delta in (0.0, 1.0):
             mu = torch.empty(f.shape, dtype=torch.float64, device="cuda")
