@@ -17,9 +17,10 @@
 // readiness-driven: a point is evaluated exactly once, when every child (in the
 // tile or in the halo) is done, so each mu is a fixed function of final values
 // and the result is deterministic whatever the visit order.  "Not done" is a
-// NaN in mu.  Tiles are prioritised by decreasing time (key tref - t), a finished
-// face point activates the neighbour tile holding its parent, and a tile whose
-// interior was never written (V bit clear) reads as all not-done.
+// NaN in mu, which is filled with NaN before the sweep; a point's mu goes from
+// NaN to its final value once, so any read returns one or the other.  Tiles are
+// prioritised by decreasing time (key tref - t), and a finished face point
+// activates the neighbour tile holding its parent.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -30,6 +31,14 @@
 namespace eik {
 
 __device__ __forceinline__ double qnan64() { return as_f64(0x7FF8000000000000ull); }
+
+// mu := NaN ("not done") everywhere before the sweep, so a point of a tile that
+// has not run yet reads as not done without looking at the tile's state.
+__global__ void k_fill_nan(long long npts_total, double* mu) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < npts_total; i += stride)
+        mu[i] = qnan64();
+}
 
 // Per tile: largest time (key source) and the problem-wide largest time.
 template <int TX, int TY, int TZ>
@@ -184,10 +193,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
             s_cnt[1] = 0;
         }
 
-        // stage own points and the halo.  Loads go out in two rounds: first
-        // everything that needs no decision (own t, parents, field, dL/dt and
-        // own mu; halo t and parents), then the halo mu that the neighbour's
-        // visited bit allows, which is only known after the barrier.
+        // stage own points and the halo: every load goes out before any is used
         constexpr int NXF = 2 * TY * TZ, NYF = 2 * TX * TZ, NZF = C::D3 ? 2 * TX * TY : 0;
         constexpr int NH = NXF + NYF + NZF;
         constexpr int HPT = (NH + NT - 1) / NT;  // halo cells per thread
@@ -216,7 +222,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
         {
             double tv[NPT], fv[NPT], gv[NPT], mv[NPT];
             uint8_t pv[NPT];
-            double htv[HPT];
+            double htv[HPT], hmv[HPT];
             uint8_t hpv[HPT];
             uint32_t inb = 0, seed = 0;
 #pragma unroll
@@ -235,9 +241,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
                     pv[j] = A.par[gi];
                     fv[j] = A.field[gi];
                     gv[j] = A.g[gi];
-                    if (visited)
-                        mv[j] = as_f64(__hip_atomic_load((const uint64_t*)(A.mu + gi), __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT));
+                    mv[j] = as_f64(__hip_atomic_load((const uint64_t*)(A.mu + gi), __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT));
                     inb |= 1u << j;
                 }
             }
@@ -245,13 +250,16 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
             for (int k = 0; k < HPT; ++k) {
                 const int i = tid + k * NT;
                 htv[k] = inf64();
-                hpv[k] = 0x80;
+                hmv[k] = 0.0;
+                hpv[k] = 0x80;  // outside cells act as done sources
                 if (i < NH) {
                     int L, f;
                     const int64_t gi = halo_cell(i, L, f);
                     if (gi >= 0) {
                         htv[k] = A.t[gi];
                         hpv[k] = A.par[gi];
+                        hmv[k] = as_f64(__hip_atomic_load((const uint64_t*)(A.mu + gi), __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT));
                     }
                 }
             }
@@ -294,36 +302,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
                     (void)halo_cell(i, L, f);
                     sT[L] = htv[k];
                     sP[L] = hpv[k];
+                    sM[L] = (hpv[k] & 0x80) ? 0.0 : hmv[k];
                 }
             }
-        }
-        __syncthreads();
-        // halo mu: readable only where the neighbour tile has run (V), which
-        // it had before s_nb was read; sources and outside cells count as done
-        {
-            double hmv[HPT];
-            int hl[HPT];
-#pragma unroll
-            for (int k = 0; k < HPT; ++k) {
-                const int i = tid + k * NT;
-                hl[k] = -1;
-                hmv[k] = 0.0;
-                if (i < NH) {
-                    int L, f;
-                    const int64_t gi = halo_cell(i, L, f);
-                    hl[k] = L;
-                    if (gi >= 0 && !(sP[L] & 0x80)) {
-                        if (s_nb[f] & kV)
-                            hmv[k] = as_f64(__hip_atomic_load((const uint64_t*)(A.mu + gi), __ATOMIC_RELAXED,
-                                                              __HIP_MEMORY_SCOPE_AGENT));
-                        else
-                            hmv[k] = qnan64();
-                    }
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < HPT; ++k)
-                if (hl[k] >= 0) sM[hl[k]] = hmv[k];
         }
         __syncthreads();
         if (tid == 0) {

@@ -515,6 +515,8 @@ int adjoint(Workspace& w, const std::vector<Prob>& probs, int64_t ntiles, int64_
     hipLaunchKernelGGL(k_reset, dim3(blocks_for(std::max<int64_t>(ntiles, (int64_t)kRings * w.ring_cap), kThreads, 4096)),
                        dim3(kThreads), 0, st, s, w.tkey, (int)ntiles, w.scal + kSSrcCount,
                        (long long)kRings * w.ring_cap);
+    // mu := NaN (not done): a tile that has not run yet reads as not done
+    hipLaunchKernelGGL(k_fill_nan, dim3(blocks_for(npts, kThreads, 8192)), dim3(kThreads), 0, st, (long long)npts, mu);
     hipLaunchKernelGGL((k_adj_prep<TX, TY, TZ>), dim3((unsigned)std::min<int64_t>(ntiles, 65536)), dim3(kThreads),
                        0, st, T, (int)ntiles, t, w.tile_tmax, tref);
     hipLaunchKernelGGL(k_adj_push_all, dim3(blocks_for(ntiles, kThreads, 4096)), dim3(kThreads), 0, st,
