@@ -471,10 +471,20 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
                 }
             }
         }
+        // reduced within each wave, then one LDS atomic per wave
 #pragma unroll
-        for (int f = 0; f < 6; ++f)
-            if (fkey[f] < inf64()) atomicMin(&s_face[f], (unsigned long long)as_u64(fmax(fkey[f], 0.0)));
-        if (ndone) atomicAdd(&s_done, ndone);
+        for (int f = 0; f < 6; ++f) {
+            if (__ballot(fkey[f] < inf64())) {
+                const double m = wave_min(fkey[f]);
+                if (lane == 0) atomicMin(&s_face[f], (unsigned long long)as_u64(fmax(m, 0.0)));
+            }
+        }
+        {
+            unsigned int cnt = ndone;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+            if (cnt && lane == 0) atomicAdd(&s_done, cnt);
+        }
         stores_done();
         __syncthreads();
 

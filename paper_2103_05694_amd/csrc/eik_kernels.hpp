@@ -229,6 +229,13 @@ __device__ __forceinline__ void tstore(double* p, double v) {
     __hip_atomic_store((uint64_t*)p, as_u64(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Minimum over the 64 lanes of a wave (every lane gets it).
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+    return v;
+}
+
 // Dirty flags of the in-tile relaxation: one byte per point, stored so that
 // the NPT points of one thread (p = tid + j * NT) are adjacent and one LDS
 // access reads or clears all of them.
@@ -618,37 +625,40 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
             tm = now;
         }
         // ---- write back lowered points, gather lowered face minima ---------
-        unsigned int nchg = 0;
+        uint32_t chg = 0;  // bit j: point j was stored
         double fmin_[6] = {inf64(), inf64(), inf64(), inf64(), inf64(), inf64()};
 #pragma unroll
         for (int j = 0; j < NPT; ++j) {
             const int p = tid + j * NT;
             const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
             const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+            // the point and the six cells next to it, read together
+            const int L = C::lds(lx, ly, lz);
+            const double v = sT[L];
+            const double nxm = sT[L - 1], nxp = sT[L + 1], nym = sT[L - C::SY], nyp = sT[L + C::SY];
+            const double nzm = C::D3 ? sT[L - C::SZ] : inf64(), nzp = C::D3 ? sT[L + C::SZ] : inf64();
             if (x < P.nx && y < P.ny && z < P.nz) {
-                const double v = sT[C::lds(lx, ly, lz)];
                 if (v < t_in[j]) {
                     tstore(A.t + P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x, v);
-                    ++nchg;
+                    chg |= 1u << j;
                     // a lowered face value matters to the neighbour only where
                     // it is below the neighbour's own value there (its halo
                     // cell here, as staged; values only decrease): the
                     // operator ignores a neighbour above the point it updates
-                    const int L = C::lds(lx, ly, lz);
                     constexpr bool kAny = OP != 0;  // not causal: every lowered face value
-                    if (lx == 0 && (kAny || v < sT[L - 1])) fmin_[0] = fmin(fmin_[0], v);
-                    if (lx == TX - 1 && (kAny || v < sT[L + 1])) fmin_[1] = fmin(fmin_[1], v);
-                    if (ly == 0 && (kAny || v < sT[L - C::SY])) fmin_[2] = fmin(fmin_[2], v);
-                    if (ly == TY - 1 && (kAny || v < sT[L + C::SY])) fmin_[3] = fmin(fmin_[3], v);
+                    if (lx == 0 && (kAny || v < nxm)) fmin_[0] = fmin(fmin_[0], v);
+                    if (lx == TX - 1 && (kAny || v < nxp)) fmin_[1] = fmin(fmin_[1], v);
+                    if (ly == 0 && (kAny || v < nym)) fmin_[2] = fmin(fmin_[2], v);
+                    if (ly == TY - 1 && (kAny || v < nyp)) fmin_[3] = fmin(fmin_[3], v);
                     if (C::D3) {
-                        if (lz == 0 && (kAny || v < sT[L - C::SZ])) fmin_[4] = fmin(fmin_[4], v);
-                        if (lz == TZ - 1 && (kAny || v < sT[L + C::SZ])) fmin_[5] = fmin(fmin_[5], v);
+                        if (lz == 0 && (kAny || v < nzm)) fmin_[4] = fmin(fmin_[4], v);
+                        if (lz == TZ - 1 && (kAny || v < nzp)) fmin_[5] = fmin(fmin_[5], v);
                     }
                 } else if (OP != 0 && v != t_in[j]) {
                     // an ablation operator raised the value: store it, and with
                     // change tracking activate the neighbours across its faces
                     tstore(A.t + P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x, v);
-                    ++nchg;
+                    chg |= 1u << j;
                     if (S.track) {
                         if (lx == 0) fmin_[0] = fmin(fmin_[0], v);
                         if (lx == TX - 1) fmin_[1] = fmin(fmin_[1], v);
@@ -658,12 +668,26 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
                 }
             }
         }
+        // block-wide minima and counts: reduced within each wave first, then
+        // one LDS atomic per wave (per-lane atomics on one LDS word would be
+        // serialised lane by lane)
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
-            if (fmin_[f] < inf64()) atomicMin(&s_face[f], (unsigned long long)as_u64(fmin_[f]));
+            if (__ballot(fmin_[f] < inf64())) {
+                const double m = wave_min(fmin_[f]);
+                if (lane == 0) atomicMin(&s_face[f], (unsigned long long)as_u64(m));
+            }
         }
-        if (nchg) atomicAdd(&s_upd, nchg);
-        if (pend < inf64()) atomicMin(&s_pend, (unsigned long long)as_u64(pend));
+        {
+            int cnt = 0;
+#pragma unroll
+            for (int j = 0; j < NPT; ++j) cnt += __popcll(__ballot((chg >> j) & 1u));
+            if (cnt && lane == 0) atomicAdd(&s_upd, (unsigned int)cnt);
+        }
+        if (__ballot(pend < inf64())) {
+            const double m = wave_min(pend);
+            if (lane == 0) atomicMin(&s_pend, (unsigned long long)as_u64(m));
+        }
         // every wave's stores complete before the block hands the tile's faces
         // to the neighbours
         stores_done();

@@ -21,12 +21,6 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
-    return v;
-}
-
 template <int TX, int TY, int TZ, int NW>
 __global__ void __launch_bounds__(64 * NW) k_solve_w(SolveArgs A) {
     using C = TileCfg<TX, TY, TZ, 64>;
