@@ -482,16 +482,22 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
                     const int p = tid + j * NT;
                     const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
                     const int L = C::lds(lx, ly, lz);
+                    // the point and its six neighbours, read together
+                    const double c = sT[L];
+                    const double nxm = sT[L - 1], nxp = sT[L + 1], nym = sT[L - C::SY], nyp = sT[L + C::SY];
+                    const double nzm = C::D3 ? sT[L - C::SZ] : inf64(), nzp = C::D3 ? sT[L + C::SZ] : inf64();
+                    // smallest halo value next to the point (interior cells
+                    // do not count: they have not changed since the last run)
                     double hm = inf64();
-                    if (lx == 0) hm = fmin(hm, sT[L - 1]);
-                    if (lx == TX - 1) hm = fmin(hm, sT[L + 1]);
-                    if (ly == 0) hm = fmin(hm, sT[L - C::SY]);
-                    if (ly == TY - 1) hm = fmin(hm, sT[L + C::SY]);
+                    if (lx == 0 && nxm < hm) hm = nxm;
+                    if (lx == TX - 1 && nxp < hm) hm = nxp;
+                    if (ly == 0 && nym < hm) hm = nym;
+                    if (ly == TY - 1 && nyp < hm) hm = nyp;
                     if (C::D3) {
-                        if (lz == 0) hm = fmin(hm, sT[L - C::SZ]);
-                        if (lz == TZ - 1) hm = fmin(hm, sT[L + C::SZ]);
+                        if (lz == 0 && nzm < hm) hm = nzm;
+                        if (lz == TZ - 1 && nzp < hm) hm = nzp;
                     }
-                    if (hm < sT[L]) seed |= 1u << (8 * j);
+                    if (hm < c) seed |= 1u << (8 * j);
                 }
             }
             st_flags<NPT>(sDirty[0] + tid * NPT, seed);
