@@ -43,6 +43,8 @@ CASES = [
     ("3d_layered", lambda rng: (W.layered_3d(48, 40, 24, h=10.0, seed=9, sigma=3.0).field, 10.0,
                                 [W.flat_index(20, 21, 0, 48, 40)])),
     ("3d_ragged", lambda rng: (W.random_field((13, 17, 35), rng, 0.5, 4.0, block=2), 1.0, [9, 3000])),
+    # speeds over six orders of magnitude, point by point
+    ("3d_contrast", lambda rng: (10.0 ** rng.uniform(-3.0, 3.0, size=(10, 14, 22)), 2.5, [5, 2000])),
 ]
 
 

@@ -301,3 +301,27 @@ def test_autotune_candidates_agree(gpu, layered_small):
                       save=False, log=lambda s: None)
     assert len(e["candidates"]) == 2 * (1 * 2 + 2 * 2 * 2)
     assert tuple(e["tile"]) in ((8, 8, 8), (16, 8, 8))
+
+
+EXTREME = [((1, 70, 90), 1.0, 0), ((1, 64, 64), 1e-7, 1), ((12, 20, 33), 3.5e5, 0), ((9, 17, 26), 1.0, 1)]
+
+
+@pytest.mark.parametrize("shape,h,kind", EXTREME, ids=[f"{s[0]}x{s[1]}x{s[2]}_h{h:g}_k{k}" for s, h, k in EXTREME])
+def test_extreme_contrast_bitwise(gpu, O, shape, h, kind):
+    """Speeds log-uniform over twelve orders of magnitude, point by point, and
+    grid steps from 1e-7 to 3.5e5: neighbouring times differ by many orders,
+    so the exact operator's closed-form first guess can land far from the
+    answer and the search fallback decides.  Bitwise against the oracle for
+    both field kinds."""
+    rng = np.random.default_rng(41 + shape[1])
+    f = 10.0 ** rng.uniform(-6.0, 6.0, size=shape)
+    src = rng.choice(f.size, 3, replace=False).astype(np.int64)
+    ref = O.fmm(f, h, src, kind=kind)
+    assert np.all(np.isfinite(ref))
+    kname = "speed" if kind == 0 else "slowness"
+    q = h / f if kind == 0 else h * f
+    tiles = [(32, 32), (16, 16)] if shape[0] == 1 else [(8, 8, 8), (16, 8, 8), (8, 4, 4)]
+    for tile in tiles:
+        for delta in (0.0, 4.0 * float(np.median(q))):
+            t = gpu_solve(gpu, f, h, src, kind=kname, tile=tile, delta=delta)
+            assert_bitwise(t, ref, f"tile {tile} delta {delta:g}")
