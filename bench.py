@@ -75,13 +75,23 @@ def cpu_baseline() -> dict:
     import numpy as np  # noqa: F401
     import oracle
     import workloads as W
-    p = W.layered_3d(256, 256, 128, h=10.0, seed=2)
+    p = W.layered_3d(512, 512, 128, h=10.0, seed=2)
     t0 = time.perf_counter()
     oracle.fmm(p.field, p.h, p.src)
     dt = time.perf_counter() - t0
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": p.npts / dt, "unit": "grid points/s", "cores": 1, "kind": "oracle",
-            "sample": "same layered+noise recipe (seed 2, surface-centre source) at 256x256x128 = "
-                      f"{p.npts} points, one sequential binary-heap solve, {dt:.1f} s"}
+            "sample": "same layered+noise recipe (seed 2, surface-centre source) at 512x512x128 = "
+                      f"{p.npts} points, one sequential binary-heap solve, {dt:.1f} s",
+            "host_cpu": model, "host_threads": os.cpu_count()}
 
 
 def bench_single(args, torch, eik, W) -> dict:
