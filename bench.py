@@ -396,8 +396,8 @@ def main() -> int:
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(shots would shard across GPUs with one all-reduce of the gradient; not built).",
+        print("bench.py runs on exactly one GPU: there is no multi-GPU path (shots would shard "
+              "across GPUs with one all-reduce of the gradient; designed, not implemented).",
               file=sys.stderr)
         return 2
 
