@@ -74,28 +74,36 @@ def tune(field: torch.Tensor, h: float, sources, kind: str = "speed",
     ref = None
     results: List[dict] = []
     out = torch.empty_like(field)
+
+    def run(tile, fac, gb, hz):
+        nonlocal ref
+        delta = fac * qmed * min(tile[:nd])
+        fn = lambda: api.solve(field, h, sources, kind=kind, delta=delta, tile=tile, out=out,
+                               grid_blocks=gb, horizon=hz, check_status=False)
+        fn()
+        api.status()
+        t = out.clone()
+        if ref is None:
+            ref = t
+        elif not torch.equal(ref, t):
+            raise RuntimeError(f"candidate tile={tile} delta={delta} grid={gb} horizon={hz} changed the result")
+        sec = _time(fn, reps)
+        api.status()
+        results.append({"tile": list(tile), "delta": delta, "delta_factor": fac, "grid_blocks": gb,
+                        "horizon": hz, "ms": sec * 1e3})
+        log(f"  tile {tile} delta {delta:.4g} ({fac:.3g} x qmed x edge) grid {gb} horizon {hz}: "
+            f"{sec * 1e3:.3f} ms")
+
     for tile in tiles:
-        edge = min(tile[:nd])
         for fac in delta_factors:
-            delta = fac * qmed * edge
             for hz in (horizons if fac > 0 else (0,)):
                 for gb in grid_blocks:
-                    fn = lambda: api.solve(field, h, sources, kind=kind, delta=delta, tile=tile, out=out,
-                                           grid_blocks=gb, horizon=hz, check_status=False)
-                    fn()
-                    api.status()
-                    t = out.clone()
-                    if ref is None:
-                        ref = t
-                    elif not torch.equal(ref, t):
-                        raise RuntimeError(f"candidate tile={tile} delta={delta} grid={gb} horizon={hz} "
-                                           "changed the result")
-                    sec = _time(fn, reps)
-                    api.status()
-                    results.append({"tile": list(tile), "delta": delta, "delta_factor": fac, "grid_blocks": gb,
-                                    "horizon": hz, "ms": sec * 1e3})
-                    log(f"  tile {tile} delta {delta:.4g} ({fac} x qmed x edge) grid {gb} horizon {hz}: "
-                        f"{sec * 1e3:.3f} ms")
+                    run(tile, fac, gb, hz)
+    # refine the best bucket width between its neighbours on the doubling grid
+    best = min(results, key=lambda r: r["ms"])
+    if best["delta_factor"] > 0:
+        for step in (2.0 ** -0.5, 2.0 ** 0.5):
+            run(tuple(best["tile"]), best["delta_factor"] * step, best["grid_blocks"], best["horizon"])
     best = min(results, key=lambda r: r["ms"])
     entry = {"tile": best["tile"], "delta": best["delta"], "grid_blocks": best["grid_blocks"],
              "horizon": best["horizon"], "ms": best["ms"], "qmed": qmed, "candidates": results}
@@ -119,7 +127,7 @@ def lookup_batch(nshots: int, shape: Sequence[int], kind: str = "slowness") -> O
 def tune_batch(fields: Sequence[torch.Tensor], h: float, sources, receivers, kind: str = "slowness",
                tiles: Optional[Iterable[Tuple[int, ...]]] = None,
                delta_factors: Sequence[float] = (0.25, 0.5, 1.0, 2.0, 4.0),
-               adj_delta_factors: Sequence[float] = (0.0, 0.5, 1.0, 4.0),
+               adj_delta_factors: Sequence[float] = (0.0, 0.5, 1.0, 2.0, 4.0, 8.0),
                grid_blocks: Sequence[int] = (0,), reps: int = 2, save: bool = True, log=print) -> dict:
     """Tune a batch of shots (forward with parents, then the adjoint) in one
     persistent launch each: a batch has many times the parallel work of one
@@ -140,23 +148,31 @@ def tune_batch(fields: Sequence[torch.Tensor], h: float, sources, receivers, kin
     grad = torch.empty_like(t)
     fwd: List[dict] = []
     ref = None
+
+    def run_fwd(tile, fac, gb):
+        nonlocal ref
+        delta = fac * qmed * min(tile[:nd])
+        fn = lambda: api.solve_packed(b, t, par, delta, tile, grid_blocks=gb)
+        fn()
+        api.status()
+        if ref is None:
+            ref = (t.clone(), par.clone())
+        elif not (torch.equal(ref[0], t) and torch.equal(ref[1], par)):
+            raise RuntimeError(f"batch forward tile={tile} delta={delta} grid={gb} changed the result")
+        sec = _time(fn, reps)
+        api.status()
+        fwd.append({"tile": list(tile), "delta": delta, "delta_factor": fac, "grid_blocks": gb,
+                    "ms": sec * 1e3})
+        log(f"  batch forward tile {tile} delta {delta:.4g} grid {gb}: {sec * 1e3:.2f} ms")
+
     for tile in tiles:
-        edge = min(tile[:nd])
         for fac in delta_factors:
-            delta = fac * qmed * edge
             for gb in grid_blocks:
-                fn = lambda: api.solve_packed(b, t, par, delta, tile, grid_blocks=gb)
-                fn()
-                api.status()
-                if ref is None:
-                    ref = (t.clone(), par.clone())
-                elif not (torch.equal(ref[0], t) and torch.equal(ref[1], par)):
-                    raise RuntimeError(f"batch forward tile={tile} delta={delta} grid={gb} changed the result")
-                sec = _time(fn, reps)
-                api.status()
-                fwd.append({"tile": list(tile), "delta": delta, "delta_factor": fac, "grid_blocks": gb,
-                            "ms": sec * 1e3})
-                log(f"  batch forward tile {tile} delta {delta:.4g} grid {gb}: {sec * 1e3:.2f} ms")
+                run_fwd(tile, fac, gb)
+    bf = min(fwd, key=lambda r: r["ms"])
+    if bf["delta_factor"] > 0:
+        for step in (2.0 ** -0.5, 2.0 ** 0.5):
+            run_fwd(tuple(bf["tile"]), bf["delta_factor"] * step, bf["grid_blocks"])
     t.copy_(ref[0])
     par.copy_(ref[1])
     adj: List[dict] = []
