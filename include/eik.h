@@ -176,7 +176,11 @@ int eik_parents(const eik_grid* g, const double* t, int64_t nsrc, const int64_t*
  *   dL_dslowness [nz][ny][nx] output (device).  For a speed field the gradient
  *                is still with respect to slowness s = 1/v.
  *   mu_out       NULL or [nz][ny][nx] scratch output receiving mu (device);
- *                when NULL the library uses workspace memory. */
+ *                when NULL the library uses workspace memory.  It is filled
+ *                with NaN ("not done") first; on return it holds mu at every
+ *                point (0 at sources).  Its previous contents are not read.
+ * Errors as eik_solve (EIK_EINVAL for NULL pointers or a bad grid, EIK_EDOMAIN
+ * from the device for a bad field value, reported by eik_status). */
 int eik_adjoint(const eik_grid* g, const double* field, const double* t, const uint8_t* parents,
                 const double* dL_dt, double* dL_dslowness, double* mu_out,
                 const eik_opts* opts, void* stream);
