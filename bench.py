@@ -123,6 +123,14 @@ def bench_single(args, torch, eik, W) -> dict:
         "visits_per_tile": st.tile_visits / max(st.ntiles, 1),
         "updates_per_point": st.point_updates / p.npts,
         "passes_per_visit": st.relax_passes / max(st.tile_visits, 1),
+        # where the time goes (last solve): the kernel is bound by the latency
+        # of each run, not by bandwidth
+        "workgroups": int(st.workgroups),
+        "us_per_run": {name: st.phase_us[i] / max(st.tile_visits, 1)
+                       for i, name in enumerate(("claim_wait", "stage", "relax", "write_publish"))},
+        "runs_per_us": st.tile_visits / max(kernel_ms * 1e3, 1e-9),
+        "busy_fraction": (st.phase_us[1] + st.phase_us[2] + st.phase_us[3]) /
+                         max(st.workgroups * kernel_ms * 1e3, 1e-9),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_solve (persistent soft-priority tile solver)",
