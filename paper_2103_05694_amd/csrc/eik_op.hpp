@@ -67,19 +67,24 @@ __device__ __forceinline__ double est_sqrt(double x) {
 }
 
 // Closed-form Godunov estimate from sorted minima (u = r - a0 solves the one-,
-// two- or three-term quadratic), computed without branches so all three
-// candidates overlap; infinities select the right candidate (fmax drops NaN).
-// Accuracy only affects how often the exact search below needs its fallback.
+// two- or three-term quadratic), without branches; the regime test picks the
+// radicand so one square root serves both multi-term cases, and infinities
+// select the right candidate (fmax drops NaN).  Accuracy only affects how
+// often the exact search below needs its fallback.
 __device__ __forceinline__ double guess(double a0, double a1, double a2, double q, double c) {
     const double r1 = a0 + q;
     const double b1 = a1 - a0;
-    const double d2 = fmax(c + c - b1 * b1, 0.0);
-    const double r2 = a0 + 0.5 * (b1 + est_sqrt(d2));
     const double b2 = a2 - a0;
+    const double e2 = a2 - a1;
+    // the answer lies at or below a2 iff S(a2) >= c (always when a2 = +inf):
+    // then the two-term root, else the three-term one; one square root
+    const bool two = !(b2 < inf64()) || b2 * b2 + e2 * e2 >= c;
     const double sb = b1 + b2;
+    const double d2 = fmax(c + c - b1 * b1, 0.0);
     const double d3 = fmax(sb * sb - 3.0 * (b1 * b1 + b2 * b2 - c), 0.0);
-    const double r3 = a0 + (sb + est_sqrt(d3)) * (1.0 / 3.0);
-    return r1 <= a1 ? r1 : (r2 <= a2 ? r2 : r3);
+    const double sq = est_sqrt(two ? d2 : d3);
+    const double r = two ? a0 + 0.5 * (b1 + sq) : a0 + (sb + sq) * (1.0 / 3.0);
+    return r1 <= a1 ? r1 : r;
 }
 
 // Serial search kept for the rare inputs whose guess is more than one ulp off:
