@@ -568,7 +568,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
                 bool ch, mark;
                 double r;
                 if constexpr (OP == 0) {
-                    r = update(ax, ay, az, q, q * q, tc, ch);
+                    r = update<C::D3>(ax, ay, az, q, q * q, tc, ch);
                     if (ch && !(r * S.inv_delta < hz)) {
                         pend = fmin(pend, r);
                         ch = false;

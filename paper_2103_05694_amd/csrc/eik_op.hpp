@@ -35,12 +35,15 @@ __device__ __forceinline__ double inf64() { return as_f64(kInfBits); }
 // fl(m * m) with m = max(d, 0): for d > 0 that is fl(d * d), otherwise m is a
 // zero of either sign and the square is +0, so the bits are those of the
 // definition (d is never NaN: r is finite and every a_k is finite or +inf).
+template <bool D3 = true>
 __device__ __forceinline__ bool reaches(double r, double a0, double a1, double a2, double c) {
     const double m0 = fmax(r - a0, 0.0);
     const double m1 = fmax(r - a1, 0.0);
-    const double m2 = fmax(r - a2, 0.0);
     double s = m0 * m0 + m1 * m1;
-    s = s + m2 * m2;
+    if constexpr (D3) {
+        const double m2 = fmax(r - a2, 0.0);
+        s = s + m2 * m2;
+    }
     return s >= c;
 }
 
@@ -71,6 +74,7 @@ __device__ __forceinline__ double est_sqrt(double x) {
 // radicand so one square root serves both multi-term cases, and infinities
 // select the right candidate (fmax drops NaN).  Accuracy only affects how
 // often the exact search below needs its fallback.
+template <bool D3 = true>
 __device__ __forceinline__ double guess(double a0, double a1, double a2, double q, double c) {
     const double r1 = a0 + q;
     const double b1 = a1 - a0;
@@ -78,7 +82,7 @@ __device__ __forceinline__ double guess(double a0, double a1, double a2, double 
     const double e2 = a2 - a1;
     // the answer lies at or below a2 iff S(a2) >= c (always when a2 = +inf):
     // then the two-term root, else the three-term one; one square root
-    const bool two = !(b2 < inf64()) || b2 * b2 + e2 * e2 >= c;
+    const bool two = !D3 || !(b2 < inf64()) || b2 * b2 + e2 * e2 >= c;
     const double sb = b1 + b2;
     const double d2 = fmax(c + c - b1 * b1, 0.0);
     const double d3 = fmax(sb * sb - 3.0 * (b1 * b1 + b2 * b2 - c), 0.0);
@@ -130,19 +134,32 @@ __device__ __noinline__ double search_slow(double a0, double a1, double a2, doub
 // clamped to [A0 + 2, prev(tcur)], so G - 2 >= A0 (where the predicate is
 // false when G - 2 == A0, as S(a0) = 0 < c).  Otherwise the serial search
 // decides.
+//
+// D3 = false (two-dimensional grids, z = +inf) drops the third term: it is +0
+// there, and adding +0 to a sum of squares (itself >= +0) changes no bit.
+template <bool D3 = true>
 __device__ __forceinline__ double update(double x, double y, double z, double q, double c,
                                          double tcur, bool& changed) {
     changed = false;
-    double a0 = x, a1 = y, a2 = z;
-    sort3(a0, a1, a2);
+    double a0, a1, a2;
+    if constexpr (D3) {
+        a0 = x;
+        a1 = y;
+        a2 = z;
+        sort3(a0, a1, a2);
+    } else {
+        a0 = fmin(x, y);
+        a1 = fmax(x, y);
+        a2 = inf64();
+    }
     if (!(a0 < tcur)) return tcur;                 // result > a0 >= tcur: nothing to do
     const uint64_t tcb = as_u64(tcur);
     // most evaluations in a relaxation do not improve the point: one predicate
     // rejects them before the guess is computed
-    if (!reaches(as_f64(tcb - 1), a0, a1, a2, c)) return tcur;
+    if (!reaches<D3>(as_f64(tcb - 1), a0, a1, a2, c)) return tcur;
     const uint64_t A0 = as_u64(a0);
     // reaches(tcb - 1) is false whenever tcb - 1 <= A0, so here tcb - 1 > A0
-    uint64_t G = as_u64(guess(a0, a1, a2, q, c));
+    uint64_t G = as_u64(guess<D3>(a0, a1, a2, q, c));
     if (!(G >= A0 + 2)) G = A0 + 2;                // also catches a NaN pattern
     if (G > tcb - 1) G = tcb - 1;
     // S is non-decreasing in r, so the four outcomes are false...false
@@ -157,11 +174,13 @@ __device__ __forceinline__ double update(double x, double y, double z, double q,
 #pragma unroll
     for (int k = 0; k < 4; ++k) m1[k] = fmax(r[k] - a1, 0.0);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) m2[k] = fmax(r[k] - a2, 0.0);
-#pragma unroll
     for (int k = 0; k < 4; ++k) sm[k] = m0[k] * m0[k] + m1[k] * m1[k];
+    if constexpr (D3) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) sm[k] = sm[k] + m2[k] * m2[k];
+        for (int k = 0; k < 4; ++k) m2[k] = fmax(r[k] - a2, 0.0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sm[k] = sm[k] + m2[k] * m2[k];
+    }
     int cnt = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) cnt += sm[k] >= c ? 1 : 0;

@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(64 * NW) k_solve_w(SolveArgs A) {
                     const double ax = fmin(sT[L - 1], sT[L + 1]);
                     const double ay = fmin(sT[L - C::SY], sT[L + C::SY]);
                     const double az = C::D3 ? fmin(sT[L - C::SZ], sT[L + C::SZ]) : inf64();
-                    const double r = update(ax, ay, az, q, q * q, tc, ch);
+                    const double r = update<C::D3>(ax, ay, az, q, q * q, tc, ch);
                     if (ch) sT[L] = r;
                 }
                 // append the in-tile neighbours of lowered points, once each
