@@ -129,11 +129,12 @@ __device__ __noinline__ double search_slow(double a0, double a1, double a2, doub
 //
 // First r < tcur  <=>  S(prev(tcur)) >= c (S is monotone), so one predicate
 // rejects every non-improving update.  Then the predicate is evaluated at
-// G-2 .. G+1 around the guess G as four independent chains; the answer is the
-// first of G-1, G, G+1 that satisfies it while the one below does not.  G is
-// clamped to [A0 + 2, prev(tcur)], so G - 2 >= A0 (where the predicate is
-// false when G - 2 == A0, as S(a0) = 0 < c).  Otherwise the serial search
-// decides.
+// G-1, G, G+1 around the guess G as three independent chains; the answer is G
+// or G+1 when it is the first of them that satisfies it while the one below
+// does not.  (Measured over whole solves, the guess is never more than one
+// ulp below the answer and never above it, so this window decides every
+// case; the serial search covers the rest.)  G is clamped to
+// [A0 + 2, prev(tcur)], so G - 1 > A0.
 //
 // D3 = false (two-dimensional grids, z = +inf) drops the third term: it is +0
 // there, and adding +0 to a sum of squares (itself >= +0) changes no bit.
@@ -162,30 +163,30 @@ __device__ __forceinline__ double update(double x, double y, double z, double q,
     uint64_t G = as_u64(guess<D3>(a0, a1, a2, q, c));
     if (!(G >= A0 + 2)) G = A0 + 2;                // also catches a NaN pattern
     if (G > tcb - 1) G = tcb - 1;
-    // S is non-decreasing in r, so the four outcomes are false...false
-    // true...true and their count locates the answer: 3 -> G-1, 2 -> G,
-    // 1 -> G+1; 4 (the answer is below G-1) or 0 (above G+1) need the search.
-    // The chains are written side by side so that they interleave.
-    double r[4], m0[4], m1[4], m2[4], sm[4];
+    // S is non-decreasing in r, so the three outcomes are false...false
+    // true...true and their count locates the answer: 2 -> G, 1 -> G+1;
+    // 3 (the answer is below G) or 0 (above G+1) need the search.  The
+    // chains are written side by side so that they interleave.
+    double r[3], m0[3], m1[3], m2[3], sm[3];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) r[k] = as_f64(G - 2 + (uint64_t)k);
+    for (int k = 0; k < 3; ++k) r[k] = as_f64(G - 1 + (uint64_t)k);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) m0[k] = fmax(r[k] - a0, 0.0);
+    for (int k = 0; k < 3; ++k) m0[k] = fmax(r[k] - a0, 0.0);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) m1[k] = fmax(r[k] - a1, 0.0);
+    for (int k = 0; k < 3; ++k) m1[k] = fmax(r[k] - a1, 0.0);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) sm[k] = m0[k] * m0[k] + m1[k] * m1[k];
+    for (int k = 0; k < 3; ++k) sm[k] = m0[k] * m0[k] + m1[k] * m1[k];
     if constexpr (D3) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) m2[k] = fmax(r[k] - a2, 0.0);
+        for (int k = 0; k < 3; ++k) m2[k] = fmax(r[k] - a2, 0.0);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) sm[k] = sm[k] + m2[k] * m2[k];
+        for (int k = 0; k < 3; ++k) sm[k] = sm[k] + m2[k] * m2[k];
     }
     int cnt = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) cnt += sm[k] >= c ? 1 : 0;
+    for (int k = 0; k < 3; ++k) cnt += sm[k] >= c ? 1 : 0;
     changed = true;
-    if (cnt == 0 || cnt == 4) return search_slow(a0, a1, a2, c, A0, G, tcb);
+    if (cnt == 0 || cnt == 3) return search_slow(a0, a1, a2, c, A0, G, tcb);
     return as_f64(G + 2 - (uint64_t)cnt);
 }
 
