@@ -329,3 +329,35 @@ def test_extreme_contrast_bitwise(gpu, O, shape, h, kind):
         for delta in (0.0, 4.0 * float(np.median(q))):
             t = gpu_solve(gpu, f, h, src, kind=kname, tile=tile, delta=delta)
             assert_bitwise(t, ref, f"tile {tile} delta {delta:g}")
+
+
+def test_every_point_a_source(gpu, O):
+    """Degenerate case: every point is fixed, so nothing is updated and the
+    output is t0 bit for bit (zeros included)."""
+    rng = np.random.default_rng(61)
+    for shape in ((1, 33, 47), (5, 9, 17)):
+        f = W.random_field(shape, rng, 0.5, 2.0)
+        src = np.arange(f.size, dtype=np.int64)
+        t0 = rng.uniform(0.0, 10.0, f.size)
+        t0[::7] = 0.0
+        ref = O.fmm(f, 1.0, src, t0)
+        assert np.array_equal(ref.reshape(-1), t0)
+        tiles = [(32, 32), (16, 16)] if shape[0] == 1 else [(8, 8, 8), (16, 8, 8)]
+        for tile in tiles:
+            t = gpu_solve(gpu, f, 1.0, src, t0, tile=tile, delta=0.5)
+            assert_bitwise(t, ref, f"{shape} tile {tile}")
+
+
+def test_plane_of_sources_with_mixed_t0(gpu, O):
+    """A whole surface plane of sources whose start times span six orders of
+    magnitude: the front starts everywhere at once, out of order."""
+    rng = np.random.default_rng(62)
+    f = W.random_field((20, 24, 40), rng, 0.5, 4.0, block=4)
+    iy, ix = np.meshgrid(np.arange(24), np.arange(40), indexing="ij")
+    src = W.flat_index(ix.ravel(), iy.ravel(), 0, 40, 24)
+    t0 = 10.0 ** rng.uniform(-3.0, 3.0, src.size)
+    ref = O.fmm(f, 1.0, src, t0)
+    for tile in ((8, 8, 8), (16, 8, 8), (32, 8, 4)):
+        for delta in (0.0, 0.5, 20.0):
+            t = gpu_solve(gpu, f, 1.0, src, t0, tile=tile, delta=delta)
+            assert_bitwise(t, ref, f"tile {tile} delta {delta}")
