@@ -145,3 +145,23 @@ def test_batched_adjoint_equals_per_problem(gpu, O):
         tr = O.fmm(f, 1.0, s)
         ref = O.adjoint(tr, O.parents(tr, s), f, 1.0, g)
         assert_close_or_equal(gr.cpu().numpy(), ref, "batched adjoint")
+
+
+def test_adjoint_degenerate_gradients(gpu, O):
+    """dL/dt = 0 gives a zero gradient everywhere; dL/dt only at the sources
+    also gives zero (a source has no parents to pass it on to); both agree with
+    the oracle bit for bit."""
+    rng = np.random.default_rng(71)
+    f = W.random_field((9, 14, 21), rng, 0.5, 3.0, block=3)
+    src = np.array([5, 1000, 2500], dtype=np.int64)
+    t = O.fmm(f, 1.0, src)
+    par = O.parents(t, src)
+    for name, g in (("zero", np.zeros(f.shape)), ("sources", np.zeros(f.shape))):
+        if name == "sources":
+            g.reshape(-1)[src] = rng.standard_normal(src.size)
+        ref = O.adjoint(t, par, f, 1.0, g)
+        assert not np.any(ref)
+        for tile in ((8, 8, 8), (16, 8, 8)):
+            grad = gpu.adjoint(to_gpu(f), 1.0, to_gpu(t), to_gpu(par), to_gpu(g), tile=tile)
+            got = grad.cpu().numpy().reshape(f.shape)
+            assert np.array_equal(got, ref), (name, tile)
