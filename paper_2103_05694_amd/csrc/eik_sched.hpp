@@ -145,8 +145,11 @@ __device__ __forceinline__ int64_t bucket_of(const Sched& s, double t) {
 // `pending`.  `base` is the bucket the pushing run was claimed from (0 before
 // the solve starts): `cur` cannot pass it while that run is live and is at least
 // base - lookahead, so buckets in [base, base + nrings - 1 - lookahead] never
-// alias a bucket behind `cur`.  Single lane.
-__device__ __forceinline__ void push_tile(const Sched& s, uint32_t tile, double t, int64_t base) {
+// alias a bucket behind `cur`.  With count = false the ring's queued count is
+// left to the caller, which must add it after its stores are done and before
+// it ends the run (publish folds it into the end-of-run RMW).  Single lane.
+__device__ __forceinline__ void push_tile(const Sched& s, uint32_t tile, double t, int64_t base,
+                                          bool count = true) {
     int64_t k = bucket_of(s, t);
     if (k < base) k = base;
     if (k > base + s.nrings - 1 - s.lookahead) k = base + s.nrings - 1 - s.lookahead;
@@ -165,6 +168,7 @@ __device__ __forceinline__ void push_tile(const Sched& s, uint32_t tile, double 
         __builtin_amdgcn_s_sleep(1);
     }
     __hip_atomic_store(cell, ((uint64_t)(pos + 1u) << 32) | tile, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!count) return;
     // everything this wave did before (the live-work count included) completes
     // before the item becomes claimable
     stores_done();
@@ -371,16 +375,37 @@ __device__ __forceinline__ int publish(const Sched& s, uint64_t* tkey, uint32_t 
         if (delta != 0)
             __hip_atomic_fetch_add(s.pending, delta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (want && lane != cl) push_tile(s, n, as_f64(fk), bucket);
+    // Pushes into this run's own bucket leave their queued count to the one
+    // RMW below, which also ends the run (or, for a hand-on, just adds them):
+    // their cells are stored first, and the run stays counted until that RMW,
+    // so the bucket never looks drained with work of it uncounted.  Pushes to
+    // other buckets count themselves, and that completes before the RMW too.
+    const bool pushme = want && lane != cl;
+    const bool same = pushme && push_bucket(s, as_f64(fk), bucket) == bucket;
+    if (pushme) push_tile(s, n, as_f64(fk), bucket, !same);
+    bool rq_same = false;
     if (lane == 0 && requeue) {
         uint64_t kb = __hip_atomic_exchange((unsigned long long*)(tkey + tile), kInfBits, __ATOMIC_RELAXED,
                                             __HIP_MEMORY_SCOPE_AGENT);
         if (self_key < kb) kb = self_key;
-        push_tile(s, tile, kb == kInfBits ? 0.0 : as_f64(kb), bucket);
+        const double key = kb == kInfBits ? 0.0 : as_f64(kb);
+        rq_same = push_bucket(s, key, bucket) == bucket;
+        push_tile(s, tile, key, bucket, !rq_same);
     }
-    if (cl >= 0) return (int)__shfl(n, cl);
+    const uint64_t nsame = (uint64_t)__popcll(__ballot(same)) + (uint64_t)__popcll(__ballot(rq_same));
+    const int ring = (int)(bucket % s.nrings);
+    if (cl >= 0) {
+        if (lane == 0 && nsame) {
+            stores_done();
+            cr_add(s, ring, nsame);
+        }
+        return (int)__shfl(n, cl);
+    }
     // this run's own pushes are counted: the bucket it came from may now drain
-    if (lane == 0) end_run(s, bucket);
+    if (lane == 0) {
+        stores_done();
+        cr_add(s, ring, nsame - kRunOne);
+    }
     return -1;
 }
 
