@@ -27,7 +27,9 @@
  *    the library only reads/writes them inside work enqueued on `stream`.
  *  - All work is enqueued on `stream` (a hipStream_t, NULL = default stream);
  *    only eik_status(), eik_residual() and eik_timeline() synchronise the host
- *    (and the first call of a given batch layout, which uploads its table).
+ *    (and the first call with a given batch layout -- problems, tile shape,
+ *    source offsets -- which uploads its table; up to 64 layouts are kept per
+ *    workspace).
  *  - The library owns a workspace per (device, stream) (tile states, priority
  *    queues, counters), allocated on first use, grown on demand and freed by
  *    eik_release().  Two calls on the same stream are ordered; calls on
@@ -58,13 +60,24 @@ extern "C" {
 #define EIK_EHANG (-8)    /* a device-side watchdog expired (internal error) */
 
 #define EIK_FLAG_TIME_KERNELS 1u  /* eik_opts.flags: time the persistent kernel with HIP events */
-#define EIK_FLAG_WAVE_TILES 2u    /* eik_opts.flags: forward solve with one tile per wave (tiles
-                                     3D 8x8x4, 16x8x4, 8x8x8, 16x4x4; 2D 16x16, 32x16, 32x8) */
+                                  /* bit value 2 is unused (rejected as unknown) */
 #define EIK_FLAG_TIMELINE 4u      /* eik_opts.flags: record when the lowest open priority bucket
                                      moves on (read back with eik_timeline) */
 #define EIK_FLAG_TRACK_CHANGE 8u  /* eik_opts.flags, ablation operators only: re-activate the
                                      neighbours when a value changes, not only when it decreases
                                      (the precision section's change tracking) */
+#define EIK_FLAG_WARM_START 16u   /* eik_opts.flags, forward solves with EIK_OP_DBAR: resume from
+                                     the times already in t_out instead of +inf.  They must be
+                                     an upper bound of the solution at every point (>= +0, not
+                                     NaN; +inf allowed), e.g. the output of a call on the same
+                                     problem that stopped with EIK_ELIMIT.  The operator is
+                                     monotone and causal, so from any such state every update
+                                     order reaches the same fixed point as a cold solve (the
+                                     argument of Theorem 1): the result is bit-identical.
+                                     Sources are fixed at their t0 again; every tile with a
+                                     finite value in itself or a face neighbour is queued.  A
+                                     NaN or negative (sign bit set) input value is replaced by
+                                     +inf and reported by eik_status as EIK_EINVAL. */
 
 #define EIK_OP_DBAR 0     /* eik_opts.op: smallest double with S(r) >= c (section "Achieving
                              Exact Monotonicity with Finite Precision Arithmetic") */
@@ -84,7 +97,9 @@ typedef struct {
 } eik_grid;
 
 typedef struct {
-    double delta;            /* priority bucket width in time units; 0 => one bucket (FIFO) */
+    double delta;            /* priority bucket width in time units; 0 => one bucket (FIFO);
+                                EIK_EINVAL when negative, NaN or so small that 1/delta
+                                overflows */
     int32_t tile[3];         /* tile shape (x, y, z); zeros => default for ndim (3D 16x8x8,
                                 2D 32x32).  Supported: 3D 32x8x4, 16x8x8, 8x8x8, 64x4x4,
                                 16x8x4, 8x8x4, 8x4x4; 2D 32x32, 64x16, 128x8, 16x16, 16x8 */
@@ -94,7 +109,8 @@ typedef struct {
                                 around the persistent kernel (solve or adjoint) on `stream`;
                                 eik_status then reports the mean duration of the kernels timed
                                 since the previous eik_status (at most 4096 launches in
-                                between).  EIK_FLAG_WAVE_TILES, EIK_FLAG_TIMELINE: above */
+                                between).  EIK_FLAG_TIMELINE, EIK_FLAG_TRACK_CHANGE,
+                                EIK_FLAG_WARM_START: above */
     int32_t lookahead;       /* 0..8: work may be taken from the lowest non-drained bucket
                                 and this many buckets above it (0 = strict bucket order) */
     int32_t horizon;         /* 0 => off; k in 1..4: a run of a tile claimed from bucket b
@@ -146,7 +162,8 @@ typedef struct {
  *   src_idx  nsrc flat indices (iz*ny+iy)*nx+ix (device int64).  Duplicates are
  *            allowed (the smallest start time wins).
  *   src_t0   nsrc start times >= +0.0 and finite (device), or NULL for all +0.0.
- *   t_out    [nz][ny][nx] arrival times (device, written entirely).
+ *   t_out    [nz][ny][nx] arrival times (device, written entirely; with
+ *            EIK_FLAG_WARM_START also read first: the starting upper bound).
  *   parents_out  NULL, or [nz][ny][nx] uint8 upwind-parent record computed from
  *            the final times: per axis k (bits 2k..2k+1) 0 = axis not upwind,
  *            1 = minus-side neighbour, 2 = plus-side neighbour (ties: minus);

@@ -367,6 +367,66 @@ done:
     return rc;
 }
 
+/* Fast marching resumed from a given state.  On entry t holds, at every point,
+ * an upper bound of the solution (>= +0 and not NaN; +inf allowed).  Sources
+ * are fixed at their start times again, every other point keeps its value, and
+ * every point with a finite value is queued; then the loop of Algorithm "Fast
+ * Marching Method" runs as in orc_fmm with the exact monotone operator.  Since
+ * that operator is monotone and causal, the state never drops below the
+ * solution and every point is re-evaluated after its upwind neighbours last
+ * changed, so the result is the one fixed point of Theorem 1 whatever upper
+ * bound the loop started from.  With max_pops > 0 the loop stops after that
+ * many non-stale pops and returns 1, leaving a state that is still an upper
+ * bound (it can be resumed again); otherwise it returns 0 when the heap is
+ * empty.  -5: a start value was NaN or negative. */
+int orc_fmm_resume(int ndim, int64_t nx, int64_t ny, int64_t nz, double h, const double *field,
+                   int kind, int64_t nsrc, const int64_t *src, const double *t0, int64_t max_pops,
+                   double *t, int64_t *stats) {
+    grid_t g = mkgrid(ndim, nx, ny, nz, h);
+    double *start = (double *)malloc(sizeof(double) * (size_t)g.n);
+    if (!start) return -2;
+    for (int64_t i = 0; i < g.n; ++i) {
+        if (t[i] != t[i] || signbit(t[i])) { free(start); return -5; }
+        start[i] = t[i];
+    }
+    double *q;
+    uint8_t *fixed;
+    int rc = setup(&g, field, kind, nsrc, src, t0, t, &q, &fixed);
+    if (rc) { free(start); return rc; }
+    for (int64_t i = 0; i < g.n; ++i)
+        if (!fixed[i]) t[i] = start[i];
+    free(start);
+    heap_t hp = {0, 0, 0};
+    int64_t pops = 0, applies = 0, accepts = 0;
+    for (int64_t i = 0; i < g.n; ++i)
+        if (t[i] < INFINITY && heap_push(&hp, t[i], i)) { rc = -2; goto done; }
+    while (hp.n > 0) {
+        if (max_pops > 0 && pops >= max_pops) { rc = 1; break; }
+        item_t it = heap_pop(&hp);
+        if (it.t != t[it.i]) continue;
+        ++pops;
+        int64_t nb[6];
+        int k = nbrs(&g, it.i, nb);
+        for (int j = 0; j < k; ++j) {
+            int64_t m = nb[j];
+            if (fixed[m]) continue;
+            double r = apply_op(&g, t, q, m, OP_DBAR);
+            ++applies;
+            if (r < t[m]) {
+                t[m] = r;
+                ++accepts;
+                if (heap_push(&hp, r, m)) { rc = -2; goto done; }
+            }
+        }
+    }
+done:
+    if (stats) { stats[0] = pops; stats[1] = applies; stats[2] = accepts; }
+    free(hp.a);
+    free(q);
+    free(fixed);
+    return rc;
+}
+
 /* Topology-driven schedule (Algorithm "topology-driven"): apply the operator at
  * every point, in index order, until a whole round changes nothing. */
 int orc_sweep_all(int ndim, int64_t nx, int64_t ny, int64_t nz, double h, const double *field,

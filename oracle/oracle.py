@@ -9,6 +9,8 @@ Each function cites the passage of the paper it follows:
                          extended to the one-sided case and to three axes.
   * ``fmm``           -- Algorithm "Fast Marching Method" with the update
                          operator of Algorithm "Eikonal Update Operator".
+  * ``fmm_resume``    -- the same loop started from any upper bound of the
+                         solution (checkpoint / resume; Theorem 1's argument).
   * ``sweep_all``     -- the topology-driven schedule (rounds over all nodes).
   * ``fsm``           -- Algorithm "Fast Sweeping Method".
   * ``async_random``  -- an unordered worklist with random priority inversions
@@ -71,6 +73,9 @@ def lib():
         L.orc_async_random.restype = _int
         L.orc_async_random.argtypes = [_int, _i64, _i64, _i64, _d, _ptr, _int, _i64, _ptr, _ptr,
                                        _int, ctypes.c_uint64, _int, _ptr, _ptr]
+        L.orc_fmm_resume.restype = _int
+        L.orc_fmm_resume.argtypes = [_int, _i64, _i64, _i64, _d, _ptr, _int, _i64, _ptr, _ptr, _i64,
+                                     _ptr, _ptr]
         L.orc_residual.restype = _i64
         L.orc_residual.argtypes = [_int, _i64, _i64, _i64, _d, _ptr, _int, _i64, _ptr, _ptr,
                                    _int, ctypes.POINTER(_d)]
@@ -174,6 +179,25 @@ def fmm(field, h, src, t0=None, kind=SPEED, op=OP_DBAR, ndim=None, return_stats=
     """Binary-heap fast marching; returns t with the field's shape."""
     t, st = _solve("orc_fmm", field, h, src, t0, kind, op, ndim)
     return (t, st) if return_stats else t
+
+
+def fmm_resume(field, h, src, t_start, t0=None, kind=SPEED, ndim=None, max_pops: int = 0):
+    """Fast marching resumed from `t_start` (an upper bound of the solution at
+    every point, +inf allowed), sources fixed again.  Returns (t, finished):
+    finished is False when max_pops > 0 stopped the loop early, leaving an
+    upper bound that can be resumed again."""
+    field, nx, ny, nz, src, t0 = _prep(field, src, t0)
+    if ndim is None:
+        ndim = 2 if nz == 1 else 3
+    t = np.array(_f64(t_start).reshape(field.shape), copy=True)
+    stats = np.zeros(3, dtype=np.int64)
+    rc = lib().orc_fmm_resume(ndim, nx, ny, nz, float(h), _p(field), kind, src.size, _p(src), _p(t0),
+                              int(max_pops), _p(t), _p(stats))
+    if rc == -5:
+        raise OracleError("fmm_resume: a start value is NaN or negative")
+    if rc not in (0, 1):
+        _check(rc, "fmm_resume")
+    return t, rc == 0
 
 
 def sweep_all(field, h, src, t0=None, kind=SPEED, op=OP_DBAR, ndim=None):

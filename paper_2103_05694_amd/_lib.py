@@ -24,13 +24,13 @@ EIK_EHANG = -8
 EIK_SPEED = 0
 EIK_SLOWNESS = 1
 EIK_FLAG_TIME_KERNELS = 1
-EIK_FLAG_WAVE_TILES = 2
 EIK_FLAG_TIMELINE = 4
 EIK_OP_DBAR = 0
 EIK_OP_DHAT = 1
 EIK_OP_DTILDE = 2
 EIK_OP_NEWTON = 3
 EIK_FLAG_TRACK_CHANGE = 8
+EIK_FLAG_WARM_START = 16
 
 EXPORTED = (
     "eik_solve", "eik_parents", "eik_adjoint", "eik_solve_batched", "eik_adjoint_batched",

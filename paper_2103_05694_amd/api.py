@@ -39,9 +39,9 @@ def _grid_of(shape: Sequence[int], h: float, kind: str) -> eik_grid:
 
 def make_opts(delta: float = 0.0, tile: Optional[Sequence[int]] = None, grid_blocks: int = 0,
               max_tile_visits: int = 0, time_kernels: bool = False, lookahead: int = 0,
-              wave_tiles: bool = False, timeline: bool = False, op: str = "dbar",
-              horizon: int = 0, work_ref: Optional[torch.Tensor] = None,
-              track_change: bool = False) -> eik_opts:
+              timeline: bool = False, op: str = "dbar", horizon: int = 0,
+              work_ref: Optional[torch.Tensor] = None, track_change: bool = False,
+              warm_start: bool = False) -> eik_opts:
     o = eik_opts()
     o.delta = float(delta)
     t = tuple(tile) if tile else (0, 0, 0)
@@ -52,8 +52,8 @@ def make_opts(delta: float = 0.0, tile: Optional[Sequence[int]] = None, grid_blo
     o.grid_blocks = int(grid_blocks)
     o.max_tile_visits = int(max_tile_visits)
     o.flags = (_lib.EIK_FLAG_TIME_KERNELS if time_kernels else 0) | \
-        (_lib.EIK_FLAG_WAVE_TILES if wave_tiles else 0) | (_lib.EIK_FLAG_TIMELINE if timeline else 0) | \
-        (_lib.EIK_FLAG_TRACK_CHANGE if track_change else 0)
+        (_lib.EIK_FLAG_TIMELINE if timeline else 0) | (_lib.EIK_FLAG_TRACK_CHANGE if track_change else 0) | \
+        (_lib.EIK_FLAG_WARM_START if warm_start else 0)
     o.lookahead = int(lookahead)
     o.horizon = int(horizon)
     o.op = _op_code(op)
@@ -78,6 +78,22 @@ def _check_field(field: torch.Tensor) -> None:
         raise ValueError("field must live on the GPU (there is no CPU path)")
     if not field.is_contiguous():
         raise ValueError("field must be contiguous")
+
+
+def _check_buf(buf: torch.Tensor, name: str, dtype: torch.dtype, numel: int, device: torch.device) -> None:
+    """A caller-supplied buffer the kernels read or write through a raw
+    pointer: it must have exactly the dtype, element count and device the call
+    assumes, and be contiguous (checked before anything is launched)."""
+    if not isinstance(buf, torch.Tensor):
+        raise TypeError(f"{name} must be a tensor")
+    if buf.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {buf.dtype}")
+    if buf.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {buf.numel()}")
+    if buf.device != device:
+        raise ValueError(f"{name} must be on {device}, got {buf.device}")
+    if not buf.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
 
 
 def source_indices(sources, shape: Sequence[int], device) -> torch.Tensor:
@@ -157,12 +173,16 @@ def solve(field: torch.Tensor, h: float, sources, t0: Optional[torch.Tensor] = N
           tile: Optional[Sequence[int]] = None, grid_blocks: int = 0, max_tile_visits: int = 0,
           out: Optional[torch.Tensor] = None, parents_out: Optional[torch.Tensor] = None,
           check_status: bool = True, stream=None, time_kernels: bool = False, lookahead: int = 0,
-          wave_tiles: bool = False, timeline: bool = False, op: str = "dbar", horizon: int = 0,
-          work_ref: Optional[torch.Tensor] = None, track_change: bool = False):
-    """First-arrival times; returns t, or (t, parents) when parents=True.  `wave_tiles`
-    selects the one-tile-per-wave solver (tile shapes 3D 8x8x4, 16x8x4, 8x8x8,
-    16x4x4; 2D 16x16, 32x16, 32x8)."""
+          timeline: bool = False, op: str = "dbar", horizon: int = 0,
+          work_ref: Optional[torch.Tensor] = None, track_change: bool = False, warm_start: bool = False):
+    """First-arrival times; returns t, or (t, parents) when parents=True.
+
+    With warm_start=True the solve resumes from the times in `out` (required):
+    any upper bound of the solution, e.g. the output of a solve stopped by
+    max_tile_visits; the result is bit-identical to a cold solve."""
     _check_field(field)
+    if warm_start and out is None:
+        raise ValueError("warm_start needs the starting times in `out`")
     L = _lib.load()
     g = _grid_of(field.shape, h, kind)
     src = source_indices(sources, field.shape, field.device)
@@ -171,17 +191,21 @@ def solve(field: torch.Tensor, h: float, sources, t0: Optional[torch.Tensor] = N
         t0d = torch.as_tensor(t0, dtype=torch.float64).reshape(-1).to(field.device).contiguous()
         if t0d.numel() != src.numel():
             raise ValueError("t0 needs one value per source")
+    if out is not None:
+        _check_buf(out, "out", torch.float64, field.numel(), field.device)
     t = out if out is not None else torch.empty_like(field)
     par = None
     if parents:
+        if parents_out is not None:
+            _check_buf(parents_out, "parents_out", torch.uint8, field.numel(), field.device)
         par = parents_out if parents_out is not None else torch.empty(field.shape, dtype=torch.uint8,
                                                                        device=field.device)
     if work_ref is not None:
         _check_field(work_ref)
         if work_ref.shape != field.shape:
             raise ValueError("work_ref must have the field's shape")
-    o = make_opts(delta, tile, grid_blocks, max_tile_visits, time_kernels, lookahead, wave_tiles, timeline, op,
-                  horizon, work_ref, track_change)
+    o = make_opts(delta, tile, grid_blocks, max_tile_visits, time_kernels, lookahead, timeline, op,
+                  horizon, work_ref, track_change, warm_start)
     rc = L.eik_solve(ctypes.byref(g), field.data_ptr(), src.numel(), src.data_ptr(),
                      t0d.data_ptr() if t0d is not None else None, t.data_ptr(),
                      par.data_ptr() if par is not None else None, ctypes.byref(o),
@@ -216,6 +240,15 @@ def adjoint(field: torch.Tensor, h: float, t: torch.Tensor, parents: torch.Tenso
         raise ValueError("parents must be a uint8 tensor of the field's shape")
     if t.shape != field.shape or dL_dt.shape != field.shape:
         raise ValueError("t and dL_dt must have the field's shape")
+    if out is not None:
+        _check_buf(out, "out", torch.float64, field.numel(), field.device)
+    if mu_out is not None:
+        _check_buf(mu_out, "mu_out", torch.float64, field.numel(), field.device)
+    for a in (t, parents, dL_dt):
+        if a.device != field.device:
+            raise ValueError("t, parents and dL_dt must be on the field's device")
+    if not parents.is_contiguous():
+        raise ValueError("parents must be contiguous")
     L = _lib.load()
     g = _grid_of(field.shape, h, kind)
     grad = out if out is not None else torch.empty_like(field)
@@ -322,11 +355,14 @@ def pack(fields: Sequence[torch.Tensor], hs: Union[float, Sequence[float]], sour
 
 def solve_packed(b: Batch, t_packed: torch.Tensor, par_packed: Optional[torch.Tensor] = None,
                  delta: float = 0.0, tile=None, grid_blocks: int = 0, stream=None,
-                 time_kernels: bool = False, lookahead: int = 0, wave_tiles: bool = False,
-                 horizon: int = 0) -> None:
+                 time_kernels: bool = False, lookahead: int = 0, horizon: int = 0) -> None:
     """Enqueue one batched forward launch (no host synchronisation)."""
+    dev = b.field.device
+    _check_buf(t_packed, "t_packed", torch.float64, b.npts, dev)
+    if par_packed is not None:
+        _check_buf(par_packed, "par_packed", torch.uint8, b.npts, dev)
     L = _lib.load()
-    o = make_opts(delta, tile, grid_blocks, 0, time_kernels, lookahead, wave_tiles, horizon=horizon)
+    o = make_opts(delta, tile, grid_blocks, 0, time_kernels, lookahead, horizon=horizon)
     check(L.eik_solve_batched(b.nprob, b.grids, b.offsets, b.field.data_ptr(), b.src_off,
                               b.src.data_ptr(), b.t0.data_ptr() if b.t0 is not None else None,
                               t_packed.data_ptr(), par_packed.data_ptr() if par_packed is not None else None,
@@ -337,6 +373,14 @@ def adjoint_packed(b: Batch, t_packed: torch.Tensor, par_packed: torch.Tensor, g
                    grad_packed: torch.Tensor, mu_packed: Optional[torch.Tensor] = None, delta: float = 0.0,
                    tile=None, grid_blocks: int = 0, stream=None, time_kernels: bool = False,
                    lookahead: int = 0) -> None:
+    """Enqueue one batched adjoint launch (no host synchronisation)."""
+    dev = b.field.device
+    _check_buf(t_packed, "t_packed", torch.float64, b.npts, dev)
+    _check_buf(par_packed, "par_packed", torch.uint8, b.npts, dev)
+    _check_buf(g_packed, "g_packed", torch.float64, b.npts, dev)
+    _check_buf(grad_packed, "grad_packed", torch.float64, b.npts, dev)
+    if mu_packed is not None:
+        _check_buf(mu_packed, "mu_packed", torch.float64, b.npts, dev)
     L = _lib.load()
     o = make_opts(delta, tile, grid_blocks, 0, time_kernels, lookahead)
     check(L.eik_adjoint_batched(b.nprob, b.grids, b.offsets, b.field.data_ptr(), t_packed.data_ptr(),

@@ -13,7 +13,6 @@
 
 #include "eik.h"
 #include "eik_adjoint.hpp"
-#include "eik_wave.hpp"
 
 using namespace eik;
 
@@ -43,6 +42,16 @@ constexpr int kScalWords = 192;
 constexpr int kTimelineCap = 1 << 16;
 constexpr int kSCur = 0, kSPending = 64, kSFlags = 128, kSPoisoned = 129, kSSrcCount = 130;
 
+// One uploaded batch layout: the problem table (tile shape and offsets
+// included) and the source offsets, as on the host and on the device.
+struct Table {
+    std::vector<Prob> probs;
+    std::vector<int64_t> src_off;   // empty for a table uploaded by the adjoint
+    Prob* d_probs = nullptr;
+    int64_t* d_src_off = nullptr;
+};
+constexpr size_t kMaxTables = 64;
+
 struct Workspace {
     int device = -1;
     hipStream_t stream = nullptr;
@@ -62,12 +71,9 @@ struct Workspace {
     unsigned long long* counters = nullptr;
     int32_t* srclist = nullptr;
     int64_t srclist_cap = 0;
-    // problem table and source offsets
-    Prob* probs = nullptr;
-    int64_t* src_off = nullptr;
-    int64_t probs_cap = 0;
-    std::vector<Prob> probs_host;      // what is on the device now
-    std::vector<int64_t> src_off_host;
+    // device problem tables of batched calls (problem list + source offsets),
+    // one per distinct layout, kept until eik_release
+    std::vector<Table> tables;
     // adjoint scratch
     double* mu = nullptr;
     int64_t mu_cap = 0;
@@ -185,41 +191,52 @@ int ensure_tiles(Workspace& w, int64_t ntiles) {
     return EIK_OK;
 }
 
-// Makes the device problem table (and, when `src_off` is given, the source
-// offsets) match; a no-op when they already do, so repeated calls with the same
-// problems enqueue nothing but kernels (HIP graph capture relies on this).
-int upload_table(Workspace& w, const std::vector<Prob>& probs, const std::vector<int64_t>* src_off) {
-    int64_t n = (int64_t)probs.size();
-    bool same = (int64_t)w.probs_host.size() == n &&
-                std::memcmp(w.probs_host.data(), probs.data(), sizeof(Prob) * (size_t)n) == 0 &&
-                (src_off == nullptr || w.src_off_host == *src_off);
-    if (same && w.probs) return EIK_OK;
+bool same_probs(const std::vector<Prob>& a, const std::vector<Prob>& b) {
+    return a.size() == b.size() && std::memcmp(a.data(), b.data(), sizeof(Prob) * a.size()) == 0;
+}
+
+// Finds or uploads the device table of a batch layout.  Each distinct layout
+// (problems with their tile geometry, and the source offsets when `src_off` is
+// given) is uploaded once and kept, so the forward and the adjoint of a batch
+// may use different tile shapes and repeated calls enqueue nothing but
+// kernels: HIP graph capture of a call relies on this after one warm-up call
+// with each layout.  The adjoint (src_off == NULL) reuses any table with the
+// same problems.  Uploading synchronises the stream; past kMaxTables layouts
+// the oldest is freed (after a synchronisation) to make room.
+int upload_table(Workspace& w, const std::vector<Prob>& probs, const std::vector<int64_t>* src_off,
+                 const Table** out) {
+    for (const Table& tb : w.tables) {
+        if (!same_probs(tb.probs, probs)) continue;
+        if (src_off && tb.src_off != *src_off) continue;
+        *out = &tb;
+        return EIK_OK;
+    }
+    HIP_TRY(hipStreamSynchronize(w.stream));
+    if (w.tables.size() >= kMaxTables) {
+        HIP_TRY(hipFree(w.tables.front().d_probs));
+        HIP_TRY(hipFree(w.tables.front().d_src_off));
+        w.tables.erase(w.tables.begin());
+    }
+    Table tb;
+    tb.probs = probs;
+    if (src_off) tb.src_off = *src_off;
     std::vector<int64_t> so = src_off ? *src_off : std::vector<int64_t>(probs.size() + 1, 0);
-    if (w.probs_cap < n + 1) {
-        if (w.probs) {
-            HIP_TRY(hipStreamSynchronize(w.stream));
-            HIP_TRY(hipFree(w.probs));
-            HIP_TRY(hipFree(w.src_off));
-            w.probs = nullptr;
-            w.src_off = nullptr;
-        }
-        int64_t cap = n + 16;
-        hipError_t e = hipMalloc((void**)&w.probs, sizeof(Prob) * (size_t)cap);
-        if (e == hipSuccess) e = hipMalloc((void**)&w.src_off, sizeof(int64_t) * (size_t)(cap + 1));
-        if (e != hipSuccess) return fail(EIK_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
-        w.probs_cap = cap;
+    hipError_t e = hipMalloc((void**)&tb.d_probs, sizeof(Prob) * probs.size());
+    if (e == hipSuccess) e = hipMalloc((void**)&tb.d_src_off, sizeof(int64_t) * so.size());
+    if (e != hipSuccess) {
+        (void)hipFree(tb.d_probs);
+        return fail(EIK_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
     }
     // synchronous copies: the host vectors may be gone before the stream runs
-    HIP_TRY(hipStreamSynchronize(w.stream));
-    HIP_TRY(hipMemcpy(w.probs, probs.data(), sizeof(Prob) * (size_t)n, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(w.src_off, so.data(), sizeof(int64_t) * so.size(), hipMemcpyHostToDevice));
-    w.probs_host = probs;
-    w.src_off_host = so;
+    HIP_TRY(hipMemcpy(tb.d_probs, probs.data(), sizeof(Prob) * probs.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(tb.d_src_off, so.data(), sizeof(int64_t) * so.size(), hipMemcpyHostToDevice));
+    w.tables.push_back(std::move(tb));
+    *out = &w.tables.back();
     return EIK_OK;
 }
 
 // Kernel-side problem table: a single problem travels by value (nothing to
-// upload, no synchronisation); a batch uses the device copy.
+// upload, no synchronisation); a batch uses its device copy.
 int make_table(Workspace& w, const std::vector<Prob>& probs, const std::vector<int64_t>* src_off,
                ProbTable* T) {
     T->probs = nullptr;
@@ -228,10 +245,11 @@ int make_table(Workspace& w, const std::vector<Prob>& probs, const std::vector<i
     T->p0 = probs[0];
     T->nsrc0 = src_off ? (*src_off)[1] - (*src_off)[0] : 0;
     if (probs.size() == 1) return EIK_OK;
-    int rc = upload_table(w, probs, src_off);
+    const Table* tb = nullptr;
+    int rc = upload_table(w, probs, src_off, &tb);
     if (rc) return rc;
-    T->probs = w.probs;
-    T->src_off = w.src_off;
+    T->probs = tb->d_probs;
+    T->src_off = tb->d_src_off;
     return EIK_OK;
 }
 
@@ -245,30 +263,18 @@ struct TileShape {
 
 #define EIK_TILES_3D(X) X(32, 8, 4) X(16, 8, 8) X(8, 8, 8) X(64, 4, 4) X(16, 8, 4) X(8, 8, 4) X(8, 4, 4)
 #define EIK_TILES_2D(X) X(32, 32, 1) X(64, 16, 1) X(128, 8, 1) X(16, 16, 1) X(16, 8, 1)
-// one tile per wave (EIK_FLAG_WAVE_TILES)
-#define EIK_WTILES_3D(X) X(8, 8, 4) X(16, 8, 4) X(8, 8, 8) X(16, 4, 4)
-#define EIK_WTILES_2D(X) X(16, 16, 1) X(32, 16, 1) X(32, 8, 1)
-constexpr int kWavesPerBlock = 4;
 
-bool tile_supported(int ndim, int x, int y, int z, bool wave) {
+bool tile_supported(int ndim, int x, int y, int z) {
 #define EIK_MATCH(a, b, c) \
     if (x == a && y == b && z == c) return (ndim == 3) == (c > 1);
-    if (wave) {
-        EIK_WTILES_3D(EIK_MATCH)
-        EIK_WTILES_2D(EIK_MATCH)
-    } else {
-        EIK_TILES_3D(EIK_MATCH)
-        EIK_TILES_2D(EIK_MATCH)
-    }
+    EIK_TILES_3D(EIK_MATCH)
+    EIK_TILES_2D(EIK_MATCH)
 #undef EIK_MATCH
     return false;
 }
 
-bool wave_mode(const eik_opts* o) { return o && (o->flags & EIK_FLAG_WAVE_TILES); }
-
 TileShape pick_tile(int ndim, const eik_opts* o) {
     if (o && (o->tile[0] || o->tile[1] || o->tile[2])) return {o->tile[0], o->tile[1], o->tile[2]};
-    if (wave_mode(o)) return ndim == 3 ? TileShape{8, 8, 4} : TileShape{16, 16, 1};
     if (ndim == 3) return {16, 8, 8};
     return {32, 32, 1};
 }
@@ -288,19 +294,23 @@ int check_grid(const eik_grid* g) {
 int check_opts(const eik_opts* o) {
     if (!o) return EIK_OK;
     if (!(o->delta >= 0.0) || std::isnan(o->delta)) return fail(EIK_EINVAL, "delta must be >= 0");
+    // bucket keys are floor(t / delta) through 1 / delta: a width whose
+    // reciprocal overflows (subnormal) would put every value beyond any bucket
+    if (o->delta > 0.0 && !std::isfinite(1.0 / o->delta))
+        return fail(EIK_EINVAL, "delta too small (its reciprocal overflows)");
     if (o->grid_blocks < 0) return fail(EIK_EINVAL, "grid_blocks must be >= 0");
     if (o->max_tile_visits < 0) return fail(EIK_EINVAL, "max_tile_visits must be >= 0");
-    if (o->flags & ~(EIK_FLAG_TIME_KERNELS | EIK_FLAG_WAVE_TILES | EIK_FLAG_TIMELINE | EIK_FLAG_TRACK_CHANGE))
+    if (o->flags & ~(EIK_FLAG_TIME_KERNELS | EIK_FLAG_TIMELINE | EIK_FLAG_TRACK_CHANGE | EIK_FLAG_WARM_START))
         return fail(EIK_EINVAL, "unknown flags");
     if (o->lookahead < 0 || o->lookahead > 8) return fail(EIK_EINVAL, "lookahead must be in 0..8");
     if (o->op < EIK_OP_DBAR || o->op > EIK_OP_NEWTON) return fail(EIK_EINVAL, "unknown operator");
     if ((o->flags & EIK_FLAG_TRACK_CHANGE) && o->op == EIK_OP_DBAR)
         return fail(EIK_EINVAL, "change tracking applies to the ablation operators only");
     if (o->horizon < 0 || o->horizon > 4) return fail(EIK_EINVAL, "horizon must be in 0..4");
-    if (o->work_ref && (wave_mode(o) || o->op != EIK_OP_DBAR))
-        return fail(EIK_ENOTSUP, "work classification runs with block tiles and d-bar only");
-    if (o->op != EIK_OP_DBAR && wave_mode(o))
-        return fail(EIK_ENOTSUP, "the ablation operators run with block tiles only");
+    if (o->work_ref && o->op != EIK_OP_DBAR)
+        return fail(EIK_ENOTSUP, "work classification runs with d-bar only");
+    if ((o->flags & EIK_FLAG_WARM_START) && o->op != EIK_OP_DBAR)
+        return fail(EIK_ENOTSUP, "a warm start needs the monotone operator (d-bar)");
     return EIK_OK;
 }
 
@@ -374,12 +384,13 @@ int blocks_for(int64_t n, int threads, int cap = 65536) {
 }
 
 // The full forward sequence for one tile shape.
-template <int TX, int TY, int TZ, bool WAVE, int OP = 0>
+template <int TX, int TY, int TZ, int OP = 0>
 int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int64_t>& src_off,
             int64_t ntiles, int64_t npts_total, const double* field, const int64_t* src_idx,
             const double* src_t0, double* t, uint8_t* par, const eik_opts* o) {
     int rc;
     const int64_t nsrc = src_off.back();
+    const bool warm = o && (o->flags & EIK_FLAG_WARM_START);
     if ((rc = ensure_tiles(w, ntiles))) return rc;
     if ((rc = grow(&w.srclist, &w.srclist_cap, nsrc, w.stream))) return rc;
     ProbTable T;
@@ -395,10 +406,17 @@ int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int6
                        (long long)kRings * w.ring_cap);
     hipLaunchKernelGGL((k_src_mark<TX, TY, TZ>), dim3(blocks_for(nsrc, kThreads)), dim3(kThreads), 0, st,
                        T, src_idx, src_t0, (long long)nsrc, s, w.srclist, srccnt);
-    hipLaunchKernelGGL(k_fill_inf, dim3(blocks_for(npts_total, kThreads, 8192)), dim3(kThreads), 0, st,
-                       (long long)npts_total, t);
+    if (warm)
+        hipLaunchKernelGGL((k_warm_prep<TX, TY, TZ>), dim3((unsigned)std::min<int64_t>(ntiles, 65536)),
+                           dim3(kThreads), 0, st, T, (int)ntiles, t, w.tile_tmax, s);
+    else
+        hipLaunchKernelGGL(k_fill_inf, dim3(blocks_for(npts_total, kThreads, 8192)), dim3(kThreads), 0, st,
+                           (long long)npts_total, t);
     hipLaunchKernelGGL((k_src_place<TX, TY, TZ>), dim3(blocks_for(nsrc, kThreads)), dim3(kThreads), 0, st,
                        T, src_idx, src_t0, (long long)nsrc, t, s);
+    if (warm)
+        hipLaunchKernelGGL(k_warm_push, dim3(blocks_for(ntiles, kThreads, 4096)), dim3(kThreads), 0, st, T,
+                           (int)ntiles, (const uint64_t*)w.tile_tmax, s);
     HIP_TRY(hipGetLastError());
 
     SolveArgs a;
@@ -409,37 +427,26 @@ int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int6
     a.work_ref = o ? o->work_ref : nullptr;
     a.s = s;
     int grid = 0;
-    if constexpr (WAVE) {
-        constexpr int nt = 64 * kWavesPerBlock;
-        if ((rc = occupancy_grid(k_solve_w<TX, TY, TZ, kWavesPerBlock>, nt, &grid))) return rc;
-        if (o && o->grid_blocks > 0) grid = std::min(grid, o->grid_blocks);
-        const int64_t need = (ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
-        if ((int64_t)grid > need) grid = (int)need;
-        if (grid < 1) grid = 1;
-        if ((rc = timing_begin(w, o))) return rc;
-        hipLaunchKernelGGL((k_solve_w<TX, TY, TZ, kWavesPerBlock>), dim3(grid), dim3(nt), 0, st, a);
-    } else {
-        constexpr int nt = tile_threads<TX, TY, TZ>();
-        const bool count = a.work_ref != nullptr;
-        if constexpr (OP == EIK_OP_DBAR) {
-            if (count) {
-                if ((rc = occupancy_grid(k_solve<TX, TY, TZ, nt, OP, true>, nt, &grid))) return rc;
-            } else {
-                if ((rc = occupancy_grid(k_solve<TX, TY, TZ, nt, OP>, nt, &grid))) return rc;
-            }
+    constexpr int nt = tile_threads<TX, TY, TZ>();
+    const bool count = a.work_ref != nullptr;
+    if constexpr (OP == EIK_OP_DBAR) {
+        if (count) {
+            if ((rc = occupancy_grid(k_solve<TX, TY, TZ, nt, OP, true>, nt, &grid))) return rc;
         } else {
             if ((rc = occupancy_grid(k_solve<TX, TY, TZ, nt, OP>, nt, &grid))) return rc;
         }
-        if (o && o->grid_blocks > 0) grid = std::min(grid, o->grid_blocks);
-        if ((int64_t)grid > ntiles) grid = (int)ntiles;
-        if (grid < 1) grid = 1;
-        if ((rc = timing_begin(w, o))) return rc;
-        if constexpr (OP == EIK_OP_DBAR) {
-            if (count) hipLaunchKernelGGL((k_solve<TX, TY, TZ, nt, OP, true>), dim3(grid), dim3(nt), 0, st, a);
-            else hipLaunchKernelGGL((k_solve<TX, TY, TZ, nt, OP>), dim3(grid), dim3(nt), 0, st, a);
-        } else {
-            hipLaunchKernelGGL((k_solve<TX, TY, TZ, nt, OP>), dim3(grid), dim3(nt), 0, st, a);
-        }
+    } else {
+        if ((rc = occupancy_grid(k_solve<TX, TY, TZ, nt, OP>, nt, &grid))) return rc;
+    }
+    if (o && o->grid_blocks > 0) grid = std::min(grid, o->grid_blocks);
+    if ((int64_t)grid > ntiles) grid = (int)ntiles;
+    if (grid < 1) grid = 1;
+    if ((rc = timing_begin(w, o))) return rc;
+    if constexpr (OP == EIK_OP_DBAR) {
+        if (count) hipLaunchKernelGGL((k_solve<TX, TY, TZ, nt, OP, true>), dim3(grid), dim3(nt), 0, st, a);
+        else hipLaunchKernelGGL((k_solve<TX, TY, TZ, nt, OP>), dim3(grid), dim3(nt), 0, st, a);
+    } else {
+        hipLaunchKernelGGL((k_solve<TX, TY, TZ, nt, OP>), dim3(grid), dim3(nt), 0, st, a);
     }
     HIP_TRY(hipGetLastError());
     if ((rc = timing_end(w, o))) return rc;
@@ -461,19 +468,16 @@ int dispatch_forward(TileShape ts, Workspace& w, const std::vector<Prob>& probs,
                      uint8_t* par, const eik_opts* o) {
 #define EIK_CASE(a, b, c)                                                                      \
     if (ts.x == a && ts.y == b && ts.z == c)                                                   \
-        return forward<a, b, c, false>(w, probs, src_off, ntiles, npts, field, src_idx, src_t0, t, par, o);
-#define EIK_WCASE(a, b, c)                                                                     \
-    if (ts.x == a && ts.y == b && ts.z == c)                                                   \
-        return forward<a, b, c, true>(w, probs, src_off, ntiles, npts, field, src_idx, src_t0, t, par, o);
+        return forward<a, b, c>(w, probs, src_off, ntiles, npts, field, src_idx, src_t0, t, par, o);
 #define EIK_HCASE(a, b, c)                                                                     \
     if (ts.x == a && ts.y == b && ts.z == c)                                                   \
-        return forward<a, b, c, false, 1>(w, probs, src_off, ntiles, npts, field, src_idx, src_t0, t, par, o);
+        return forward<a, b, c, 1>(w, probs, src_off, ntiles, npts, field, src_idx, src_t0, t, par, o);
 #define EIK_TCASE(a, b, c)                                                                     \
     if (ts.x == a && ts.y == b && ts.z == c)                                                   \
-        return forward<a, b, c, false, 2>(w, probs, src_off, ntiles, npts, field, src_idx, src_t0, t, par, o);
+        return forward<a, b, c, 2>(w, probs, src_off, ntiles, npts, field, src_idx, src_t0, t, par, o);
 #define EIK_NCASE(a, b, c)                                                                     \
     if (ts.x == a && ts.y == b && ts.z == c)                                                   \
-        return forward<a, b, c, false, 3>(w, probs, src_off, ntiles, npts, field, src_idx, src_t0, t, par, o);
+        return forward<a, b, c, 3>(w, probs, src_off, ntiles, npts, field, src_idx, src_t0, t, par, o);
     const int op = o ? o->op : EIK_OP_DBAR;
     if (op == EIK_OP_DHAT) {
         EIK_TILES_2D(EIK_HCASE)
@@ -481,15 +485,11 @@ int dispatch_forward(TileShape ts, Workspace& w, const std::vector<Prob>& probs,
         EIK_TILES_2D(EIK_TCASE)
     } else if (op == EIK_OP_NEWTON) {
         EIK_TILES_2D(EIK_NCASE)
-    } else if (wave_mode(o)) {
-        EIK_WTILES_3D(EIK_WCASE)
-        EIK_WTILES_2D(EIK_WCASE)
     } else {
         EIK_TILES_3D(EIK_CASE)
         EIK_TILES_2D(EIK_CASE)
     }
 #undef EIK_CASE
-#undef EIK_WCASE
 #undef EIK_HCASE
 #undef EIK_TCASE
 #undef EIK_NCASE
@@ -609,7 +609,7 @@ const char* eik_last_error(void) { return g_last_error.c_str(); }
 int64_t eik_num_tiles(const eik_grid* g, const eik_opts* o) {
     if (check_grid(g)) return -1;
     TileShape ts = pick_tile(g->ndim, o);
-    if (!tile_supported(g->ndim, ts.x, ts.y, ts.z, wave_mode(o))) return -1;
+    if (!tile_supported(g->ndim, ts.x, ts.y, ts.z)) return -1;
     return tiles_of(make_prob(*g, ts, 0, 0));
 }
 
@@ -628,7 +628,7 @@ int eik_solve_batched(int32_t nprob, const eik_grid* grids_host, const int64_t* 
         if (soff[i + 1] - soff[i] < 1) return fail(EIK_EINVAL, "every problem needs at least one source");
     if (soff[nprob] > ((int64_t)1 << 31)) return fail(EIK_ENOTSUP, "too many sources");
     TileShape ts = pick_tile(grids_host[0].ndim, opts);
-    if (!tile_supported(grids_host[0].ndim, ts.x, ts.y, ts.z, wave_mode(opts)))
+    if (!tile_supported(grids_host[0].ndim, ts.x, ts.y, ts.z))
         return fail(EIK_ENOTSUP, "unsupported tile shape for this ndim");
     if (opts && opts->op != EIK_OP_DBAR && grids_host[0].ndim != 2)
         return fail(EIK_ENOTSUP, "the ablation operators are two-dimensional");
@@ -729,9 +729,8 @@ int eik_adjoint_batched(int32_t nprob, const eik_grid* grids_host, const int64_t
     if (offsets_host[0] != 0) return fail(EIK_EINVAL, "offsets must start at 0");
     int rc = check_opts(opts);
     if (rc) return rc;
-    if (wave_mode(opts)) return fail(EIK_ENOTSUP, "the adjoint runs one tile per block (no EIK_FLAG_WAVE_TILES)");
     TileShape ts = pick_tile(grids_host[0].ndim, opts);
-    if (!tile_supported(grids_host[0].ndim, ts.x, ts.y, ts.z, false))
+    if (!tile_supported(grids_host[0].ndim, ts.x, ts.y, ts.z))
         return fail(EIK_ENOTSUP, "unsupported tile shape for this ndim");
     std::vector<Prob> probs;
     int64_t ntiles = 0, npts = 0;
@@ -774,6 +773,7 @@ int eik_status(void* stream, eik_stats* out) {
     int code = EIK_OK;
     if (flags & kFlagWatchdog) code = EIK_EHANG;
     else if (flags & kFlagBadSrc) code = EIK_EBADSRC;
+    else if (flags & kFlagBadStart) code = EIK_EINVAL;
     else if (flags & kFlagDomain) code = EIK_EDOMAIN;
     else if (flags & kFlagLimit) code = EIK_ELIMIT;
     if (out) {
@@ -804,7 +804,8 @@ int eik_status(void* stream, eik_stats* out) {
         }
     }
     w->ev_used = 0;
-    if (code != EIK_OK) g_last_error = eik_strerror(code);
+    if (code != EIK_OK)
+        g_last_error = code == EIK_EINVAL ? "warm-start times must be >= +0 and not NaN" : eik_strerror(code);
     return code;
 }
 
@@ -846,8 +847,10 @@ void eik_release(void) {
         (void)hipFree(w->scal);
         (void)hipFree(w->counters);
         (void)hipFree(w->srclist);
-        (void)hipFree(w->probs);
-        (void)hipFree(w->src_off);
+        for (Table& tb : w->tables) {
+            (void)hipFree(tb.d_probs);
+            (void)hipFree(tb.d_src_off);
+        }
         (void)hipFree(w->mu);
         (void)hipFree(w->tile_tmax);
         for (hipEvent_t e : w->ev) (void)hipEventDestroy(e);

@@ -199,6 +199,71 @@ __global__ void k_src_unsign(ProbTable T, const int64_t* src_idx, const double* 
 }
 
 // ---------------------------------------------------------------------------
+// warm start: resume from an upper bound of the solution
+// ---------------------------------------------------------------------------
+
+// Checks a caller-supplied starting state and records each tile's smallest
+// value (bits of a non-negative double; kInfBits when the tile is all +inf).
+// A value that is NaN or has its sign bit set (the solver's source marker) is
+// not a valid upper bound: it raises kFlagBadStart and is replaced by +inf, so
+// the solve still runs on a valid state.
+template <int TX, int TY, int TZ>
+__global__ void k_warm_prep(ProbTable T, int ntiles, double* t, uint64_t* tile_min, Sched s) {
+    __shared__ unsigned long long s_m;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const Prob P = prob_of_tile(T, tile);
+        const int tl = tile - P.tile_off;
+        const int tx = tl % P.ntx, ty = (tl / P.ntx) % P.nty, tz = tl / (P.ntx * P.nty);
+        if (threadIdx.x == 0) s_m = kInfBits;
+        __syncthreads();
+        unsigned long long m = kInfBits;
+        for (int i = threadIdx.x; i < TX * TY * TZ; i += blockDim.x) {
+            const int lx = i % TX, ly = (i / TX) % TY, lz = i / (TX * TY);
+            const int x = tx * TX + lx, y = ty * TY + ly, z = tz * TZ + lz;
+            if (x < P.nx && y < P.ny && z < P.nz) {
+                double* p = t + P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x;
+                const double v = *p;
+                if (v != v || signbit(v)) {
+                    set_flag(s, kFlagBadStart);
+                    *p = inf64();
+                } else if (as_u64(v) < m) {
+                    m = as_u64(v);
+                }
+            }
+        }
+        if (m != kInfBits) atomicMin(&s_m, m);
+        __syncthreads();
+        if (threadIdx.x == 0) tile_min[tile] = s_m;
+        __syncthreads();
+    }
+}
+
+// Queues every tile that has a finite value in itself or in a face neighbour
+// (any other tile can only change once a neighbour lowers its face, which
+// activates it), keyed by the smallest of those values.  Tiles already queued
+// (the source tiles) are left alone.  Their state words were cleared by the
+// reset, so every first run relaxes all of its points.
+__global__ void k_warm_push(ProbTable T, int ntiles, const uint64_t* tile_min, Sched s) {
+    for (int tile = blockIdx.x * blockDim.x + threadIdx.x; tile < ntiles; tile += gridDim.x * blockDim.x) {
+        const Prob P = prob_of_tile(T, tile);
+        const int tl = tile - P.tile_off;
+        const int t3[3] = {tl % P.ntx, (tl / P.ntx) % P.nty, tl / (P.ntx * P.nty)};
+        const int lim[3] = {P.ntx, P.nty, P.ntz};
+        uint64_t key = tile_min[tile];
+        for (int f = 0; f < 6; ++f) {
+            int nt[3] = {t3[0], t3[1], t3[2]};
+            nt[f >> 1] += (f & 1) ? 1 : -1;
+            if (nt[f >> 1] < 0 || nt[f >> 1] >= lim[f >> 1]) continue;
+            const uint64_t k = tile_min[P.tile_off + (nt[2] * P.nty + nt[1]) * P.ntx + nt[0]];
+            if (k < key) key = k;
+        }
+        if (key == kInfBits) continue;
+        const uint32_t old = __hip_atomic_fetch_or(s.tstate + tile, kQ, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!(old & kQ)) activate_push(s, (uint32_t)tile, as_f64(key), 0);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // the persistent solver
 // ---------------------------------------------------------------------------
 
@@ -379,7 +444,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
         // is lost; larger candidates are left for a later run of this tile,
         // keyed by the smallest of them, instead of being written and
         // propagated now as provisional values.
-        const double hz = S.horizon > 0 ? (double)(s_bucket + S.horizon) : inf64();
+        const double hz = (double)(s_bucket + S.horizon);
 
         // ---- stage the tile and its halo in LDS ----------------------------
         // t starts at +inf everywhere, so every in-grid value read here is a
@@ -569,7 +634,11 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
                 double r;
                 if constexpr (OP == 0) {
                     r = update<C::D3>(ax, ay, az, q, q * q, tc, ch);
-                    if (ch && !(r * S.inv_delta < hz)) {
+                    // held back: its bucket lies at or beyond the horizon (a
+                    // value whose bucket index overflows the range is settled
+                    // at once, so the requeue can never repeat forever)
+                    const double rb = r * S.inv_delta;
+                    if (S.horizon > 0 && ch && rb >= hz && rb < 1.0e15) {
                         pend = fmin(pend, r);
                         ch = false;
                     }

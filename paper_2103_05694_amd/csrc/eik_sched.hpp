@@ -83,7 +83,7 @@ constexpr uint64_t kCountBias = 1ull << 31; // count is stored biased, so it may
 constexpr uint64_t kRunOne = 1ull << 32;
 
 // device status flags
-constexpr uint32_t kFlagDomain = 1u, kFlagLimit = 2u, kFlagBadSrc = 4u, kFlagWatchdog = 8u;
+constexpr uint32_t kFlagDomain = 1u, kFlagLimit = 2u, kFlagBadSrc = 4u, kFlagWatchdog = 8u, kFlagBadStart = 16u;
 
 struct Sched {
     uint64_t* items;     // [nrings][cap]
@@ -234,10 +234,20 @@ __device__ __forceinline__ void idle_sleep(int units) {
 // Called by all 64 lanes of one wave.  Returns a tile and the bucket it came
 // from (*bucket), counted as running there, or -1 when no work is left anywhere
 // (pending == 0), or -2 on a watchdog expiry.
+//
+// The watchdog counts consecutive polls that saw no progress anywhere: the
+// window's first count word (it changes with every claim, push and end of a
+// run in the current bucket), the current bucket and the live-work count are
+// compared with the previous poll's, and any change restarts the count.  So it
+// fires only when nothing has moved for 2^19 polls (about 14 s with the
+// back-off below), however long a valid solve takes.
 __device__ __forceinline__ int claim(const Sched& s, int64_t* bucket) {
     const int lane = threadIdx.x & 63;
     const int win = s.lookahead + 1;
-    long long idle = 0;
+    long long idle = 0;   // polls so far (sets the back-off)
+    long long stall = 0;  // polls since anything last moved (the watchdog)
+    unsigned long long seen_w = ~0ull;
+    long long seen_cp = -1;
     for (;;) {
         const int32_t c = ld_rlx(s.cur);
         const int r = (int)(((int64_t)c + lane) % s.nrings);
@@ -257,11 +267,17 @@ __device__ __forceinline__ int claim(const Sched& s, int64_t* bucket) {
             if (got == -2) return -2;
             continue;
         }
-        if (__shfl(w, 0) == kCountBias) {
-            // bucket `cur` drained: find the next non-empty bucket (full scan)
+        const unsigned long long w0 = __shfl(w, 0);
+        int32_t pend_now = -1;
+        if (w0 == kCountBias) {
+            // bucket `cur` drained: move to the next bucket that has work
+            // queued or still running (full scan).  A bucket whose runs (taken
+            // through the lookahead window) are still live is not skipped:
+            // their pushes may land in it, and its ring must not be reused
+            // for a later bucket meanwhile.
             unsigned long long wf = kCountBias;
             if (lane < s.nrings) wf = ld_cr(s, r);
-            const unsigned long long m2 = __ballot(cr_count(wf) > 0) & ~1ull;
+            const unsigned long long m2 = __ballot(wf != kCountBias) & ~1ull;
             if (m2) {
                 const int j = __ffsll((long long)m2) - 1;
                 if (lane == 0) {
@@ -280,10 +296,17 @@ __device__ __forceinline__ int claim(const Sched& s, int64_t* bucket) {
                 }
                 continue;
             }
-            if (ld_rlx(s.pending) <= 0) return -1;
+            pend_now = ld_rlx(s.pending);
+            if (pend_now <= 0) return -1;
+        }
+        const long long cp = ((long long)c << 32) ^ (long long)(uint32_t)pend_now;
+        if (w0 != seen_w || cp != seen_cp) {
+            stall = 0;  // something moved since the last poll
+            seen_w = w0;
+            seen_cp = cp;
         }
         ++idle;
-        if (idle > (1ll << 19)) {
+        if (++stall > (1ll << 19)) {
             if (lane == 0) set_flag(s, kFlagWatchdog);
             return -2;
         }

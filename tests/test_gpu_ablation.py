@@ -134,12 +134,10 @@ def test_work_classification(gpu, O, delta, horizon):
     assert torch.equal(ref, fo)
 
 
-def test_work_classification_needs_block_tiles_and_dbar(gpu):
+def test_work_classification_needs_dbar(gpu):
     f = torch.ones(64, 64, dtype=torch.float64, device="cuda")
     ref = gpu.solve(f, 1.0, torch.tensor([0]))
     with pytest.raises(gpu.EikError):
         gpu.solve(f, 1.0, torch.tensor([0]), op="dhat", work_ref=ref)
-    with pytest.raises(gpu.EikError):
-        gpu.solve(f, 1.0, torch.tensor([0]), wave_tiles=True, work_ref=ref)
     with pytest.raises(gpu.EikError):
         gpu.solve(f, 1.0, torch.tensor([0]), track_change=True)   # d-bar needs no tracking

@@ -165,3 +165,57 @@ def test_adjoint_degenerate_gradients(gpu, O):
             grad = gpu.adjoint(to_gpu(f), 1.0, to_gpu(t), to_gpu(par), to_gpu(g), tile=tile)
             got = grad.cpu().numpy().reshape(f.shape)
             assert np.array_equal(got, ref), (name, tile)
+
+
+def test_graph_capture_with_different_forward_and_adjoint_tiles(gpu, O):
+    """A batch whose forward and adjoint run with different tile shapes (two
+    device problem tables): warm-up uploads both, the captured graph replays
+    without any upload, and every replay equals the per-shot plain launches
+    bit for bit."""
+    from paper_2103_05694_amd.batch import ShotBatch
+    shots = uneven_shots(5, 3)
+    fields = [to_gpu(1.0 / f) for f, _ in shots]
+    srcs = [torch.as_tensor(s) for _, s in shots]
+    recs = [torch.arange(0, f.size, 7, device="cuda") for f, _ in shots]
+    sb = ShotBatch(fields, 1.0, srcs, recs, kind="slowness", delta=0.3, tile=(16, 8, 8),
+                   adj_delta=0.6, adj_tile=(8, 8, 8))
+    sb.capture()
+    t_plain = torch.empty_like(sb.t)
+    g_plain = torch.empty_like(sb.grad)
+    sb.plain_step(t_plain, g_plain)
+    torch.cuda.synchronize()
+    gpu.status()
+    for rep in range(3):
+        sb.replay()
+        sb.sync()
+        gpu.status(sb.stream)
+        assert torch.equal(sb.t, t_plain), f"replay {rep} times"
+        assert torch.equal(sb.grad, g_plain), f"replay {rep} gradient"
+        torch.cuda.synchronize()
+    for i, (f, s) in enumerate(shots):
+        ref = O.fmm(1.0 / f, 1.0, s, kind=O.SLOWNESS)
+        assert np.array_equal(sb.shot_views(sb.t)[i].cpu().numpy(), ref)
+
+
+def test_bad_buffers_raise_before_launch(gpu):
+    f = torch.ones(8, 9, 10, dtype=torch.float64, device="cuda")
+    src = torch.tensor([0])
+    with pytest.raises(TypeError):
+        gpu.solve(f, 1.0, src, out=torch.empty(8, 9, 10, dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        gpu.solve(f, 1.0, src, out=torch.empty(719, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        gpu.solve(f, 1.0, src, out=torch.empty(720, dtype=torch.float64))
+    with pytest.raises(TypeError):
+        gpu.solve(f, 1.0, src, parents=True, parents_out=torch.empty(720, dtype=torch.int32, device="cuda"))
+    t, par = gpu.solve(f, 1.0, src, parents=True)
+    g = torch.zeros_like(f)
+    with pytest.raises(ValueError):
+        gpu.adjoint(f, 1.0, t, par, g, mu_out=torch.empty(10, dtype=torch.float64, device="cuda"))
+    b = gpu.pack([f, f], 1.0, [src, src])
+    with pytest.raises(ValueError):
+        gpu.solve_packed(b, torch.empty(b.npts - 1, dtype=torch.float64, device="cuda"))
+    tt = torch.empty(b.npts, dtype=torch.float64, device="cuda")
+    pp = torch.empty(b.npts, dtype=torch.uint8, device="cuda")
+    with pytest.raises(TypeError):
+        gpu.adjoint_packed(b, tt, pp, torch.zeros(b.npts, dtype=torch.float32, device="cuda"), tt.clone())

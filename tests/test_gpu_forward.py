@@ -94,36 +94,6 @@ def test_ragged_and_degenerate_shapes(gpu, O, case):
             assert_bitwise(t, ref, f"{name} tile {tile} delta {delta} lookahead {la} horizon {hz}")
 
 
-WTILES_3D = [(8, 8, 4), (16, 8, 4), (8, 8, 8), (16, 4, 4)]
-WTILES_2D = [(16, 16), (32, 16), (32, 8)]
-
-
-@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
-def test_wave_tiles_ragged(gpu, O, case):
-    name, f, h, src, t0 = case
-    ref = O.fmm(f, h, src, t0)
-    tiles = WTILES_2D if f.shape[0] == 1 else WTILES_3D
-    for tile in tiles:
-        for delta, la in ((0.0, 0), (0.5, 0), (0.25, 2)):
-            t = gpu_solve(gpu, f, h, src, t0, tile=tile, delta=delta, lookahead=la, wave_tiles=True)
-            assert_bitwise(t, ref, f"{name} wave tile {tile} delta {delta} lookahead {la}")
-
-
-def test_wave_tiles_scaled_workloads(gpu, O, layered_small):
-    p = layered_small
-    ref = O.fmm(p.field, p.h, p.src)
-    for tile in WTILES_3D:
-        for delta, la in ((0.0, 0), (0.02, 0), (0.01, 2)):
-            t = gpu_solve(gpu, p.field, p.h, p.src, tile=tile, delta=delta, lookahead=la, wave_tiles=True)
-            assert_bitwise(t, ref, f"layered wave tile {tile} delta {delta}")
-    q = W.blocky_2d(n=512, nsrc=16, seed=3, block=16)
-    ref = O.fmm(q.field, q.h, q.src)
-    for tile in WTILES_2D:
-        for delta, la in ((0.0, 0), (4.0, 0), (2.0, 4)):
-            t = gpu_solve(gpu, q.field, q.h, q.src, tile=tile, delta=delta, lookahead=la, wave_tiles=True)
-            assert_bitwise(t, ref, f"blocky wave tile {tile} delta {delta}")
-
-
 def test_slowness_field(gpu, O):
     rng = np.random.default_rng(5)
     s = 1.0 / W.random_field((8, 20, 24), rng, 0.5, 5.0)
@@ -224,6 +194,35 @@ def test_parents_match_oracle(gpu, O):
         assert np.array_equal(par.cpu().numpy().reshape(shape), ref_p)
         par2 = gpu.parents_of(t, torch.tensor(src))
         assert np.array_equal(par2.cpu().numpy().reshape(shape), ref_p)
+
+
+def test_parents_on_exact_ties(gpu, O):
+    """Parents where the two neighbours on an axis are equal bit for bit: two
+    sources mirrored about a column of a unit medium (2D), and a point source
+    in the middle of a constant 3D medium, whose solution has exact mirror
+    symmetry on every axis.  The GPU record (in-kernel and eik_parents) equals
+    the oracle's, tie rule included."""
+    cases = []
+    ny, nx = 31, 41
+    cases.append((np.ones((1, ny, nx)), np.array([15 * nx + 10, 15 * nx + 30])))
+    cases.append((np.ones((1, 101, 101)), np.array([50 * 101 + 50])))
+    n = 17
+    cases.append((np.full((n, n, n), 2.0), np.array([W.flat_index(8, 8, 8, n, n)])))
+    for f, src in cases:
+        shape = f.shape
+        ref_t = O.fmm(f, 1.0, src)
+        ref_p = O.parents(ref_t, src)
+        assert np.array_equal(ref_t, ref_t[..., ::-1])
+        ft = torch.from_numpy(f).cuda()
+        if shape[0] == 1:
+            ft = ft[0]
+        tiles = [(32, 32), (16, 8)] if shape[0] == 1 else [(8, 8, 8), (16, 8, 4)]
+        for tile in tiles:
+            t, par = gpu.solve(ft, 1.0, torch.tensor(src), parents=True, tile=tile, delta=1.0)
+            assert_bitwise(t.cpu().numpy().reshape(shape), ref_t, f"t {shape} {tile}")
+            assert np.array_equal(par.cpu().numpy().reshape(shape), ref_p), f"parents {shape} {tile}"
+            par2 = gpu.parents_of(t, torch.tensor(src))
+            assert np.array_equal(par2.cpu().numpy().reshape(shape), ref_p), f"eik_parents {shape} {tile}"
 
 
 def test_domain_error_reported(gpu):
@@ -379,3 +378,89 @@ def test_plane_of_sources_with_mixed_t0(gpu, O):
         for delta in (0.0, 0.5, 20.0):
             t = gpu_solve(gpu, f, 1.0, src, t0, tile=tile, delta=delta)
             assert_bitwise(t, ref, f"tile {tile} delta {delta}")
+
+
+def test_warm_start_resumes_to_the_same_bits(gpu, O, layered_small):
+    """EIK_FLAG_WARM_START (checkpoint / resume, Theorem 1's argument): a solve
+    stopped by the visit cap leaves an upper bound; resuming from it, or from
+    any other upper bound, gives the cold solve's bits."""
+    p = layered_small
+    ref = O.fmm(p.field, p.h, p.src)
+    f = torch.from_numpy(p.field).cuda()
+    src = torch.as_tensor(p.src)
+    for tile, delta in (((8, 8, 8), 0.02), ((16, 8, 8), 0.0), ((8, 4, 4), 0.005)):
+        for cap in (3, 60, 400):
+            t = gpu.solve(f, p.h, src, tile=tile, delta=delta, max_tile_visits=cap, check_status=False)
+            assert gpu.status(raise_on_error=False).status == -5
+            part = t.cpu().numpy()
+            assert np.all(part >= ref) and np.isinf(part).any()
+            # stop once more, then finish
+            gpu.solve(f, p.h, src, tile=tile, delta=delta, max_tile_visits=cap, out=t, warm_start=True,
+                      check_status=False)
+            gpu.status(raise_on_error=False)
+            gpu.solve(f, p.h, src, tile=tile, delta=delta, out=t, warm_start=True)
+            assert_bitwise(t.cpu().numpy(), ref, f"resume tile {tile} delta {delta} cap {cap}")
+    # from the oracle's own partial solve, from a raised exact solution, from +inf
+    rng = np.random.default_rng(17)
+    part, done = O.fmm_resume(p.field, p.h, p.src, np.full(p.field.shape, np.inf), max_pops=p.npts // 4)
+    assert not done
+    up = ref * (1.0 + rng.uniform(0.0, 0.3, ref.shape) * (rng.random(ref.shape) < 0.2))
+    up[rng.random(ref.shape) < 0.05] = np.inf
+    for name, start in (("oracle partial", part), ("raised", up), ("inf", np.full(ref.shape, np.inf))):
+        t = torch.from_numpy(np.ascontiguousarray(start)).cuda()
+        gpu.solve(f, p.h, src, tile=(8, 8, 8), delta=0.02, out=t, warm_start=True)
+        assert_bitwise(t.cpu().numpy(), ref, f"warm start from {name}")
+
+
+def test_warm_start_sources_and_batches(gpu, O):
+    """Resume with several sources and start times (the sources are fixed
+    again whatever the start state holds there), in 2D and in a batch."""
+    name, f, h, src, t0 = CASES[0]
+    ref = O.fmm(f, h, src, t0)
+    start = ref + 1.0
+    start.reshape(-1)[src] = 7.0
+    ft = torch.from_numpy(f).cuda()
+    out = torch.from_numpy(start).cuda()
+    gpu.solve(ft, h, torch.as_tensor(src), t0=torch.as_tensor(t0), tile=(8, 8, 8), delta=0.5, out=out,
+              warm_start=True)
+    assert_bitwise(out.cpu().numpy(), ref, name)
+    q = W.blocky_2d(n=256, nsrc=5, seed=9, block=16)
+    refq = O.fmm(q.field, q.h, q.src)
+    fq = torch.from_numpy(q.field[0]).cuda()
+    tq = gpu.solve(fq, q.h, torch.as_tensor(q.src), tile=(32, 32), delta=4.0, max_tile_visits=20,
+                   check_status=False)
+    gpu.status(raise_on_error=False)
+    gpu.solve(fq, q.h, torch.as_tensor(q.src), tile=(16, 16), delta=1.0, out=tq, warm_start=True)
+    assert_bitwise(tq.cpu().numpy()[None], refq, "2D blocky resume")
+    rng = np.random.default_rng(4)
+    fields = [W.random_field(s, rng, 0.5, 4.0, block=2) for s in ((9, 20, 17), (12, 8, 30), (5, 5, 5))]
+    srcs = [np.array([3]), np.array([100, 2000]), np.array([62])]
+    b = gpu.pack([torch.from_numpy(x).cuda() for x in fields], 1.0, [torch.as_tensor(s) for s in srcs])
+    tb = torch.empty(b.npts, dtype=torch.float64, device="cuda")
+    gpu.solve_packed(b, tb, tile=(8, 8, 8), delta=0.5)
+    gpu.status()
+    tb.mul_(1.5)   # an upper bound of every problem's solution
+    from paper_2103_05694_amd import _lib
+    import ctypes
+    o = gpu.make_opts(0.5, (8, 8, 8), warm_start=True)
+    _lib.check(_lib.load().eik_solve_batched(b.nprob, b.grids, b.offsets, b.field.data_ptr(), b.src_off,
+                                             b.src.data_ptr(), None, tb.data_ptr(), None, ctypes.byref(o),
+                                             ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    gpu.status()
+    for x, s, v in zip(fields, srcs, b.views(tb)):
+        assert_bitwise(v.cpu().numpy(), O.fmm(x, 1.0, s), "batched resume")
+
+
+def test_warm_start_rejects_invalid_start(gpu, O):
+    f = torch.ones(20, 30, dtype=torch.float64, device="cuda")
+    ref = O.fmm(np.ones((1, 20, 30)), 1.0, np.array([7]))[0]
+    for bad in (float("nan"), -1.0, -0.0):
+        t = torch.full_like(f, float("inf"))
+        t[5, 5] = bad
+        gpu.solve(f, 1.0, torch.tensor([7]), out=t, warm_start=True, check_status=False)
+        st = gpu.status(raise_on_error=False)
+        assert st.status == -1
+        # the bad value was replaced by +inf, so the solve itself completed
+        assert_bitwise(t.cpu().numpy(), ref, f"start value {bad}")
+    with pytest.raises(ValueError):
+        gpu.solve(f, 1.0, torch.tensor([7]), warm_start=True)

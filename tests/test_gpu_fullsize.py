@@ -8,11 +8,12 @@ sampled shots the oracle computes one by one.
   d loss / d slowness within 1e-12 relative of the oracle's adjoint fed with
   the oracle's own times and observations.
 * Uneven batch: 64 shots of 128^3 .. 256x256x128 (343M points) in one
-  persistent forward launch and one adjoint launch; two sampled shots checked
-  the same way, and a property of every shot (zero residual).
+  persistent forward launch and one adjoint launch; one sampled shot of each
+  size (two of 128^3) checked the same way, and every ninth shot through the
+  oracle's residual on a host copy (zero, hence the unique fixed point).
 * The paper's grid shape, 2D 11204 x 54404 (609M points, folded layers): a
   scaled-down version of the same recipe bitwise against the oracle, and the
-  full size through its residual (zero, hence the unique fixed point).
+  full size through the oracle's residual on a host copy of the GPU result.
 """
 import numpy as np
 import pytest
@@ -20,7 +21,7 @@ import torch
 
 import workloads as W
 
-pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+pytestmark = [pytest.mark.gpu, pytest.mark.slow, pytest.mark.timeout(600)]
 
 
 @pytest.fixture(scope="module")
@@ -105,7 +106,11 @@ def test_uneven_full_batch(gpu, O):
     gpu.status()
     rng = np.random.default_rng(12)
     small = [i for i, p in enumerate(shots) if p.npts == 128 ** 3][:2]
-    assert len(small) == 2
+    # one shot of each larger size too: they sit deep in the flattened tile
+    # space, where the tile-to-problem search of the batched launch matters
+    small += [max(i for i, p in enumerate(shots) if p.shape == shp)
+              for shp in ((128, 192, 192), (128, 256, 256))]
+    assert len(small) == 4
     g = torch.zeros_like(t)
     gv = b.views(g)
     gs = {}
@@ -129,10 +134,12 @@ def test_uneven_full_batch(gpu, O):
         got = grv[i].cpu().numpy()
         if not np.array_equal(got, ref):
             assert rel_err(got, ref) <= 1e-12, f"shot {i} gradient"
-    # every shot: the GPU result is a fixed point of the operator (hence the
-    # unique one), checked on the GPU against each shot's own field
+    # every ninth shot: the GPU result is a fixed point of the operator (hence
+    # the unique one), checked by the oracle on a host copy
     for i in range(0, 64, 9):
-        assert gpu.residual(fields[i], 10.0, srcs[i], tv[i], kind="slowness") == (0, 0.0), f"shot {i}"
+        p = shots[i]
+        res = O.residual(tv[i].cpu().numpy(), 1.0 / p.field, p.h, p.src, kind=O.SLOWNESS)
+        assert res == (0, 0.0), f"shot {i}"
 
 
 def test_paper_scale_2d(gpu, O):
@@ -149,5 +156,9 @@ def test_paper_scale_2d(gpu, O):
     f = torch.from_numpy(p.field[0]).cuda()
     t = gpu.solve(f, p.h, torch.as_tensor(p.src), tile=tuple(cfg["tile"]), delta=cfg["delta"],
                   grid_blocks=int(cfg.get("grid_blocks", 0)), horizon=int(cfg.get("horizon", 0)))
-    assert gpu.residual(f, p.h, torch.as_tensor(p.src), t) == (0, 0.0)
-    assert float(t.max()) < np.inf
+    del f
+    th = t.cpu().numpy()
+    del t
+    assert np.all(np.isfinite(th))
+    # the oracle re-applies the operator at all 609M points of the GPU result
+    assert O.residual(th[None], p.field, p.h, p.src) == (0, 0.0)

@@ -190,3 +190,41 @@ def test_explicit_formula_is_schedule_dependent(O):
     exact = O.fmm(f, 1.0, src)
     for seed in range(8):
         assert np.array_equal(O.async_random(f, 1.0, src, seed), exact)
+
+
+def test_resume_from_any_upper_bound_reaches_the_fixed_point(O):
+    """Checkpoint / resume (Theorem 1's argument: from any state above the
+    fixed point, a maximal sequence of monotone, causal updates ends at it).
+    A solve stopped after k pops, resumed (possibly stopped again), equals the
+    cold solve bit for bit; so does a resume from the exact solution raised at
+    random points, from +inf everywhere, and from a state with holes of +inf."""
+    rng = np.random.default_rng(31)
+    for _, f, h, src, t0 in CASES:
+        ref = O.fmm(f, h, src, t0)
+        inf = np.full(f.shape, np.inf)
+        t, done = O.fmm_resume(f, h, src, inf, t0)
+        assert done and np.array_equal(t, ref)
+        for k in (1, 7, f.size // 3):
+            part, done = O.fmm_resume(f, h, src, inf, t0, max_pops=k)
+            assert not done
+            mask = np.ones(f.shape, bool)
+            mask.reshape(-1)[np.asarray(src)] = False
+            assert np.all(part >= ref) and np.isinf(part[mask]).any()
+            part2, _ = O.fmm_resume(f, h, src, part, t0, max_pops=k)
+            t, done = O.fmm_resume(f, h, src, part2, t0)
+            assert done and np.array_equal(t, ref), k
+        up = ref * (1.0 + rng.uniform(0.0, 0.5, f.shape) * (rng.random(f.shape) < 0.3))
+        up[rng.random(f.shape) < 0.1] = np.inf
+        t, done = O.fmm_resume(f, h, src, up, t0)
+        assert done and np.array_equal(t, ref)
+
+
+def test_resume_rejects_invalid_start(O):
+    p = W.point_source_2d(n=9, src=(4, 4))
+    bad = np.full(p.field.shape, np.inf)
+    bad[0, 0, 0] = np.nan
+    with pytest.raises(O.OracleError):
+        O.fmm_resume(p.field, p.h, p.src, bad)
+    bad[0, 0, 0] = -1.0
+    with pytest.raises(O.OracleError):
+        O.fmm_resume(p.field, p.h, p.src, bad)
