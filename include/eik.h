@@ -175,6 +175,26 @@ int eik_solve(const eik_grid* g, const double* field, int64_t nsrc, const int64_
               const double* src_t0, double* t_out, uint8_t* parents_out,
               const eik_opts* opts, void* stream);
 
+/* Allocation-free forward solve.  For callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, results (bit for bit), options and errors
+ * as eik_solve, for one problem; but every work buffer (bucket rings, tile
+ * states, counters, status words) lives in a static array of the library, one
+ * copy per GPU it runs on (about 17.6 MiB, held until the process ends), so
+ * the call allocates nothing and uses no per-stream workspace.  Its device
+ * address is looked up once per device, on the first call there.
+ * Limits, checked before anything is enqueued (EIK_ENOTSUP): at most 65536
+ * tiles (see eik_num_tiles) and 65536 sources; EIK_FLAG_TIME_KERNELS and
+ * EIK_FLAG_TIMELINE are not available.
+ * Every call on a GPU shares that GPU's array, which keeps the last call's
+ * contents: each call clears what it needs, but calls whose work may overlap
+ * on one GPU (different streams, or different host threads on one stream
+ * without ordering) race and give wrong results; serialise them.  The device
+ * status of the call is read with eik_status(stream), as for eik_solve. */
+int eik_solve_noalloc(const eik_grid* g, const double* field, int64_t nsrc, const int64_t* src_idx,
+                      const double* src_t0, double* t_out, uint8_t* parents_out,
+                      const eik_opts* opts, void* stream);
+
 /* Upwind-parent record (same encoding as parents_out above) from final times t
  * of a finished solve.  src_idx as for eik_solve. */
 int eik_parents(const eik_grid* g, const double* t, int64_t nsrc, const int64_t* src_idx,

@@ -35,7 +35,7 @@ EIK_FLAG_WARM_START = 16
 EXPORTED = (
     "eik_solve", "eik_parents", "eik_adjoint", "eik_solve_batched", "eik_adjoint_batched",
     "eik_reserve", "eik_num_tiles", "eik_status", "eik_strerror", "eik_last_error",
-    "eik_release", "eik_version", "eik_timeline", "eik_residual",
+    "eik_release", "eik_version", "eik_timeline", "eik_residual", "eik_solve_noalloc",
 )
 
 
@@ -88,6 +88,8 @@ def load() -> ctypes.CDLL:
     L = ctypes.CDLL(LIB_PATH)
     L.eik_solve.restype = _i32
     L.eik_solve.argtypes = [_gp, _vp, _i64, _vp, _vp, _vp, _vp, _op, _vp]
+    L.eik_solve_noalloc.restype = _i32
+    L.eik_solve_noalloc.argtypes = [_gp, _vp, _i64, _vp, _vp, _vp, _vp, _op, _vp]
     L.eik_parents.restype = _i32
     L.eik_parents.argtypes = [_gp, _vp, _i64, _vp, _vp, _vp]
     L.eik_adjoint.restype = _i32

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -80,6 +81,7 @@ struct Workspace {
     uint64_t* tile_tmax = nullptr;     // per-tile largest time (adjoint priorities)
     int last_kind = 0;                 // 0 none, 1 forward, 2 adjoint
     int64_t last_ntiles = 0;
+    uint64_t last_seq = 0;             // order of the last call among all calls (status lookup)
     std::vector<hipEvent_t> ev;        // event pairs bracketing timed persistent kernels
     size_t ev_used = 0;                // pairs recorded since the last eik_status
 };
@@ -107,6 +109,8 @@ int timing_end(Workspace& w, const eik_opts* o) {
 
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
+std::atomic<uint64_t> g_seq{0};
+uint64_t next_seq() { return ++g_seq; }
 
 template <class T>
 int grow(T** p, int64_t* cap, int64_t need, hipStream_t st) {
@@ -331,7 +335,40 @@ Prob make_prob(const eik_grid& g, TileShape ts, int64_t pt_off, int64_t tile_off
 
 int64_t tiles_of(const Prob& p) { return (int64_t)p.ntx * p.nty * p.ntz; }
 
-Sched make_sched(Workspace& w, const eik_opts* o) {
+// The device buffers one forward or adjoint launch sequence works in: the
+// stream's workspace, or (eik_solve_noalloc) the library's static scratch.
+struct Bufs {
+    hipStream_t stream = nullptr;
+    uint64_t* items = nullptr;
+    uint32_t* ctr = nullptr;
+    uint32_t* tstate = nullptr;
+    uint64_t* tkey = nullptr;
+    uint64_t* tile_aux = nullptr;   // per-tile min (warm start) or max (adjoint) time
+    int32_t* scal = nullptr;
+    unsigned long long* counters = nullptr;
+    int32_t* srclist = nullptr;
+    unsigned long long* timeline = nullptr;
+    uint32_t ring_cap = 0;
+    int force_wipe = 0;             // re-initialise the rings in this call's reset
+};
+
+Bufs bufs_of(Workspace& w) {
+    Bufs b;
+    b.stream = w.stream;
+    b.items = w.items;
+    b.ctr = w.ctr;
+    b.tstate = w.tstate;
+    b.tkey = w.tkey;
+    b.tile_aux = w.tile_tmax;
+    b.scal = w.scal;
+    b.counters = w.counters;
+    b.srclist = w.srclist;
+    b.timeline = w.timeline;
+    b.ring_cap = w.ring_cap;
+    return b;
+}
+
+Sched make_sched(const Bufs& w, const eik_opts* o) {
     Sched s;
     s.items = w.items;
     s.ctr = w.ctr;
@@ -349,25 +386,33 @@ Sched make_sched(Workspace& w, const eik_opts* o) {
     s.lookahead = o ? o->lookahead : 0;
     s.horizon = o ? o->horizon : 0;
     s.track = (o && (o->flags & EIK_FLAG_TRACK_CHANGE)) ? 1 : 0;
-    const bool tl = o && (o->flags & EIK_FLAG_TIMELINE);
+    const bool tl = o && (o->flags & EIK_FLAG_TIMELINE) && w.timeline;
     s.timeline = tl ? w.timeline : nullptr;
     s.timeline_cap = tl ? kTimelineCap : 0;
     return s;
 }
 
+// Persistent workgroups that fit on the device at once.  With `cached`, the
+// per-kernel occupancy is remembered (a host map); the allocation-free entry
+// point asks the runtime every time instead.
 template <class K>
-int occupancy_grid(K kernel, int threads, int* out) {
+int occupancy_grid(K kernel, int threads, int* out, bool cached = true) {
     static std::map<const void*, int> cache;
     static std::mutex m;
-    std::lock_guard<std::mutex> lk(m);
-    auto it = cache.find((const void*)kernel);
-    int per_cu;
-    if (it != cache.end()) {
-        per_cu = it->second;
+    int per_cu = 0;
+    if (cached) {
+        std::lock_guard<std::mutex> lk(m);
+        auto it = cache.find((const void*)kernel);
+        if (it != cache.end()) {
+            per_cu = it->second;
+        } else {
+            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0));
+            if (per_cu < 1) per_cu = 1;
+            cache[(const void*)kernel] = per_cu;
+        }
     } else {
         HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0));
         if (per_cu < 1) per_cu = 1;
-        cache[(const void*)kernel] = per_cu;
     }
     int dev = 0, cus = 0;
     HIP_TRY(hipGetDevice(&dev));
@@ -383,32 +428,29 @@ int blocks_for(int64_t n, int threads, int cap = 65536) {
     return (int)b;
 }
 
-// The full forward sequence for one tile shape.
+// The forward launch sequence for one tile shape, on buffers that already
+// exist (no allocation, no host synchronisation).  `tw` receives the timing
+// events (NULL: no timing); `cached` as for occupancy_grid.
 template <int TX, int TY, int TZ, int OP = 0>
-int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int64_t>& src_off,
-            int64_t ntiles, int64_t npts_total, const double* field, const int64_t* src_idx,
-            const double* src_t0, double* t, uint8_t* par, const eik_opts* o) {
+int forward_seq(const Bufs& b, const ProbTable& T, int64_t nsrc, int64_t ntiles, int64_t npts_total,
+                const double* field, const int64_t* src_idx, const double* src_t0, double* t, uint8_t* par,
+                const eik_opts* o, Workspace* tw, bool cached) {
     int rc;
-    const int64_t nsrc = src_off.back();
     const bool warm = o && (o->flags & EIK_FLAG_WARM_START);
-    if ((rc = ensure_tiles(w, ntiles))) return rc;
-    if ((rc = grow(&w.srclist, &w.srclist_cap, nsrc, w.stream))) return rc;
-    ProbTable T;
-    if ((rc = make_table(w, probs, &src_off, &T))) return rc;
-    hipStream_t st = w.stream;
-    Sched s = make_sched(w, o);
+    hipStream_t st = b.stream;
+    Sched s = make_sched(b, o);
     // the ablation operators need not settle: cap the runs unless the caller did
     if (OP != EIK_OP_DBAR && s.max_visits == 0) s.max_visits = 256 * (long long)ntiles;
-    int32_t* srccnt = w.scal + kSSrcCount;
+    int32_t* srccnt = b.scal + kSSrcCount;
 
-    hipLaunchKernelGGL(k_reset, dim3(blocks_for(std::max<int64_t>(ntiles, (int64_t)kRings * w.ring_cap), kThreads, 4096)),
-                       dim3(kThreads), 0, st, s, w.tkey, (int)ntiles, srccnt,
-                       (long long)kRings * w.ring_cap);
+    hipLaunchKernelGGL(k_reset, dim3(blocks_for(std::max<int64_t>(ntiles, (int64_t)kRings * b.ring_cap), kThreads, 4096)),
+                       dim3(kThreads), 0, st, s, b.tkey, (int)ntiles, srccnt,
+                       (long long)kRings * b.ring_cap, b.force_wipe);
     hipLaunchKernelGGL((k_src_mark<TX, TY, TZ>), dim3(blocks_for(nsrc, kThreads)), dim3(kThreads), 0, st,
-                       T, src_idx, src_t0, (long long)nsrc, s, w.srclist, srccnt);
+                       T, src_idx, src_t0, (long long)nsrc, s, b.srclist, srccnt);
     if (warm)
         hipLaunchKernelGGL((k_warm_prep<TX, TY, TZ>), dim3((unsigned)std::min<int64_t>(ntiles, 65536)),
-                           dim3(kThreads), 0, st, T, (int)ntiles, t, w.tile_tmax, s);
+                           dim3(kThreads), 0, st, T, (int)ntiles, t, b.tile_aux, s);
     else
         hipLaunchKernelGGL(k_fill_inf, dim3(blocks_for(npts_total, kThreads, 8192)), dim3(kThreads), 0, st,
                            (long long)npts_total, t);
@@ -416,14 +458,14 @@ int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int6
                        T, src_idx, src_t0, (long long)nsrc, t, s);
     if (warm)
         hipLaunchKernelGGL(k_warm_push, dim3(blocks_for(ntiles, kThreads, 4096)), dim3(kThreads), 0, st, T,
-                           (int)ntiles, (const uint64_t*)w.tile_tmax, s);
+                           (int)ntiles, (const uint64_t*)b.tile_aux, s);
     HIP_TRY(hipGetLastError());
 
     SolveArgs a;
     a.pt = T;
     a.field = field;
     a.t = t;
-    a.tkey = w.tkey;
+    a.tkey = b.tkey;
     a.work_ref = o ? o->work_ref : nullptr;
     a.s = s;
     int grid = 0;
@@ -431,17 +473,17 @@ int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int6
     const bool count = a.work_ref != nullptr;
     if constexpr (OP == EIK_OP_DBAR) {
         if (count) {
-            if ((rc = occupancy_grid(k_solve<TX, TY, TZ, nt, OP, true>, nt, &grid))) return rc;
+            if ((rc = occupancy_grid(k_solve<TX, TY, TZ, nt, OP, true>, nt, &grid, cached))) return rc;
         } else {
-            if ((rc = occupancy_grid(k_solve<TX, TY, TZ, nt, OP>, nt, &grid))) return rc;
+            if ((rc = occupancy_grid(k_solve<TX, TY, TZ, nt, OP>, nt, &grid, cached))) return rc;
         }
     } else {
-        if ((rc = occupancy_grid(k_solve<TX, TY, TZ, nt, OP>, nt, &grid))) return rc;
+        if ((rc = occupancy_grid(k_solve<TX, TY, TZ, nt, OP>, nt, &grid, cached))) return rc;
     }
     if (o && o->grid_blocks > 0) grid = std::min(grid, o->grid_blocks);
     if ((int64_t)grid > ntiles) grid = (int)ntiles;
     if (grid < 1) grid = 1;
-    if ((rc = timing_begin(w, o))) return rc;
+    if (tw && (rc = timing_begin(*tw, o))) return rc;
     if constexpr (OP == EIK_OP_DBAR) {
         if (count) hipLaunchKernelGGL((k_solve<TX, TY, TZ, nt, OP, true>), dim3(grid), dim3(nt), 0, st, a);
         else hipLaunchKernelGGL((k_solve<TX, TY, TZ, nt, OP>), dim3(grid), dim3(nt), 0, st, a);
@@ -449,7 +491,7 @@ int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int6
         hipLaunchKernelGGL((k_solve<TX, TY, TZ, nt, OP>), dim3(grid), dim3(nt), 0, st, a);
     }
     HIP_TRY(hipGetLastError());
-    if ((rc = timing_end(w, o))) return rc;
+    if (tw && (rc = timing_end(*tw, o))) return rc;
 
     if (par)
         hipLaunchKernelGGL(k_parents, dim3(blocks_for(npts_total, kThreads, 1 << 16)), dim3(kThreads), 0,
@@ -457,8 +499,26 @@ int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int6
     hipLaunchKernelGGL(k_src_unsign, dim3(blocks_for(nsrc, kThreads)), dim3(kThreads), 0, st, T, src_idx,
                        src_t0, (long long)nsrc, t);
     HIP_TRY(hipGetLastError());
+    return EIK_OK;
+}
+
+// The full forward sequence on the stream's workspace (grown as needed).
+template <int TX, int TY, int TZ, int OP = 0>
+int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int64_t>& src_off,
+            int64_t ntiles, int64_t npts_total, const double* field, const int64_t* src_idx,
+            const double* src_t0, double* t, uint8_t* par, const eik_opts* o) {
+    int rc;
+    const int64_t nsrc = src_off.back();
+    if ((rc = ensure_tiles(w, ntiles))) return rc;
+    if ((rc = grow(&w.srclist, &w.srclist_cap, nsrc, w.stream))) return rc;
+    ProbTable T;
+    if ((rc = make_table(w, probs, &src_off, &T))) return rc;
+    if ((rc = forward_seq<TX, TY, TZ, OP>(bufs_of(w), T, nsrc, ntiles, npts_total, field, src_idx, src_t0, t,
+                                          par, o, &w, true)))
+        return rc;
     w.last_kind = 1;
     w.last_ntiles = ntiles;
+    w.last_seq = next_seq();
     return EIK_OK;
 }
 
@@ -509,12 +569,12 @@ int adjoint(Workspace& w, const std::vector<Prob>& probs, int64_t ntiles, int64_
     ProbTable T;
     if ((rc = make_table(w, probs, nullptr, &T))) return rc;
     hipStream_t st = w.stream;
-    Sched s = make_sched(w, o);
+    Sched s = make_sched(bufs_of(w), o);
     s.max_visits = 0;
     unsigned long long* tref = w.counters + 4;
     hipLaunchKernelGGL(k_reset, dim3(blocks_for(std::max<int64_t>(ntiles, (int64_t)kRings * w.ring_cap), kThreads, 4096)),
                        dim3(kThreads), 0, st, s, w.tkey, (int)ntiles, w.scal + kSSrcCount,
-                       (long long)kRings * w.ring_cap);
+                       (long long)kRings * w.ring_cap, 0);
     // mu := NaN (not done): a tile that has not run yet reads as not done
     hipLaunchKernelGGL(k_fill_nan, dim3(blocks_for(npts, kThreads, 8192)), dim3(kThreads), 0, st, (long long)npts, mu);
     hipLaunchKernelGGL((k_adj_prep<TX, TY, TZ>), dim3((unsigned)std::min<int64_t>(ntiles, 65536)), dim3(kThreads),
@@ -545,6 +605,7 @@ int adjoint(Workspace& w, const std::vector<Prob>& probs, int64_t ntiles, int64_
     if ((rc = timing_end(w, o))) return rc;
     w.last_kind = 2;
     w.last_ntiles = ntiles;
+    w.last_seq = next_seq();
     return EIK_OK;
 }
 
@@ -577,6 +638,116 @@ int build_problems(int32_t nprob, const eik_grid* grids, const int64_t* offsets,
     *ntiles = tile_off;
     *npts = offsets[nprob];
     return EIK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free forward solve (eik_solve_noalloc)
+// ---------------------------------------------------------------------------
+
+// Layout of the static scratch array, in bytes (each part 256-byte aligned):
+// the 32 bucket rings at full capacity for kNaMaxTiles tiles, their counters,
+// tile states, requeue keys, per-tile minima (warm start), the scalars, the
+// statistics words and the source-tile list.
+constexpr int64_t kNaMaxTiles = 1 << 16;
+constexpr int64_t kNaMaxSrc = 1 << 16;
+constexpr size_t na_round(size_t x) { return (x + 255) / 256 * 256; }
+constexpr size_t kNaItems = 0;
+constexpr size_t kNaCtr = kNaItems + na_round(sizeof(uint64_t) * kRings * kNaMaxTiles);
+constexpr size_t kNaTstate = kNaCtr + na_round(sizeof(uint32_t) * kRings * kCtrStride);
+constexpr size_t kNaTkey = kNaTstate + na_round(sizeof(uint32_t) * kNaMaxTiles);
+constexpr size_t kNaTmin = kNaTkey + na_round(sizeof(uint64_t) * kNaMaxTiles);
+constexpr size_t kNaScal = kNaTmin + na_round(sizeof(uint64_t) * kNaMaxTiles);
+constexpr size_t kNaCounters = kNaScal + na_round(sizeof(int32_t) * kScalWords);
+constexpr size_t kNaSrclist = kNaCounters + na_round(sizeof(unsigned long long) * kCounters);
+constexpr size_t kNaBytes = kNaSrclist + na_round(sizeof(int32_t) * kNaMaxSrc);
+
+}  // namespace
+
+// The allocation-free entry point's workspace: one copy per GPU the library
+// runs on, held until the process ends (about 17.6 MiB).  Host code never
+// uses this name as an address: it asks the runtime for each device's copy
+// (hipGetSymbolAddress) and passes that pointer to the kernels.
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace {
+
+constexpr int kNaMaxDevices = 64;
+struct NaDevice {
+    unsigned char* ptr = nullptr;   // this device's `scratch`
+    bool wiped = false;             // its rings have been initialised once
+    hipStream_t last_stream = nullptr;
+    uint64_t last_seq = 0;          // order of its last call among all calls
+    int64_t last_ntiles = 0;
+};
+NaDevice g_na[kNaMaxDevices];
+std::mutex g_na_mu;
+
+// The device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+int na_device(int* dev_out, NaDevice** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNaMaxDevices) return fail(EIK_ENOTSUP, "device index beyond 63");
+    NaDevice& d = g_na[dev];
+    if (!d.ptr) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(EIK_EHIP, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+        d.ptr = (unsigned char*)p;
+    }
+    *dev_out = dev;
+    *out = &d;
+    return EIK_OK;
+}
+
+Bufs na_bufs(const NaDevice& d, hipStream_t st) {
+    Bufs b;
+    b.stream = st;
+    b.items = (uint64_t*)(d.ptr + kNaItems);
+    b.ctr = (uint32_t*)(d.ptr + kNaCtr);
+    b.tstate = (uint32_t*)(d.ptr + kNaTstate);
+    b.tkey = (uint64_t*)(d.ptr + kNaTkey);
+    b.tile_aux = (uint64_t*)(d.ptr + kNaTmin);
+    b.scal = (int32_t*)(d.ptr + kNaScal);
+    b.counters = (unsigned long long*)(d.ptr + kNaCounters);
+    b.srclist = (int32_t*)(d.ptr + kNaSrclist);
+    b.timeline = nullptr;
+    b.ring_cap = (uint32_t)kNaMaxTiles;
+    // the first call on a device initialises the rings (their memory has
+    // never been written by this library); later calls find them drained
+    b.force_wipe = d.wiped ? 0 : 1;
+    return b;
+}
+
+int na_dispatch(TileShape ts, const Bufs& b, const ProbTable& T, int64_t nsrc, int64_t ntiles, int64_t npts,
+                const double* field, const int64_t* src_idx, const double* src_t0, double* t, uint8_t* par,
+                const eik_opts* o) {
+#define EIK_NA(a, b_, c, OPV)                                                                             \
+    if (ts.x == a && ts.y == b_ && ts.z == c)                                                             \
+        return forward_seq<a, b_, c, OPV>(b, T, nsrc, ntiles, npts, field, src_idx, src_t0, t, par, o, nullptr, \
+                                          false);
+#define EIK_NA0(a, b_, c) EIK_NA(a, b_, c, 0)
+#define EIK_NA1(a, b_, c) EIK_NA(a, b_, c, 1)
+#define EIK_NA2(a, b_, c) EIK_NA(a, b_, c, 2)
+#define EIK_NA3(a, b_, c) EIK_NA(a, b_, c, 3)
+    const int op = o ? o->op : EIK_OP_DBAR;
+    if (op == EIK_OP_DHAT) {
+        EIK_TILES_2D(EIK_NA1)
+    } else if (op == EIK_OP_DTILDE) {
+        EIK_TILES_2D(EIK_NA2)
+    } else if (op == EIK_OP_NEWTON) {
+        EIK_TILES_2D(EIK_NA3)
+    } else {
+        EIK_TILES_3D(EIK_NA0)
+        EIK_TILES_2D(EIK_NA0)
+    }
+#undef EIK_NA
+#undef EIK_NA0
+#undef EIK_NA1
+#undef EIK_NA2
+#undef EIK_NA3
+    return fail(EIK_ENOTSUP, "unsupported tile shape");
 }
 
 }  // namespace
@@ -650,6 +821,46 @@ int eik_solve(const eik_grid* g, const double* field, int64_t nsrc, const int64_
     int64_t offs[2] = {0, (int64_t)g->nx * g->ny * g->nz};
     int64_t soff[2] = {0, nsrc};
     return eik_solve_batched(1, g, offs, field, soff, src_idx, src_t0, t_out, parents_out, opts, stream);
+}
+
+int eik_solve_noalloc(const eik_grid* g, const double* field, int64_t nsrc, const int64_t* src_idx,
+                      const double* src_t0, double* t_out, uint8_t* parents_out, const eik_opts* opts,
+                      void* stream) {
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (nsrc < 1) return fail(EIK_EINVAL, "nsrc must be >= 1");
+    if (nsrc > kNaMaxSrc) return fail(EIK_ENOTSUP, "eik_solve_noalloc: more than 65536 sources");
+    if (!field || !src_idx || !t_out) return fail(EIK_EINVAL, "NULL device pointer");
+    if ((rc = check_opts(opts))) return rc;
+    if (opts && (opts->flags & (EIK_FLAG_TIME_KERNELS | EIK_FLAG_TIMELINE)))
+        return fail(EIK_ENOTSUP, "eik_solve_noalloc: no kernel timing or timeline (they need memory)");
+    const TileShape ts = pick_tile(g->ndim, opts);
+    if (!tile_supported(g->ndim, ts.x, ts.y, ts.z)) return fail(EIK_ENOTSUP, "unsupported tile shape for this ndim");
+    if (opts && opts->op != EIK_OP_DBAR && g->ndim != 2)
+        return fail(EIK_ENOTSUP, "the ablation operators are two-dimensional");
+    ProbTable T;
+    T.probs = nullptr;
+    T.src_off = nullptr;
+    T.nprob = 1;
+    T.p0 = make_prob(*g, ts, 0, 0);
+    T.nsrc0 = nsrc;
+    const int64_t ntiles = tiles_of(T.p0);
+    if (ntiles > kNaMaxTiles)
+        return fail(EIK_ENOTSUP, "eik_solve_noalloc: more than 65536 tiles (use eik_solve)");
+    int dev = 0;
+    NaDevice* d = nullptr;
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    if ((rc = na_device(&dev, &d))) return rc;
+    const hipStream_t st = (hipStream_t)stream;
+    const Bufs b = na_bufs(*d, st);
+    const int64_t npts = (int64_t)g->nx * g->ny * g->nz;
+    if ((rc = na_dispatch(ts, b, T, nsrc, ntiles, npts, field, src_idx, src_t0, t_out, parents_out, opts)))
+        return rc;
+    d->wiped = true;
+    d->last_stream = st;
+    d->last_ntiles = ntiles;
+    d->last_seq = next_seq();
+    return EIK_OK;
 }
 
 int eik_parents(const eik_grid* g, const double* t, int64_t nsrc, const int64_t* src_idx,
@@ -761,14 +972,44 @@ int eik_reserve(int64_t ntiles, int64_t npts, void* stream) {
 }
 
 int eik_status(void* stream, eik_stats* out) {
+    const hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
     Workspace* w = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_ws.find(std::make_pair(dev, st));
+        if (it != g_ws.end()) w = it->second;
+    }
+    // The last call on this stream may have been eik_solve_noalloc, whose
+    // status words live in this device's scratch array; then nothing is
+    // allocated here either.
+    const int32_t* scal_src = nullptr;
+    const unsigned long long* ctr_src = nullptr;
+    int64_t last_ntiles = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_na_mu);
+        if (dev >= 0 && dev < kNaMaxDevices) {
+            const NaDevice& d = g_na[dev];
+            if (d.ptr && d.last_seq > 0 && d.last_stream == st && (!w || d.last_seq > w->last_seq)) {
+                scal_src = (const int32_t*)(d.ptr + kNaScal);
+                ctr_src = (const unsigned long long*)(d.ptr + kNaCounters);
+                last_ntiles = d.last_ntiles;
+            }
+        }
+    }
     int rc;
-    if ((rc = get_ws((hipStream_t)stream, &w))) return rc;
-    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    if (!scal_src) {
+        if (!w && (rc = get_ws(st, &w))) return rc;
+        scal_src = w->scal;
+        ctr_src = w->counters;
+        last_ntiles = w->last_ntiles;
+    }
+    HIP_TRY(hipStreamSynchronize(st));
     int32_t sc[kScalWords];
     unsigned long long ctr[kCounters];
-    HIP_TRY(hipMemcpy(sc, w->scal, sizeof(sc), hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(ctr, w->counters, sizeof(ctr), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(sc, scal_src, sizeof(sc), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(ctr, ctr_src, sizeof(ctr), hipMemcpyDeviceToHost));
     uint32_t flags = (uint32_t)sc[kSFlags];
     int code = EIK_OK;
     if (flags & kFlagWatchdog) code = EIK_EHANG;
@@ -780,11 +1021,11 @@ int eik_status(void* stream, eik_stats* out) {
         out->tile_visits = (int64_t)ctr[0];
         out->point_updates = (int64_t)ctr[1];
         out->relax_passes = (int64_t)ctr[2];
-        out->ntiles = w->last_ntiles;
+        out->ntiles = last_ntiles;
         out->flags = flags;
         out->status = code;
         out->kernel_ms = -1.0;
-        out->kernel_launches = (int64_t)w->ev_used;
+        out->kernel_launches = w ? (int64_t)w->ev_used : 0;
         for (int i = 0; i < 4; ++i) out->phase_us[i] = (double)ctr[5 + i] / 100.0;  // 100 MHz clock
         out->process_us = (double)ctr[9] / 100.0;
         out->workgroups = (int64_t)ctr[10];
@@ -793,7 +1034,7 @@ int eik_status(void* stream, eik_stats* out) {
         out->evaluations = (int64_t)ctr[16];
         out->improving = (int64_t)ctr[17];
         out->final_updates = (int64_t)ctr[18];
-        if (w->ev_used) {
+        if (w && w->ev_used) {
             double sum = 0.0;
             for (size_t i = 0; i < w->ev_used; ++i) {
                 float ms = 0.f;
@@ -803,7 +1044,7 @@ int eik_status(void* stream, eik_stats* out) {
             out->kernel_ms = sum / (double)w->ev_used;
         }
     }
-    w->ev_used = 0;
+    if (w) w->ev_used = 0;
     if (code != EIK_OK)
         g_last_error = code == EIK_EINVAL ? "warm-start times must be >= +0 and not NaN" : eik_strerror(code);
     return code;

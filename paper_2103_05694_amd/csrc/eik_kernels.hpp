@@ -92,11 +92,12 @@ __device__ __forceinline__ double field_q(double f, double h, int kind, bool& ok
 // ---------------------------------------------------------------------------
 
 // Clears tile states and requeue keys, the window, counters and flags.  When the
-// previous solve on this workspace ended abnormally (`poisoned`), it also
+// previous solve on this workspace ended abnormally (`poisoned`), or the caller
+// asks for it (`force_wipe`: memory whose contents are not known yet), it also
 // re-initialises the rings so no stale slot can be taken for a new item.
 __global__ void k_reset(Sched s, uint64_t* tkey, int ntiles, int32_t* srclist_count,
-                        long long ring_words) {
-    const bool wipe = __hip_atomic_load(s.poisoned, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+                        long long ring_words, int force_wipe) {
+    const bool wipe = force_wipe || __hip_atomic_load(s.poisoned, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
     const long long stride = (long long)gridDim.x * blockDim.x;
     const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     for (long long i = i0; i < ntiles; i += stride) {
