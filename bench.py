@@ -6,16 +6,23 @@ Headline (the JSON `value`): grid points solved per second for the 3D
 (1 + 0.1 g), one source at the surface centre, FP64).  One step = one complete
 forward solve through the C ABI: per-solve reset, source placement, the
 persistent soft-priority tile kernel and finalisation, with the speed field
-already resident in HBM.
+already resident in HBM.  After the timed steps the output is checked: the
+device status must be clean and the times' SHA-256 must equal the one the
+oracle's solve gives (tests/golden/layered_512x512x256_seed2.json).
 
 Also reported on the same JSON line:
   * roofline: the persistent solve kernel's algorithmic bytes (16 B per point:
     read the speed once, write the time once) over its mean duration measured
     with HIP events on its stream during the timed steps, against 8 TB/s;
     `traffic` comes from the committed rocprofv3 counter summary when it was
-    taken on the current kernel source, else null;
-  * cpu_baseline: the oracle (sequential binary-heap fast marching, 1 thread)
-    on a bounded sample (the same recipe at 256x256x128);
+    taken on the current kernel source, else null.  Beside it, a latency
+    estimate: the tile hops from the source tile to the farthest tile (a run
+    can pass values on only to its face neighbours) times the busy time of one
+    run measured with a single workgroup;
+  * cpu_baseline: the oracle, timed in a separate process on the host: one
+    sequential binary-heap solve on one core over a bounded sample of the same
+    recipe (512x512x128), and the tomography step (forward, parents, adjoint)
+    for one shot per host core, all cores in parallel;
   * batched: forward + adjoint shots/s for a tomography batch, one graph replay
     of two persistent launches vs one plain solve + adjoint per shot.
 
@@ -71,27 +78,119 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline() -> dict:
-    import numpy as np  # noqa: F401
-    import oracle
-    import workloads as W
-    p = W.layered_3d(512, 512, 128, h=10.0, seed=2)
-    t0 = time.perf_counter()
-    oracle.fmm(p.field, p.h, p.src)
-    dt = time.perf_counter() - t0
-    model = "unknown"
+def _host_cpu() -> str:
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
                 if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
+                    return line.split(":", 1)[1].strip()
     except OSError:
         pass
-    return {"value": p.npts / dt, "unit": "grid points/s", "cores": 1, "kind": "oracle",
-            "sample": "same layered+noise recipe (seed 2, surface-centre source) at 512x512x128 = "
-                      f"{p.npts} points, one sequential binary-heap solve, {dt:.1f} s",
-            "host_cpu": model, "host_threads": os.cpu_count()}
+    return "unknown"
+
+
+_TOMO = None
+
+
+def _tomo_shot(i: int):
+    """One tomography step of shot i on the CPU oracle: forward solve with
+    parents, misfit gradient at the receivers, adjoint.  Runs in a worker
+    process forked from the baseline process (no GPU there)."""
+    import numpy as np
+    import oracle
+    case, t_obs = _TOMO
+    src = np.array([case.sources[i]], dtype=np.int64)
+    t = oracle.fmm(case.s0, case.h, src, kind=oracle.SLOWNESS)
+    par = oracle.parents(t, src)
+    g = np.zeros(t.size)
+    np.add.at(g, case.receivers, t.reshape(-1)[case.receivers] - t_obs[i])
+    grad = oracle.adjoint(t, par, case.s0, case.h, g.reshape(t.shape), kind=oracle.SLOWNESS)
+    return float(np.abs(grad).sum())
+
+
+def _tomo_obs(i: int):
+    import numpy as np
+    import oracle
+    case = _TOMO[0]
+    src = np.array([case.sources[i]], dtype=np.int64)
+    return oracle.fmm(case.s_true, case.h, src, kind=oracle.SLOWNESS).reshape(-1)[case.receivers]
+
+
+def cpu_baseline_worker() -> dict:
+    """The oracle timed on the host (this runs in a process of its own that
+    never touches the GPU): one sequential solve on one core, and one
+    tomography step per core with all cores in parallel."""
+    global _TOMO
+    import multiprocessing as mp
+    import oracle
+    import workloads as W
+    oracle.lib()
+    p = W.layered_3d(512, 512, 128, h=10.0, seed=2)
+    t0 = time.perf_counter()
+    oracle.fmm(p.field, p.h, p.src)
+    dt = time.perf_counter() - t0
+    single = {"value": p.npts / dt, "unit": "grid points/s", "cores": 1, "kind": "oracle",
+              "sample": "same layered+noise recipe (seed 2, surface-centre source) at 512x512x128 = "
+                        f"{p.npts} points, one sequential binary-heap solve, {dt:.1f} s",
+              "host_cpu": _host_cpu(), "host_threads": os.cpu_count()}
+    # one worker per host core, at most 16 (the host share of one GPU)
+    cores = max(1, min(16, os.cpu_count() or 1))
+    case = W.tomography(256, 256, 128, nshots=32, seed=5)
+    shots = list(range(cores))
+    _TOMO = (case, None)
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores) as pool:
+        t_obs = dict(zip(shots, pool.map(_tomo_obs, shots)))
+    _TOMO = (case, t_obs)
+    with ctx.Pool(cores) as pool:
+        t0 = time.perf_counter()
+        pool.map(_tomo_shot, shots)
+        wall = time.perf_counter() - t0
+    single["batched"] = {
+        "value": len(shots) / wall, "unit": "shots/s (forward + parents + adjoint)", "cores": cores,
+        "kind": "oracle",
+        "sample": f"{len(shots)} of the 32 tomography shots on 256x256x128 (one per core, in parallel worker "
+                  f"processes), {wall:.1f} s wall"}
+    return single
+
+
+def cpu_baseline() -> dict:
+    """Runs cpu_baseline_worker in a child process (this process has the GPU
+    open) and returns its JSON."""
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker"], capture_output=True,
+                       text=True, timeout=900)
+    if r.returncode != 0:
+        raise RuntimeError(f"cpu baseline failed: {r.stderr[-2000:]}")
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+GOLDEN = os.path.join(ROOT, "tests", "golden", "layered_512x512x256_seed2.json")
+
+
+def times_sha256(t) -> str:
+    import numpy as np
+    return hashlib.sha256(np.ascontiguousarray(t, dtype="<f8").tobytes()).hexdigest()
+
+
+def latency_estimate(args, torch, eik, W, shape, src_xyz) -> dict:
+    """Tile hops from the source's tile to the farthest tile of the headline
+    grid (6-connected tile grid: a run passes values only to face
+    neighbours), times the busy time of one run (staging, relaxation, write
+    and publish) measured with a single workgroup on a 128x128x64 model of
+    the same recipe in the same launch configuration."""
+    nz, ny, nx = shape
+    tx, ty, tz = args.tile
+    nt = ((nx + tx - 1) // tx, (ny + ty - 1) // ty, (nz + tz - 1) // tz)
+    s = (src_xyz[0] // tx, src_xyz[1] // ty, src_xyz[2] // tz)
+    hops = sum(max(s[k], nt[k] - 1 - s[k]) for k in range(3))
+    q = W.layered_3d(128, 128, 64, h=10.0, seed=2)
+    f = torch.from_numpy(q.field).cuda()
+    eik.solve(f, q.h, torch.as_tensor(q.src).cuda(), delta=args.delta, tile=args.tile, grid_blocks=1,
+              horizon=args.horizon, packed=args.packed)
+    st = eik.status()
+    run_us = (st.phase_us[1] + st.phase_us[2] + st.phase_us[3]) / max(st.tile_visits, 1)
+    return {"tile_hops": hops, "run_us_one_workgroup": run_us, "latency_bound_ms": hops * run_us * 1e-3}
 
 
 def bench_single(args, torch, eik, W) -> dict:
@@ -101,7 +200,7 @@ def bench_single(args, torch, eik, W) -> dict:
     src = torch.as_tensor(p.src).cuda()
     out = torch.empty_like(f)
     kw = dict(delta=args.delta, tile=args.tile, grid_blocks=args.grid_blocks, horizon=args.horizon, out=out,
-              check_status=False)
+              packed=args.packed, check_status=False)
     for _ in range(args.warmup):
         eik.solve(f, p.h, src, **kw)
     eik.status()
@@ -111,8 +210,16 @@ def bench_single(args, torch, eik, W) -> dict:
         eik.solve(f, p.h, src, time_kernels=True, **kw)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    st = eik.status()
+    st = eik.status()   # raises on any device-side error of the timed solves
     ms = wall * 1e3 / args.steps
+    # the timed output is the oracle's solution, bit for bit
+    digest = times_sha256(out.cpu().numpy())
+    golden = None
+    if os.path.exists(GOLDEN):
+        with open(GOLDEN) as fh:
+            golden = json.load(fh)
+    validated = (golden is not None and golden["input_sha256_16"] == p.sha256()
+                 and golden["times_sha256"] == digest)
     kernel_ms = st.kernel_ms
     algo_bytes = 16.0 * p.npts
     achieved = algo_bytes / (kernel_ms * 1e-3) / 1e9
@@ -135,7 +242,12 @@ def bench_single(args, torch, eik, W) -> dict:
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_solve (persistent soft-priority tile solver)",
                      "algorithmic_bytes_per_launch": algo_bytes},
+        "output": {"status": int(st.status), "times_sha256": digest,
+                   "oracle_sha256": golden["times_sha256"] if golden else None, "validated": validated},
     }
+    lat = latency_estimate(args, torch, eik, W, p.shape, (p.nx // 2, p.ny // 2, 0))
+    res["roofline"].update(lat)
+    res["roofline"]["latency_frac"] = lat["latency_bound_ms"] / kernel_ms
     # with the parent record (adds 9 B/pt)
     if args.parents:
         par = torch.empty(f.shape, dtype=torch.uint8, device="cuda")
@@ -160,14 +272,14 @@ def bench_tomography(args, torch, eik, W) -> dict:
     rec = torch.as_tensor(case.receivers).cuda()
     obs = ShotBatch([s_true] * args.shots, case.h, srcs, [rec] * args.shots, kind="slowness",
                     delta=args.tomo_delta, tile=args.tomo_tile, grid_blocks=args.tomo_grid_blocks,
-                    horizon=args.tomo_horizon, **args.adj_cfg)
+                    horizon=args.tomo_horizon, packed=args.tomo_packed, **args.adj_cfg)
     obs.step()
     obs.sync()
     eik.status(obs.stream)
     t_obs = [v.reshape(-1).index_select(0, rec) for v in obs.shot_views(obs.t)]
     sb = ShotBatch([s0] * args.shots, case.h, srcs, [rec] * args.shots, t_obs=t_obs, kind="slowness",
                    delta=args.tomo_delta, tile=args.tomo_tile, grid_blocks=args.tomo_grid_blocks,
-                   horizon=args.tomo_horizon, **args.adj_cfg)
+                   horizon=args.tomo_horizon, packed=args.tomo_packed, **args.adj_cfg)
     sb.capture()
     reps = max(args.steps // 4, 2)
     for _ in range(2):
@@ -221,7 +333,8 @@ def bench_uneven(args, torch, eik, W) -> dict:
         recs.append(torch.as_tensor(W.flat_index(RX.ravel(), RY.ravel(), 0, p.nx, p.ny)).cuda())
     npts = sum(p.npts for p in shots)
     obs = ShotBatch(fields_true, 10.0, srcs, recs, kind="slowness", delta=args.tomo_delta, tile=args.tomo_tile,
-                    grid_blocks=args.tomo_grid_blocks, horizon=args.tomo_horizon, **args.adj_cfg)
+                    grid_blocks=args.tomo_grid_blocks, horizon=args.tomo_horizon, packed=args.tomo_packed,
+                    **args.adj_cfg)
     obs.step()
     obs.sync()
     eik.status(obs.stream)
@@ -229,7 +342,7 @@ def bench_uneven(args, torch, eik, W) -> dict:
     del obs
     sb = ShotBatch(fields, 10.0, srcs, recs, t_obs=t_obs, kind="slowness", delta=args.tomo_delta,
                    tile=args.tomo_tile, grid_blocks=args.tomo_grid_blocks, horizon=args.tomo_horizon,
-                   **args.adj_cfg)
+                   packed=args.tomo_packed, **args.adj_cfg)
     sb.capture()
     reps = max(args.steps // 8, 2)
     sb.replay()
@@ -302,7 +415,7 @@ def bench_schedules(args, torch, eik, W) -> dict:
     p = W.layered_3d(512, 512, 256, h=10.0, seed=2)
     f = torch.from_numpy(p.field).cuda()
     src = torch.as_tensor(p.src).cuda()
-    kw = dict(tile=args.tile, grid_blocks=args.grid_blocks, check_status=False)
+    kw = dict(tile=args.tile, grid_blocks=args.grid_blocks, packed=args.packed, check_status=False)
     ref = eik.solve(f, p.h, src, delta=args.delta, horizon=args.horizon, **kw)
     eik.status()
     out = {"workload": "3D 512x512x256 layered model (the headline solve)", "tile": list(args.tile), "rows": []}
@@ -338,8 +451,9 @@ def bench_paper_scale(args, torch, eik, W) -> dict:
     delta = cfg["delta"] if cfg else 32 * p.h / 3000.0
     gb = int(cfg.get("grid_blocks", 0)) if cfg else 0
     hz = int(cfg.get("horizon", 0)) if cfg else 0
+    pk = bool(cfg.get("packed", False)) if cfg else False
     out = torch.empty_like(f)
-    kw = dict(tile=tile, delta=delta, grid_blocks=gb, horizon=hz, out=out, check_status=False)
+    kw = dict(tile=tile, delta=delta, grid_blocks=gb, horizon=hz, out=out, packed=pk, check_status=False)
     eik.solve(f, p.h, src, **kw)
     eik.status()
     reps = 3
@@ -359,24 +473,31 @@ def bench_paper_scale(args, torch, eik, W) -> dict:
 
 
 def profile_mode(args, torch, eik, W) -> None:
-    """A short run for rocprofv3: a plain 1 GiB device copy (counter
-    calibration), then a few solves of the headline workload."""
+    """A short run for rocprofv3: kernels of known traffic for the counter
+    calibration -- a plain 1 GiB device copy (reads and writes 1 GiB), the
+    residual kernel over the headline grid (reads its times, speeds and
+    source mask: 17 B per point) -- then a few solves of the headline
+    workload in the benchmark's launch configuration."""
     n = (1 << 30) // 8
     a = torch.ones(n, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
+    del a, b
     p = W.layered_3d(512, 512, 256, h=10.0, seed=2)
     f = torch.from_numpy(p.field).cuda()
     src = torch.as_tensor(p.src).cuda()
+    out = torch.empty_like(f)
     for i in range(args.steps):
         eik.solve(f, p.h, src, delta=args.delta, tile=args.tile, grid_blocks=args.grid_blocks,
-                  horizon=args.horizon, check_status=False)
+                  horizon=args.horizon, packed=args.packed, out=out, check_status=False)
         torch.cuda.synchronize()
         log(f"profile solve {i} done")
     eik.status()
+    res = eik.residual(f, p.h, src, out)
+    torch.cuda.synchronize()
     print(json.dumps({"profile_mode": True, "copy_bytes_each_way": n * 8, "solves": args.steps,
-                      "npts": p.npts, "source_hash": kernel_source_hash()}), flush=True)
+                      "npts": p.npts, "residual": list(res), "source_hash": kernel_source_hash()}), flush=True)
 
 
 def main() -> int:
@@ -400,7 +521,12 @@ def main() -> int:
     ap.add_argument("--no-schedules", action="store_true")
     ap.add_argument("--no-paper-scale", action="store_true")
     ap.add_argument("--profile-mode", action="store_true")
+    ap.add_argument("--cpu-baseline-worker", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
+
+    if args.cpu_baseline_worker:
+        print(json.dumps(cpu_baseline_worker()), flush=True)
+        return 0
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -427,6 +553,7 @@ def main() -> int:
         args.grid_blocks = int(cfg.get("grid_blocks", 0)) if cfg else 0
     if args.horizon is None:
         args.horizon = int(cfg.get("horizon", 0)) if cfg else 0
+    args.packed = bool(cfg.get("packed", False)) if cfg else False
     tcfg = autotune.lookup_batch(args.shots, (128, 256, 256), "slowness") or \
         autotune.lookup((128, 256, 256), "slowness")
     if args.tomo_tile is not None:
@@ -437,6 +564,7 @@ def main() -> int:
         args.tomo_delta = tcfg["delta"] if tcfg else 0.02
     args.tomo_grid_blocks = int(tcfg.get("grid_blocks", 0)) if tcfg else 0
     args.tomo_horizon = int(tcfg.get("horizon", 0)) if tcfg else 0
+    args.tomo_packed = bool(tcfg.get("packed", False)) if tcfg else False
     args.adj_cfg = {}
     if tcfg and "adj_delta" in tcfg:
         args.adj_cfg = dict(adj_delta=tcfg["adj_delta"], adj_tile=tuple(tcfg["adj_tile"]),
@@ -444,7 +572,8 @@ def main() -> int:
     # the per-shot baseline runs with the single-shot tuning (its best), not the batch's
     scfg = autotune.lookup((128, 256, 256), "slowness")
     args.shot_cfg = (dict(delta=scfg["delta"], tile=tuple(scfg["tile"]), grid_blocks=int(scfg.get("grid_blocks", 0)),
-                          horizon=int(scfg.get("horizon", 0))) if scfg else {})
+                          horizon=int(scfg.get("horizon", 0)), packed=bool(scfg.get("packed", False)))
+                     if scfg else {})
     args.shot_cfg.update(args.adj_cfg)
 
     if args.profile_mode:
@@ -480,6 +609,8 @@ def main() -> int:
         log("cpu baseline (oracle)")
         cpu = cpu_baseline()
     value = single["npts"] / (single["ms_per_step"] * 1e-3)
+    if not single["output"]["validated"]:
+        log(f"ERROR: the timed output does not match the oracle's hash: {single['output']}")
     line = {
         "metric": METRIC, "value": value, "unit": "grid points/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": single["ms_per_step"], "higher_is_better": True,
@@ -487,14 +618,14 @@ def main() -> int:
         "config": {"workload": "3D 512x512x256 layered+noise speed (h=10 m, 1500-6000 m/s, 8 layers, "
                                "seed 2), one surface-centre source, single forward solve",
                    "delta": args.delta, "tile": list(args.tile), "grid_blocks": args.grid_blocks,
-                   "horizon": args.horizon,
+                   "horizon": args.horizon, "packed": args.packed,
                    "points": single["npts"]},
         "roofline": single["roofline"],
         "cpu_baseline": cpu,
         "extra": extra,
     }
     print(json.dumps(line), flush=True)
-    return 0
+    return 0 if single["output"]["validated"] else 3
 
 
 if __name__ == "__main__":

@@ -31,6 +31,7 @@ EIK_OP_DTILDE = 2
 EIK_OP_NEWTON = 3
 EIK_FLAG_TRACK_CHANGE = 8
 EIK_FLAG_WARM_START = 16
+EIK_FLAG_PACKED = 32
 
 EXPORTED = (
     "eik_solve", "eik_parents", "eik_adjoint", "eik_solve_batched", "eik_adjoint_batched",

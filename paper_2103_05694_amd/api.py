@@ -41,7 +41,7 @@ def make_opts(delta: float = 0.0, tile: Optional[Sequence[int]] = None, grid_blo
               max_tile_visits: int = 0, time_kernels: bool = False, lookahead: int = 0,
               timeline: bool = False, op: str = "dbar", horizon: int = 0,
               work_ref: Optional[torch.Tensor] = None, track_change: bool = False,
-              warm_start: bool = False) -> eik_opts:
+              warm_start: bool = False, packed: bool = False) -> eik_opts:
     o = eik_opts()
     o.delta = float(delta)
     t = tuple(tile) if tile else (0, 0, 0)
@@ -53,7 +53,7 @@ def make_opts(delta: float = 0.0, tile: Optional[Sequence[int]] = None, grid_blo
     o.max_tile_visits = int(max_tile_visits)
     o.flags = (_lib.EIK_FLAG_TIME_KERNELS if time_kernels else 0) | \
         (_lib.EIK_FLAG_TIMELINE if timeline else 0) | (_lib.EIK_FLAG_TRACK_CHANGE if track_change else 0) | \
-        (_lib.EIK_FLAG_WARM_START if warm_start else 0)
+        (_lib.EIK_FLAG_WARM_START if warm_start else 0) | (_lib.EIK_FLAG_PACKED if packed else 0)
     o.lookahead = int(lookahead)
     o.horizon = int(horizon)
     o.op = _op_code(op)
@@ -174,8 +174,10 @@ def solve(field: torch.Tensor, h: float, sources, t0: Optional[torch.Tensor] = N
           out: Optional[torch.Tensor] = None, parents_out: Optional[torch.Tensor] = None,
           check_status: bool = True, stream=None, time_kernels: bool = False, lookahead: int = 0,
           timeline: bool = False, op: str = "dbar", horizon: int = 0,
-          work_ref: Optional[torch.Tensor] = None, track_change: bool = False, warm_start: bool = False):
+          work_ref: Optional[torch.Tensor] = None, track_change: bool = False, warm_start: bool = False,
+          packed: bool = False):
     """First-arrival times; returns t, or (t, parents) when parents=True.
+    `packed` selects the compacted relaxation passes (EIK_FLAG_PACKED).
 
     With warm_start=True the solve resumes from the times in `out` (required):
     any upper bound of the solution, e.g. the output of a solve stopped by
@@ -205,7 +207,7 @@ def solve(field: torch.Tensor, h: float, sources, t0: Optional[torch.Tensor] = N
         if work_ref.shape != field.shape:
             raise ValueError("work_ref must have the field's shape")
     o = make_opts(delta, tile, grid_blocks, max_tile_visits, time_kernels, lookahead, timeline, op,
-                  horizon, work_ref, track_change, warm_start)
+                  horizon, work_ref, track_change, warm_start, packed)
     rc = L.eik_solve(ctypes.byref(g), field.data_ptr(), src.numel(), src.data_ptr(),
                      t0d.data_ptr() if t0d is not None else None, t.data_ptr(),
                      par.data_ptr() if par is not None else None, ctypes.byref(o),
@@ -355,14 +357,15 @@ def pack(fields: Sequence[torch.Tensor], hs: Union[float, Sequence[float]], sour
 
 def solve_packed(b: Batch, t_packed: torch.Tensor, par_packed: Optional[torch.Tensor] = None,
                  delta: float = 0.0, tile=None, grid_blocks: int = 0, stream=None,
-                 time_kernels: bool = False, lookahead: int = 0, horizon: int = 0) -> None:
+                 time_kernels: bool = False, lookahead: int = 0, horizon: int = 0,
+                 packed: bool = False) -> None:
     """Enqueue one batched forward launch (no host synchronisation)."""
     dev = b.field.device
     _check_buf(t_packed, "t_packed", torch.float64, b.npts, dev)
     if par_packed is not None:
         _check_buf(par_packed, "par_packed", torch.uint8, b.npts, dev)
     L = _lib.load()
-    o = make_opts(delta, tile, grid_blocks, 0, time_kernels, lookahead, horizon=horizon)
+    o = make_opts(delta, tile, grid_blocks, 0, time_kernels, lookahead, horizon=horizon, packed=packed)
     check(L.eik_solve_batched(b.nprob, b.grids, b.offsets, b.field.data_ptr(), b.src_off,
                               b.src.data_ptr(), b.t0.data_ptr() if b.t0 is not None else None,
                               t_packed.data_ptr(), par_packed.data_ptr() if par_packed is not None else None,
@@ -391,12 +394,12 @@ def adjoint_packed(b: Batch, t_packed: torch.Tensor, par_packed: torch.Tensor, g
 
 def solve_batched(fields: Sequence[torch.Tensor], h, sources, kind: str = "speed", parents: bool = False,
                   delta: float = 0.0, tile=None, check_status: bool = True, grid_blocks: int = 0,
-                  horizon: int = 0):
+                  horizon: int = 0, packed: bool = False):
     """Solve independent problems (uneven sizes allowed) in one persistent launch."""
     b = pack(fields, h, sources, kind)
     t = torch.empty(b.npts, dtype=torch.float64, device=b.field.device)
     par = torch.empty(b.npts, dtype=torch.uint8, device=b.field.device) if parents else None
-    solve_packed(b, t, par, delta, tile, grid_blocks=grid_blocks, horizon=horizon)
+    solve_packed(b, t, par, delta, tile, grid_blocks=grid_blocks, horizon=horizon, packed=packed)
     if check_status:
         status()
     ts = b.views(t)

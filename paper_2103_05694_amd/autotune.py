@@ -30,8 +30,9 @@ ARCH = "gfx950"
 TILES = {3: [(16, 8, 8), (8, 8, 8), (32, 8, 4)],
          2: [(32, 32), (16, 16), (64, 16)]}
 DELTA_FACTORS = (0.0, 0.25, 0.5, 1.0, 2.0, 4.0, 8.0)
-GRID_BLOCKS = (0, 512)   # 0 = as many workgroups as fit on the device
+GRID_BLOCKS = (0,)       # 0 = as many workgroups as fit on the device
 HORIZONS = (0, 1, 2)     # 0 = off; k = settle values below (bucket + k) only
+PACKED = (False, True)   # relaxation passes: per-thread points, or compacted lists
 
 
 def _key(shape: Sequence[int], kind: str) -> str:
@@ -63,7 +64,7 @@ def tune(field: torch.Tensor, h: float, sources, kind: str = "speed",
          tiles: Optional[Iterable[Tuple[int, ...]]] = None,
          delta_factors: Sequence[float] = DELTA_FACTORS, reps: int = 3,
          grid_blocks: Sequence[int] = GRID_BLOCKS, horizons: Sequence[int] = HORIZONS,
-         save: bool = True, log=print) -> dict:
+         packed: Sequence[bool] = PACKED, save: bool = True, log=print) -> dict:
     """Time every (tile, delta, grid size) candidate on this problem; all must
     agree bitwise."""
     nd = field.dim()
@@ -75,38 +76,42 @@ def tune(field: torch.Tensor, h: float, sources, kind: str = "speed",
     results: List[dict] = []
     out = torch.empty_like(field)
 
-    def run(tile, fac, gb, hz):
+    def run(tile, fac, gb, hz, pk):
         nonlocal ref
         delta = fac * qmed * min(tile[:nd])
         fn = lambda: api.solve(field, h, sources, kind=kind, delta=delta, tile=tile, out=out,
-                               grid_blocks=gb, horizon=hz, check_status=False)
+                               grid_blocks=gb, horizon=hz, packed=pk, check_status=False)
         fn()
         api.status()
         t = out.clone()
         if ref is None:
             ref = t
         elif not torch.equal(ref, t):
-            raise RuntimeError(f"candidate tile={tile} delta={delta} grid={gb} horizon={hz} changed the result")
+            raise RuntimeError(f"candidate tile={tile} delta={delta} grid={gb} horizon={hz} packed={pk} "
+                               "changed the result")
         sec = _time(fn, reps)
         api.status()
         results.append({"tile": list(tile), "delta": delta, "delta_factor": fac, "grid_blocks": gb,
-                        "horizon": hz, "ms": sec * 1e3})
-        log(f"  tile {tile} delta {delta:.4g} ({fac:.3g} x qmed x edge) grid {gb} horizon {hz}: "
+                        "horizon": hz, "packed": pk, "ms": sec * 1e3})
+        log(f"  tile {tile} delta {delta:.4g} ({fac:.3g} x qmed x edge) grid {gb} horizon {hz} packed {pk}: "
             f"{sec * 1e3:.3f} ms")
 
     for tile in tiles:
         for fac in delta_factors:
             for hz in (horizons if fac > 0 else (0,)):
                 for gb in grid_blocks:
-                    run(tile, fac, gb, hz)
+                    for pk in packed:
+                        run(tile, fac, gb, hz, pk)
     # refine the best bucket width between its neighbours on the doubling grid
     best = min(results, key=lambda r: r["ms"])
     if best["delta_factor"] > 0:
         for step in (2.0 ** -0.5, 2.0 ** 0.5):
-            run(tuple(best["tile"]), best["delta_factor"] * step, best["grid_blocks"], best["horizon"])
+            run(tuple(best["tile"]), best["delta_factor"] * step, best["grid_blocks"], best["horizon"],
+                best["packed"])
     best = min(results, key=lambda r: r["ms"])
     entry = {"tile": best["tile"], "delta": best["delta"], "grid_blocks": best["grid_blocks"],
-             "horizon": best["horizon"], "ms": best["ms"], "qmed": qmed, "candidates": results}
+             "horizon": best["horizon"], "packed": best["packed"], "ms": best["ms"], "qmed": qmed,
+             "candidates": results}
     if save:
         cache = _load()
         cache[_key(field.shape, kind)] = entry
@@ -128,7 +133,8 @@ def tune_batch(fields: Sequence[torch.Tensor], h: float, sources, receivers, kin
                tiles: Optional[Iterable[Tuple[int, ...]]] = None,
                delta_factors: Sequence[float] = (0.25, 0.5, 1.0, 2.0, 4.0),
                adj_delta_factors: Sequence[float] = (0.0, 0.5, 1.0, 2.0, 4.0, 8.0),
-               grid_blocks: Sequence[int] = (0,), reps: int = 2, save: bool = True, log=print) -> dict:
+               grid_blocks: Sequence[int] = (0,), packed: Sequence[bool] = PACKED, reps: int = 2,
+               save: bool = True, log=print) -> dict:
     """Tune a batch of shots (forward with parents, then the adjoint) in one
     persistent launch each: a batch has many times the parallel work of one
     shot, so its best trade-off differs, and the readiness-driven adjoint is
@@ -149,30 +155,31 @@ def tune_batch(fields: Sequence[torch.Tensor], h: float, sources, receivers, kin
     fwd: List[dict] = []
     ref = None
 
-    def run_fwd(tile, fac, gb):
+    def run_fwd(tile, fac, gb, pk):
         nonlocal ref
         delta = fac * qmed * min(tile[:nd])
-        fn = lambda: api.solve_packed(b, t, par, delta, tile, grid_blocks=gb)
+        fn = lambda: api.solve_packed(b, t, par, delta, tile, grid_blocks=gb, packed=pk)
         fn()
         api.status()
         if ref is None:
             ref = (t.clone(), par.clone())
         elif not (torch.equal(ref[0], t) and torch.equal(ref[1], par)):
-            raise RuntimeError(f"batch forward tile={tile} delta={delta} grid={gb} changed the result")
+            raise RuntimeError(f"batch forward tile={tile} delta={delta} grid={gb} packed={pk} changed the result")
         sec = _time(fn, reps)
         api.status()
-        fwd.append({"tile": list(tile), "delta": delta, "delta_factor": fac, "grid_blocks": gb,
+        fwd.append({"tile": list(tile), "delta": delta, "delta_factor": fac, "grid_blocks": gb, "packed": pk,
                     "ms": sec * 1e3})
-        log(f"  batch forward tile {tile} delta {delta:.4g} grid {gb}: {sec * 1e3:.2f} ms")
+        log(f"  batch forward tile {tile} delta {delta:.4g} grid {gb} packed {pk}: {sec * 1e3:.2f} ms")
 
     for tile in tiles:
         for fac in delta_factors:
             for gb in grid_blocks:
-                run_fwd(tile, fac, gb)
+                for pk in packed:
+                    run_fwd(tile, fac, gb, pk)
     bf = min(fwd, key=lambda r: r["ms"])
     if bf["delta_factor"] > 0:
         for step in (2.0 ** -0.5, 2.0 ** 0.5):
-            run_fwd(tuple(bf["tile"]), bf["delta_factor"] * step, bf["grid_blocks"])
+            run_fwd(tuple(bf["tile"]), bf["delta_factor"] * step, bf["grid_blocks"], bf["packed"])
     t.copy_(ref[0])
     par.copy_(ref[1])
     adj: List[dict] = []
@@ -205,6 +212,7 @@ def tune_batch(fields: Sequence[torch.Tensor], h: float, sources, receivers, kin
     bf = min(fwd, key=lambda r: r["ms"])
     ba = min(adj, key=lambda r: r["ms"])
     entry = {"tile": bf["tile"], "delta": bf["delta"], "grid_blocks": bf["grid_blocks"], "horizon": 0,
+             "packed": bf["packed"],
              "adj_tile": ba["tile"], "adj_delta": ba["delta"], "adj_grid_blocks": ba["grid_blocks"],
              "ms": bf["ms"] + ba["ms"], "forward_ms": bf["ms"], "adjoint_ms": ba["ms"], "qmed": qmed,
              "forward_candidates": fwd, "adjoint_candidates": adj}

@@ -26,12 +26,13 @@ class ShotBatch:
                  t_obs: Optional[Sequence[torch.Tensor]] = None, kind: str = "slowness",
                  delta: float = 0.0, tile=None, stream: Optional[torch.cuda.Stream] = None,
                  grid_blocks: int = 0, horizon: int = 0, adj_delta: Optional[float] = None,
-                 adj_tile=None, adj_grid_blocks: Optional[int] = None):
+                 adj_tile=None, adj_grid_blocks: Optional[int] = None, packed: bool = False):
         self.kind = kind
         self.delta = delta
         self.tile = tile
         self.grid_blocks = grid_blocks
         self.horizon = horizon
+        self.packed = packed
         # the adjoint is readiness-driven and may prefer other launch parameters
         self.adj_delta = delta if adj_delta is None else adj_delta
         self.adj_tile = tile if adj_tile is None else adj_tile
@@ -63,7 +64,7 @@ class ShotBatch:
     # -- one batched step: 2 persistent launches for all shots ----------------
     def _enqueue(self) -> None:
         api.solve_packed(self.b, self.t, self.par, self.delta, self.tile, grid_blocks=self.grid_blocks,
-                         stream=self.stream, horizon=self.horizon)
+                         stream=self.stream, horizon=self.horizon, packed=self.packed)
         self.g.zero_()
         self.g.index_copy_(0, self.rec, self.t.index_select(0, self.rec) - self.t_obs)
         api.adjoint_packed(self.b, self.t, self.par, self.g, self.grad, self.mu, self.adj_delta, self.adj_tile,
@@ -110,7 +111,7 @@ class ShotBatch:
     def plain_step(self, t_out: torch.Tensor, grad_out: torch.Tensor, delta: Optional[float] = None,
                    tile=None, grid_blocks: Optional[int] = None, horizon: Optional[int] = None,
                    adj_delta: Optional[float] = None, adj_tile=None,
-                   adj_grid_blocks: Optional[int] = None) -> None:
+                   adj_grid_blocks: Optional[int] = None, packed: Optional[bool] = None) -> None:
         """Per-shot eik_solve + eik_adjoint launches on the current stream,
         writing into packed outputs.  The launch parameters default to the
         batch's; a single shot may prefer others (it has far less parallel
@@ -119,6 +120,7 @@ class ShotBatch:
         tile = self.tile if tile is None else tile
         grid_blocks = self.grid_blocks if grid_blocks is None else grid_blocks
         horizon = self.horizon if horizon is None else horizon
+        packed = self.packed if packed is None else packed
         adj_delta = self.adj_delta if adj_delta is None else adj_delta
         adj_tile = self.adj_tile if adj_tile is None else adj_tile
         adj_grid_blocks = self.adj_grid_blocks if adj_grid_blocks is None else adj_grid_blocks
@@ -130,7 +132,7 @@ class ShotBatch:
         for i in range(self.nshots):
             t, par = api.solve(self.fields[i], self.hs[i], self.sources[i], kind=self.kind, parents=True,
                                delta=delta, tile=tile, grid_blocks=grid_blocks, horizon=horizon, out=tv[i],
-                               check_status=False)
+                               packed=packed, check_status=False)
             r = self.rec_local[i]
             nr = r.numel()
             gvv[i].view(-1).index_copy_(0, r, t.view(-1).index_select(0, r) - self.t_obs[rec_off:rec_off + nr])

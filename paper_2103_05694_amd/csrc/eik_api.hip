@@ -13,6 +13,10 @@
 #include <vector>
 
 #include "eik.h"
+
+#ifndef EIK_SOLVE_THREADS
+#define EIK_SOLVE_THREADS 1024
+#endif
 #include "eik_adjoint.hpp"
 
 using namespace eik;
@@ -38,6 +42,12 @@ constexpr int kThreads = 256;
 // 256 (tiles of 64 or 128 points run as one or two waves).
 template <int TX, int TY, int TZ>
 constexpr int tile_threads() { return TX * TY * TZ < kThreads ? TX * TY * TZ : kThreads; }
+// Workgroup size of the forward solver: one thread per point (up to 1024), so
+// a relaxation pass applies the operator at most once per thread (the
+// operator's latency sets the cost of a pass).
+constexpr int kSolveThreads = EIK_SOLVE_THREADS;
+template <int TX, int TY, int TZ>
+constexpr int solve_threads() { return TX * TY * TZ < kSolveThreads ? TX * TY * TZ : kSolveThreads; }
 constexpr int kRings = 32;
 constexpr int kScalWords = 192;
 constexpr int kTimelineCap = 1 << 16;
@@ -304,8 +314,11 @@ int check_opts(const eik_opts* o) {
         return fail(EIK_EINVAL, "delta too small (its reciprocal overflows)");
     if (o->grid_blocks < 0) return fail(EIK_EINVAL, "grid_blocks must be >= 0");
     if (o->max_tile_visits < 0) return fail(EIK_EINVAL, "max_tile_visits must be >= 0");
-    if (o->flags & ~(EIK_FLAG_TIME_KERNELS | EIK_FLAG_TIMELINE | EIK_FLAG_TRACK_CHANGE | EIK_FLAG_WARM_START))
+    if (o->flags & ~(EIK_FLAG_TIME_KERNELS | EIK_FLAG_TIMELINE | EIK_FLAG_TRACK_CHANGE | EIK_FLAG_WARM_START |
+                     EIK_FLAG_PACKED))
         return fail(EIK_EINVAL, "unknown flags");
+    if ((o->flags & EIK_FLAG_PACKED) && o->op != EIK_OP_DBAR)
+        return fail(EIK_ENOTSUP, "compacted passes run with d-bar only");
     if (o->lookahead < 0 || o->lookahead > 8) return fail(EIK_EINVAL, "lookahead must be in 0..8");
     if (o->op < EIK_OP_DBAR || o->op > EIK_OP_NEWTON) return fail(EIK_EINVAL, "unknown operator");
     if ((o->flags & EIK_FLAG_TRACK_CHANGE) && o->op == EIK_OP_DBAR)
@@ -395,8 +408,7 @@ Sched make_sched(const Bufs& w, const eik_opts* o) {
 // Persistent workgroups that fit on the device at once.  With `cached`, the
 // per-kernel occupancy is remembered (a host map); the allocation-free entry
 // point asks the runtime every time instead.
-template <class K>
-int occupancy_grid(K kernel, int threads, int* out, bool cached = true) {
+int occupancy_grid(const void* kernel, int threads, int* out, bool cached = true) {
     static std::map<const void*, int> cache;
     static std::mutex m;
     int per_cu = 0;
@@ -468,29 +480,34 @@ int forward_seq(const Bufs& b, const ProbTable& T, int64_t nsrc, int64_t ntiles,
     a.tkey = b.tkey;
     a.work_ref = o ? o->work_ref : nullptr;
     a.s = s;
-    int grid = 0;
-    constexpr int nt = tile_threads<TX, TY, TZ>();
+    // the two pass structures of k_solve: one thread per point (default) or
+    // compacted pass lists on 256-thread blocks (EIK_FLAG_PACKED, d-bar only)
+    constexpr int nt = solve_threads<TX, TY, TZ>();
+    constexpr int ntp = tile_threads<TX, TY, TZ>();
     const bool count = a.work_ref != nullptr;
+    const bool pack = o && (o->flags & EIK_FLAG_PACKED);
+    const void* kern = nullptr;
+    int threads = nt;
     if constexpr (OP == EIK_OP_DBAR) {
-        if (count) {
-            if ((rc = occupancy_grid(k_solve<TX, TY, TZ, nt, OP, true>, nt, &grid, cached))) return rc;
+        if (pack) {
+            threads = ntp;
+            kern = count ? (const void*)k_solve<TX, TY, TZ, ntp, OP, true, true>
+                         : (const void*)k_solve<TX, TY, TZ, ntp, OP, false, true>;
         } else {
-            if ((rc = occupancy_grid(k_solve<TX, TY, TZ, nt, OP>, nt, &grid, cached))) return rc;
+            kern = count ? (const void*)k_solve<TX, TY, TZ, nt, OP, true>
+                         : (const void*)k_solve<TX, TY, TZ, nt, OP>;
         }
     } else {
-        if ((rc = occupancy_grid(k_solve<TX, TY, TZ, nt, OP>, nt, &grid, cached))) return rc;
+        kern = (const void*)k_solve<TX, TY, TZ, nt, OP>;
     }
+    int grid = 0;
+    if ((rc = occupancy_grid(kern, threads, &grid, cached))) return rc;
     if (o && o->grid_blocks > 0) grid = std::min(grid, o->grid_blocks);
     if ((int64_t)grid > ntiles) grid = (int)ntiles;
     if (grid < 1) grid = 1;
     if (tw && (rc = timing_begin(*tw, o))) return rc;
-    if constexpr (OP == EIK_OP_DBAR) {
-        if (count) hipLaunchKernelGGL((k_solve<TX, TY, TZ, nt, OP, true>), dim3(grid), dim3(nt), 0, st, a);
-        else hipLaunchKernelGGL((k_solve<TX, TY, TZ, nt, OP>), dim3(grid), dim3(nt), 0, st, a);
-    } else {
-        hipLaunchKernelGGL((k_solve<TX, TY, TZ, nt, OP>), dim3(grid), dim3(nt), 0, st, a);
-    }
-    HIP_TRY(hipGetLastError());
+    void* kargs[] = {(void*)&a};
+    HIP_TRY(hipLaunchKernel(kern, dim3(grid), dim3(threads), kargs, 0, st));
     if (tw && (rc = timing_end(*tw, o))) return rc;
 
     if (par)
@@ -595,7 +612,7 @@ int adjoint(Workspace& w, const std::vector<Prob>& probs, int64_t ntiles, int64_
     a.s = s;
     int grid = 0;
     constexpr int nt = tile_threads<TX, TY, TZ>();
-    if ((rc = occupancy_grid(k_adjoint<TX, TY, TZ, nt>, nt, &grid))) return rc;
+    if ((rc = occupancy_grid((const void*)k_adjoint<TX, TY, TZ, nt>, nt, &grid))) return rc;
     if (o && o->grid_blocks > 0) grid = std::min(grid, o->grid_blocks);
     if ((int64_t)grid > ntiles) grid = (int)ntiles;
     if (grid < 1) grid = 1;

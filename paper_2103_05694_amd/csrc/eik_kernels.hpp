@@ -325,21 +325,24 @@ __device__ __forceinline__ void st_flags(uint8_t* f, uint32_t v) {
 // OP selects the operator: 0 the exact monotone d-bar (the solver), 1 d-hat,
 // 2 d-tilde (two-dimensional precision ablation only; see apply_op).
 // COUNT adds the work classification (A.work_ref must then be set).
-// Registers are capped for three waves per SIMD (three 256-thread blocks per
-// compute unit): the largest tiles would otherwise drop to two.
-template <int TX, int TY, int TZ, int NT, int OP = 0, bool COUNT = false>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_solve(SolveArgs A) {
+// Registers are capped for three waves per SIMD with blocks of up to 256
+// threads (three blocks per compute unit) and four with larger blocks (two
+// 512-thread blocks or one 1024-thread block per compute unit).
+template <int TX, int TY, int TZ, int NT, int OP = 0, bool COUNT = false, bool PACK = false>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 256 ? 4 : 3))) k_solve(SolveArgs A) {
     using C = TileCfg<TX, TY, TZ, NT>;
     constexpr int NPT = C::NPT;
     static_assert(NPT == 1 || NPT == 2 || NPT == 4, "1, 2 or 4 points per thread");
     constexpr uint32_t kAllDirty = NPT == 4 ? 0x01010101u : (NPT == 2 ? 0x0101u : 0x01u);
     __shared__ double sT[C::NLDS];
-    __shared__ double sQ[C::NP];
-    // dirty flags; the NT bytes past the NP flags are per-thread sinks that
-    // let the marking below store without branching
+    __shared__ double sQ[PACK ? C::NP : 1];        // constants (PACK: any thread may relax a point)
+    __shared__ uint16_t sList[PACK ? C::NP : 1];   // PACK: the pass's dirty points, compacted
+    __shared__ int s_cnt[2];                       // PACK: list lengths
+    // dirty flags, two buffers (read in one pass, marked for the next); the
+    // NT bytes past the NP flags are per-thread sinks that let the marking
+    // store without branching
     __shared__ __align__(4) uint8_t sDirty[2][C::NP + NT];
-    __shared__ uint16_t sList[C::NP];
-    __shared__ int s_cnt[2];
+    __shared__ int s_more[3];  // per pass (mod 3): some wave marked a point
     __shared__ int s_tile;
     __shared__ int64_t s_bucket;
     __shared__ uint32_t s_state;
@@ -353,6 +356,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const unsigned long long lanes_below = (1ull << lane) - 1ull;
+    (void)lanes_below;
     const Sched& S = A.s;
     // per-workgroup statistics, flushed once at exit; the phase times use the
     // 100 MHz wall clock: [0] claim, [1] stage, [2] relax, [3] write + publish
@@ -435,6 +439,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
         if (tid == 0) {
             s_upd = 0u;
             s_pend = kInfBits;
+            s_more[1] = 0;
+            s_more[2] = 0;
             s_cnt[0] = 0;
             s_cnt[1] = 0;
         }
@@ -452,7 +458,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
         // valid upper bound.  Every load of the stage (field and t of the
         // thread's points, its halo cells) is issued before any is used, so the
         // stage costs one memory round trip rather than one per load.
-        double t_in[NPT];
+        double t_in[NPT];   // the values staged (what the run started from)
+        double t_own[NPT];  // the thread's points' current values
+        double q_own[NPT];  // and their constants (0: not relaxed)
         uint32_t live = 0;  // bit j: point j is in the grid and not a source
         {
             constexpr int NXF = 2 * TY * TZ, NYF = 2 * TX * TZ, NZF = C::D3 ? 2 * TX * TY : 0;
@@ -523,8 +531,10 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
                 }
                 if (q > 0.0) live |= 1u << j;
                 sT[C::lds(lx, ly, lz)] = tvj;
-                sQ[p] = q;
+                q_own[j] = q;
+                if constexpr (PACK) sQ[p] = q;
                 t_in[j] = tvj;
+                t_own[j] = tvj;
             }
 #pragma unroll
             for (int k = 0; k < HPT; ++k)
@@ -575,123 +585,253 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
         }
 
         // ---- relax until the tile is quiet --------------------------------
-        // Each pass first compacts the dirty points into a dense list (every
-        // thread reads its points' flags with one LDS access; per-point ballots
-        // give each point its place in the wave's segment, one LDS atomic per
-        // wave reserves the segment), then applies the operator to the list,
-        // so the waves run the operator only as many times as there are dirty
-        // points, not once per owned point.  A point whose value drops marks
-        // its in-tile neighbours above the new value dirty for the next pass;
-        // values read within a pass may already be newer (any order of
-        // monotone updates is valid).
+        // Two pass structures, same result (any order of monotone updates
+        // reaches the same fixed point): PACK compacts each pass's dirty points
+        // into a dense list first (fewest operator evaluations per wave: more
+        // throughput when the device is full of work, as in a batch of shots);
+        // otherwise each thread relaxes its own point (one barrier per pass:
+        // lower latency when the front holds few tiles, as in a single solve).
         int cb = 0;
         int passes = 0;
         double pend = inf64();
-        for (;;) {
-            {
-                uint8_t* df = sDirty[cb] + tid * NPT;
-                const uint32_t fl = ld_flags<NPT>(df);
-                if (fl) st_flags<NPT>(df, 0u);
-                uint32_t m = 0;
-#pragma unroll
-                for (int j = 0; j < NPT; ++j) m |= ((fl >> (8 * j)) & 1u) << j;
-                m &= live;
-                unsigned long long B[NPT];
-                int tot = 0;
-#pragma unroll
-                for (int j = 0; j < NPT; ++j) {
-                    B[j] = __ballot((m >> j) & 1u);
-                    tot += __popcll(B[j]);
-                }
-                if (tot) {
-                    int base = 0;
-                    if (lane == 0) base = atomicAdd(&s_cnt[cb], tot);
-                    base = __shfl(base, 0);
-#pragma unroll
+        if constexpr (PACK) {
+            // Each pass first compacts the dirty points into a dense list (every
+            // thread reads its points' flags with one LDS access; per-point ballots
+            // give each point its place in the wave's segment, one LDS atomic per
+            // wave reserves the segment), then applies the operator to the list,
+            // so the waves run the operator only as many times as there are dirty
+            // points, not once per owned point.  A point whose value drops marks
+            // its in-tile neighbours above the new value dirty for the next pass;
+            // values read within a pass may already be newer (any order of
+            // monotone updates is valid).
+            for (;;) {
+                {
+                    uint8_t* df = sDirty[cb] + tid * NPT;
+                    const uint32_t fl = ld_flags<NPT>(df);
+                    if (fl) st_flags<NPT>(df, 0u);
+                    uint32_t m = 0;
+    #pragma unroll
+                    for (int j = 0; j < NPT; ++j) m |= ((fl >> (8 * j)) & 1u) << j;
+                    m &= live;
+                    unsigned long long B[NPT];
+                    int tot = 0;
+    #pragma unroll
                     for (int j = 0; j < NPT; ++j) {
-                        if ((m >> j) & 1u) sList[base + __popcll(B[j] & lanes_below)] = (uint16_t)(tid + j * NT);
-                        base += __popcll(B[j]);
+                        B[j] = __ballot((m >> j) & 1u);
+                        tot += __popcll(B[j]);
                     }
+                    if (tot) {
+                        int base = 0;
+                        if (lane == 0) base = atomicAdd(&s_cnt[cb], tot);
+                        base = __shfl(base, 0);
+    #pragma unroll
+                        for (int j = 0; j < NPT; ++j) {
+                            if ((m >> j) & 1u) sList[base + __popcll(B[j] & lanes_below)] = (uint16_t)(tid + j * NT);
+                            base += __popcll(B[j]);
+                        }
+                    }
+                }
+                __syncthreads();
+                unsigned long long tg = 0;
+                if (tid == 0) tg = wall_clock64();
+                const int n = s_cnt[cb];
+                if (n == 0) break;
+                // the other counter was last read before the previous barrier and is
+                // next filled after the coming one
+                if (tid == 0) s_cnt[cb ^ 1] = 0;
+                for (int i = tid; i < n; i += NT) {
+                    const int p = sList[i];
+                    const double q = sQ[p];
+                    const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+                    const int L = C::lds(lx, ly, lz);
+                    const double tc = sT[L];
+                    const double ax = fmin(sT[L - 1], sT[L + 1]);
+                    const double ay = fmin(sT[L - C::SY], sT[L + C::SY]);
+                    const double az = C::D3 ? fmin(sT[L - C::SZ], sT[L + C::SZ]) : inf64();
+                    bool ch, mark;
+                    double r;
+                    if constexpr (OP == 0) {
+                        r = update<C::D3>(ax, ay, az, q, q * q, tc, ch);
+                        // held back: its bucket lies at or beyond the horizon (a
+                        // value whose bucket index overflows the range is settled
+                        // at once, so the requeue can never repeat forever)
+                        const double rb = r * S.inv_delta;
+                        if (S.horizon > 0 && ch && rb >= hz && rb < 1.0e15) {
+                            pend = fmin(pend, r);
+                            ch = false;
+                        }
+                        mark = ch;
+                    } else {
+                        // the ablation operators assign (their value may rise) and
+                        // re-activate on a drop, or on any change when tracking
+                        r = apply_op<OP>(ax, ay, az, q);
+                        ch = r != tc && r == r;
+                        mark = S.track ? ch : (ch && r < tc);
+                    }
+                    if constexpr (COUNT) {
+                        bool good = false;
+                        if (ch) {
+                            const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+                            good = r == A.work_ref[P.pt_off + ((int64_t)gz * P.ny + gy) * P.nx + gx];
+                        }
+                        w_eval += __popcll(__ballot(true));
+                        w_imp += __popcll(__ballot(ch));
+                        w_good += __popcll(__ballot(good));
+                    }
+                    if (ch) sT[L] = r;
+                    if (mark) {
+                        // with d-bar only neighbours above the new value can depend
+                        // on it (the operator is causal), so only they need another
+                        // look; the ablation operators mark every neighbour.  Six
+                        // unconditional stores, unwanted ones into this thread's
+                        // sink byte (no divergent branches).
+                        constexpr bool kAll = OP != 0;
+                        uint8_t* nd = sDirty[cb ^ 1];
+                        const int sink = C::NP + tid;
+                        nd[(lx > 0 && (kAll || sT[L - 1] > r)) ? didx<NT, NPT>(p - 1) : sink] = 1;
+                        nd[(lx < TX - 1 && (kAll || sT[L + 1] > r)) ? didx<NT, NPT>(p + 1) : sink] = 1;
+                        nd[(ly > 0 && (kAll || sT[L - C::SY] > r)) ? didx<NT, NPT>(p - TX) : sink] = 1;
+                        nd[(ly < TY - 1 && (kAll || sT[L + C::SY] > r)) ? didx<NT, NPT>(p + TX) : sink] = 1;
+                        if (C::D3) {
+                            nd[(lz > 0 && (kAll || sT[L - C::SZ] > r)) ? didx<NT, NPT>(p - TX * TY) : sink] = 1;
+                            nd[(lz < TZ - 1 && (kAll || sT[L + C::SZ] > r)) ? didx<NT, NPT>(p + TX * TY) : sink] = 1;
+                        }
+                    }
+                }
+                ++passes;
+                __syncthreads();
+                if (tid == 0) ph[5] += wall_clock64() - tg;
+                cb ^= 1;
+                if (OP != 0 && passes >= (1 << 16)) {  // an ablation operator may not settle
+                    if (tid == 0) set_flag(S, kFlagLimit);
+                    break;
+                }
+                if (passes > (1 << 20)) {
+                    if (tid == 0) set_flag(S, kFlagWatchdog);
+                    break;
                 }
             }
-            __syncthreads();
-            unsigned long long tg = 0;
-            if (tid == 0) tg = wall_clock64();
-            const int n = s_cnt[cb];
-            if (n == 0) break;
-            // the other counter was last read before the previous barrier and is
-            // next filled after the coming one
-            if (tid == 0) s_cnt[cb ^ 1] = 0;
-            for (int i = tid; i < n; i += NT) {
-                const int p = sList[i];
-                const double q = sQ[p];
-                const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
-                const int L = C::lds(lx, ly, lz);
-                const double tc = sT[L];
-                const double ax = fmin(sT[L - 1], sT[L + 1]);
-                const double ay = fmin(sT[L - C::SY], sT[L + C::SY]);
-                const double az = C::D3 ? fmin(sT[L - C::SZ], sT[L + C::SZ]) : inf64();
-                bool ch, mark;
-                double r;
-                if constexpr (OP == 0) {
-                    r = update<C::D3>(ax, ay, az, q, q * q, tc, ch);
-                    // held back: its bucket lies at or beyond the horizon (a
-                    // value whose bucket index overflows the range is settled
-                    // at once, so the requeue can never repeat forever)
-                    const double rb = r * S.inv_delta;
-                    if (S.horizon > 0 && ch && rb >= hz && rb < 1.0e15) {
-                        pend = fmin(pend, r);
-                        ch = false;
-                    }
-                    mark = ch;
-                } else {
-                    // the ablation operators assign (their value may rise) and
-                    // re-activate on a drop, or on any change when tracking
-                    r = apply_op<OP>(ax, ay, az, q);
-                    ch = r != tc && r == r;
-                    mark = S.track ? ch : (ch && r < tc);
-                }
-                if constexpr (COUNT) {
-                    bool good = false;
-                    if (ch) {
-                        const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
-                        good = r == A.work_ref[P.pt_off + ((int64_t)gz * P.ny + gy) * P.nx + gx];
-                    }
-                    w_eval += __popcll(__ballot(true));
-                    w_imp += __popcll(__ballot(ch));
-                    w_good += __popcll(__ballot(good));
-                }
-                if (ch) sT[L] = r;
-                if (mark) {
-                    // with d-bar only neighbours above the new value can depend
-                    // on it (the operator is causal), so only they need another
-                    // look; the ablation operators mark every neighbour.  Six
-                    // unconditional stores, unwanted ones into this thread's
-                    // sink byte (no divergent branches).
-                    constexpr bool kAll = OP != 0;
-                    uint8_t* nd = sDirty[cb ^ 1];
-                    const int sink = C::NP + tid;
-                    nd[(lx > 0 && (kAll || sT[L - 1] > r)) ? didx<NT, NPT>(p - 1) : sink] = 1;
-                    nd[(lx < TX - 1 && (kAll || sT[L + 1] > r)) ? didx<NT, NPT>(p + 1) : sink] = 1;
-                    nd[(ly > 0 && (kAll || sT[L - C::SY] > r)) ? didx<NT, NPT>(p - TX) : sink] = 1;
-                    nd[(ly < TY - 1 && (kAll || sT[L + C::SY] > r)) ? didx<NT, NPT>(p + TX) : sink] = 1;
-                    if (C::D3) {
-                        nd[(lz > 0 && (kAll || sT[L - C::SZ] > r)) ? didx<NT, NPT>(p - TX * TY) : sink] = 1;
-                        nd[(lz < TZ - 1 && (kAll || sT[L + C::SZ] > r)) ? didx<NT, NPT>(p + TX * TY) : sink] = 1;
-                    }
-                }
+        } else {
+            // Every thread relaxes its own points (p = tid + j * NT), whose time
+            // and constant it keeps in registers; only the neighbours come from
+            // LDS.  A pass evaluates each dirty point once and marks the in-tile
+            // neighbours that may now improve in the other flag buffer, so the
+            // pass's reads (buffer cb) and marks (buffer cb ^ 1) never touch the
+            // same bytes, and ONE barrier per pass suffices: it orders this pass's
+            // marks before the next pass's reads.  A flag byte of slot s_more says
+            // whether any wave marked anything; if none did, every flag is clear
+            // and the tile is quiet.  Values read within a pass may already be
+            // newer (any order of monotone updates is valid, Theorem 1).
+            uint32_t dirty = 0;  // bit j: point j is to be evaluated in this pass
+            {
+                const uint32_t fl = ld_flags<NPT>(sDirty[0] + tid * NPT);
+    #pragma unroll
+                for (int j = 0; j < NPT; ++j) dirty |= ((fl >> (8 * j)) & 1u) << j;
+                st_flags<NPT>(sDirty[0] + tid * NPT, 0u);
+                dirty &= live;
             }
-            ++passes;
-            __syncthreads();
-            if (tid == 0) ph[5] += wall_clock64() - tg;
-            cb ^= 1;
-            if (OP != 0 && passes >= (1 << 16)) {  // an ablation operator may not settle
-                if (tid == 0) set_flag(S, kFlagLimit);
-                break;
-            }
-            if (passes > (1 << 20)) {
-                if (tid == 0) set_flag(S, kFlagWatchdog);
-                break;
+            for (;;) {
+                unsigned long long tg = 0;
+                if (tid == 0) {
+                    tg = wall_clock64();
+                    s_more[(passes + 1) % 3] = 0;  // written next pass; last read two barriers ago
+                }
+                bool marked = false;
+                uint8_t* nd = sDirty[cb ^ 1];
+                const int sink = C::NP + tid;
+    #pragma unroll
+                for (int j = 0; j < NPT; ++j) {
+                    if (!__ballot((dirty >> j) & 1u)) continue;
+                    bool ch = false, good = false;  // for the work classification
+                    if ((dirty >> j) & 1u) {
+                        const int p = tid + j * NT;
+                        const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+                        const int L = C::lds(lx, ly, lz);
+                        const double q = q_own[j];
+                        const double tc = t_own[j];
+                        const double nxm = sT[L - 1], nxp = sT[L + 1], nym = sT[L - C::SY], nyp = sT[L + C::SY];
+                        const double nzm = C::D3 ? sT[L - C::SZ] : inf64(), nzp = C::D3 ? sT[L + C::SZ] : inf64();
+                        const double ax = fmin(nxm, nxp), ay = fmin(nym, nyp), az = fmin(nzm, nzp);
+                        bool mark;
+                        double r;
+                        if constexpr (OP == 0) {
+                            r = update<C::D3>(ax, ay, az, q, q * q, tc, ch);
+                            // held back: its bucket lies at or beyond the horizon (a
+                            // value whose bucket index overflows the range is settled
+                            // at once, so the requeue can never repeat forever)
+                            const double rb = r * S.inv_delta;
+                            if (S.horizon > 0 && ch && rb >= hz && rb < 1.0e15) {
+                                pend = fmin(pend, r);
+                                ch = false;
+                            }
+                            mark = ch;
+                        } else {
+                            // the ablation operators assign (their value may rise) and
+                            // re-activate on a drop, or on any change when tracking
+                            r = apply_op<OP>(ax, ay, az, q);
+                            ch = r != tc && r == r;
+                            mark = S.track ? ch : (ch && r < tc);
+                        }
+                        if constexpr (COUNT) {
+                            if (ch) {
+                                const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+                                good = r == A.work_ref[P.pt_off + ((int64_t)gz * P.ny + gy) * P.nx + gx];
+                            }
+                        }
+                        if (ch) {
+                            t_own[j] = r;
+                            sT[L] = r;
+                        }
+                        if (mark) {
+                            // with d-bar only neighbours above the new value can depend
+                            // on it (the operator is causal); the values loaded above
+                            // can only have dropped since, so a neighbour loaded at or
+                            // below r needs no look.  The ablation operators mark every
+                            // neighbour.  Six unconditional stores, unwanted ones into
+                            // this thread's sink byte (no divergent branches).
+                            constexpr bool kAll = OP != 0;
+                            nd[(lx > 0 && (kAll || nxm > r)) ? didx<NT, NPT>(p - 1) : sink] = 1;
+                            nd[(lx < TX - 1 && (kAll || nxp > r)) ? didx<NT, NPT>(p + 1) : sink] = 1;
+                            nd[(ly > 0 && (kAll || nym > r)) ? didx<NT, NPT>(p - TX) : sink] = 1;
+                            nd[(ly < TY - 1 && (kAll || nyp > r)) ? didx<NT, NPT>(p + TX) : sink] = 1;
+                            if (C::D3) {
+                                nd[(lz > 0 && (kAll || nzm > r)) ? didx<NT, NPT>(p - TX * TY) : sink] = 1;
+                                nd[(lz < TZ - 1 && (kAll || nzp > r)) ? didx<NT, NPT>(p + TX * TY) : sink] = 1;
+                            }
+                            marked = true;
+                        }
+                    }
+                    if constexpr (COUNT) {
+                        // every lane of the wave takes part, so lane 0's totals are the wave's
+                        w_eval += __popcll(__ballot((dirty >> j) & 1u));
+                        w_imp += __popcll(__ballot(ch));
+                        w_good += __popcll(__ballot(good));
+                    }
+                }
+                if (__ballot(marked) && lane == 0) s_more[passes % 3] = 1;
+                __syncthreads();
+                const bool more = s_more[passes % 3] != 0;
+                ++passes;
+                if (tid == 0) ph[5] += wall_clock64() - tg;
+                if (!more) break;
+                cb ^= 1;
+                {
+                    uint8_t* df = sDirty[cb] + tid * NPT;
+                    const uint32_t fl = ld_flags<NPT>(df);
+                    dirty = 0;
+    #pragma unroll
+                    for (int j = 0; j < NPT; ++j) dirty |= ((fl >> (8 * j)) & 1u) << j;
+                    if (fl) st_flags<NPT>(df, 0u);
+                    dirty &= live;
+                }
+                if (OP != 0 && passes >= (1 << 16)) {  // an ablation operator may not settle
+                    if (tid == 0) set_flag(S, kFlagLimit);
+                    break;
+                }
+                if (passes > (1 << 20)) {
+                    if (tid == 0) set_flag(S, kFlagWatchdog);
+                    break;
+                }
             }
         }
 

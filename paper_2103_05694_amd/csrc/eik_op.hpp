@@ -153,13 +153,13 @@ __device__ __forceinline__ double update(double x, double y, double z, double q,
         a1 = fmax(x, y);
         a2 = inf64();
     }
-    if (!(a0 < tcur)) return tcur;                 // result > a0 >= tcur: nothing to do
     const uint64_t tcb = as_u64(tcur);
-    // most evaluations in a relaxation do not improve the point: one predicate
-    // rejects them before the guess is computed
-    if (!reaches<D3>(as_f64(tcb - 1), a0, a1, a2, c)) return tcur;
+    // Whether the point can improve at all: its value would be > a0 >= tcur,
+    // or S(prev(tcur)) < c.  Both tests and the guess below are independent,
+    // so they are computed side by side (the improving case, which dominates
+    // a relaxation, then waits for one chain instead of two).
+    const bool can = (a0 < tcur) & reaches<D3>(as_f64(tcb - 1), a0, a1, a2, c);
     const uint64_t A0 = as_u64(a0);
-    // reaches(tcb - 1) is false whenever tcb - 1 <= A0, so here tcb - 1 > A0
     uint64_t G = as_u64(guess<D3>(a0, a1, a2, q, c));
     if (!(G >= A0 + 2)) G = A0 + 2;                // also catches a NaN pattern
     if (G > tcb - 1) G = tcb - 1;
@@ -185,6 +185,8 @@ __device__ __forceinline__ double update(double x, double y, double z, double q,
     int cnt = 0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) cnt += sm[k] >= c ? 1 : 0;
+    if (!can) return tcur;
+    // reaches(tcb - 1) is false whenever tcb - 1 <= A0, so here tcb - 1 > A0
     changed = true;
     if (cnt == 0 || cnt == 3) return search_slow(a0, a1, a2, c, A0, G, tcb);
     return as_f64(G + 2 - (uint64_t)cnt);

@@ -80,7 +80,7 @@ def test_solve_rejects_bad_counts_and_options(L):
     o = eik_opts()
     o.tile[0], o.tile[1], o.tile[2] = 32, 32, 1   # a 2D tile for a 3D grid
     assert L.eik_solve(ctypes.byref(g), dummy, 1, dummy, None, dummy, None, ctypes.byref(o), None) == -6
-    for bad in (2, 32, 1 << 31):                   # no such flags
+    for bad in (2, 64, 1 << 31):                   # no such flags
         o = eik_opts()
         o.flags = bad
         assert L.eik_solve(ctypes.byref(g), dummy, 1, dummy, None, dummy, None, ctypes.byref(o), None) == -1

@@ -124,8 +124,9 @@ def test_work_classification(gpu, O, delta, horizon):
     f = torch.from_numpy(p.field).cuda()
     src = torch.as_tensor(p.src)
     ref = gpu.solve(f, p.h, src, delta=0.02, tile=(16, 8, 8))
-    for tile in ((16, 8, 8), (8, 8, 8), (8, 4, 4)):
-        t = gpu.solve(f, p.h, src, delta=delta, horizon=horizon, tile=tile, work_ref=ref, check_status=False)
+    for tile, pk in (((16, 8, 8), False), ((8, 8, 8), True), ((8, 4, 4), False), ((8, 8, 8), False)):
+        t = gpu.solve(f, p.h, src, delta=delta, horizon=horizon, tile=tile, work_ref=ref, packed=pk,
+                      check_status=False)
         st = gpu.status()
         assert torch.equal(t, ref)
         assert st.final_updates == p.npts - len(p.src)

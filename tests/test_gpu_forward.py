@@ -89,9 +89,10 @@ def test_ragged_and_degenerate_shapes(gpu, O, case):
     ref = O.fmm(f, h, src, t0)
     tiles = TILES_2D if f.shape[0] == 1 else TILES_3D
     for tile in tiles:
-        for delta, la, hz in ((0.0, 0, 0), (0.5, 0, 0), (0.25, 3, 0), (0.25, 0, 1), (0.5, 2, 2)):
-            t = gpu_solve(gpu, f, h, src, t0, tile=tile, delta=delta, lookahead=la, horizon=hz)
-            assert_bitwise(t, ref, f"{name} tile {tile} delta {delta} lookahead {la} horizon {hz}")
+        for delta, la, hz, pk in ((0.0, 0, 0, False), (0.5, 0, 0, True), (0.25, 3, 0, False), (0.25, 0, 1, True),
+                                  (0.5, 2, 2, False), (0.0, 1, 0, True)):
+            t = gpu_solve(gpu, f, h, src, t0, tile=tile, delta=delta, lookahead=la, horizon=hz, packed=pk)
+            assert_bitwise(t, ref, f"{name} tile {tile} delta {delta} lookahead {la} horizon {hz} packed {pk}")
 
 
 def test_slowness_field(gpu, O):
@@ -107,18 +108,19 @@ def test_slowness_field(gpu, O):
 def test_layered_3d_scaled(gpu, O, layered_small, tile):
     p = layered_small
     ref = O.fmm(p.field, p.h, p.src)
-    for delta, la in ((0.0, 0), (0.02, 0), (0.02, 2), (0.2, 1), (0.005, 8)):
-        t = gpu_solve(gpu, p.field, p.h, p.src, tile=tile, delta=delta, lookahead=la)
-        assert_bitwise(t, ref, f"layered tile {tile} delta {delta} lookahead {la}")
+    for delta, la, pk in ((0.0, 0, False), (0.02, 0, False), (0.02, 0, True), (0.02, 2, True), (0.2, 1, False),
+                          (0.005, 8, True)):
+        t = gpu_solve(gpu, p.field, p.h, p.src, tile=tile, delta=delta, lookahead=la, packed=pk)
+        assert_bitwise(t, ref, f"layered tile {tile} delta {delta} lookahead {la} packed {pk}")
 
 
 @pytest.mark.parametrize("tile", TILES_2D)
 def test_blocky_2d_scaled(gpu, O, tile):
     p = W.blocky_2d(n=512, nsrc=16, seed=3, block=16)
     ref = O.fmm(p.field, p.h, p.src)
-    for delta, la in ((0.0, 0), (4.0, 0), (4.0, 4), (64.0, 1)):
-        t = gpu_solve(gpu, p.field, p.h, p.src, tile=tile, delta=delta, lookahead=la)
-        assert_bitwise(t, ref, f"blocky tile {tile} delta {delta} lookahead {la}")
+    for delta, la, pk in ((0.0, 0, False), (4.0, 0, True), (4.0, 4, False), (64.0, 1, True)):
+        t = gpu_solve(gpu, p.field, p.h, p.src, tile=tile, delta=delta, lookahead=la, packed=pk)
+        assert_bitwise(t, ref, f"blocky tile {tile} delta {delta} lookahead {la} packed {pk}")
 
 
 def test_run_to_run_determinism(gpu, O, layered_small):
@@ -140,7 +142,7 @@ def bench_config(shape, kind="speed"):
     if not cfg:
         return {}
     return dict(tile=tuple(cfg["tile"]), delta=cfg["delta"], grid_blocks=int(cfg.get("grid_blocks", 0)),
-                horizon=int(cfg.get("horizon", 0)))
+                horizon=int(cfg.get("horizon", 0)), packed=bool(cfg.get("packed", False)))
 
 
 def test_blocky_full_4096(gpu, O):
@@ -171,6 +173,14 @@ def test_layered_full_size_fixed_point(gpu, O):
     t1 = gpu.solve(f, p.h, src, **cfg).cpu().numpy()
     n, worst = O.residual(t1, p.field, p.h, p.src)
     assert n == 0 and worst == 0.0
+    # bit for bit the oracle's solution (its stored hash, which the benchmark checks too)
+    import hashlib
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "layered_512x512x256_seed2.json")) as fh:
+        golden = json.load(fh)
+    assert p.sha256() == golden["input_sha256_16"]
+    assert hashlib.sha256(np.ascontiguousarray(t1, dtype="<f8").tobytes()).hexdigest() == golden["times_sha256"]
     assert t1.reshape(-1)[p.src[0]] == 0.0
     assert np.all(np.isfinite(t1))
     t2 = gpu.solve(f, p.h, src, **cfg).cpu().numpy()
@@ -314,9 +324,10 @@ def test_autotune_candidates_agree(gpu, layered_small):
     p = W.layered_3d(40, 36, 28, h=10.0, seed=4, sigma=3.0)
     f = torch.from_numpy(p.field).cuda()
     e = autotune.tune(f, p.h, torch.as_tensor(p.src), tiles=[(8, 8, 8), (16, 8, 8)],
-                      delta_factors=(0.0, 1.0, 4.0), grid_blocks=(0, 64), horizons=(0, 1), reps=1,
-                      save=False, log=lambda s: None)
-    grid = 2 * (1 * 2 + 2 * 2 * 2)
+                      delta_factors=(0.0, 1.0, 4.0), grid_blocks=(0, 64), horizons=(0, 1), packed=(False, True),
+                      reps=1, save=False, log=lambda s: None)
+    # tiles x (bucket width 0: grid sizes + other widths: horizons x grid sizes) x pass structures
+    grid = 2 * (1 * 2 + 2 * 2 * 2) * 2
     # the best bucket width is refined at 2^(+-1/2) of its factor unless it was 0
     extra = e["candidates"][grid:]
     assert len(e["candidates"]) in (grid, grid + 2)

@@ -35,7 +35,7 @@ def tuned(shape, kind, default_tile, default_delta, nshots=32):
     if not cfg:
         return dict(tile=default_tile, delta=default_delta, grid_blocks=0, horizon=0)
     out = dict(tile=tuple(cfg["tile"]), delta=cfg["delta"], grid_blocks=int(cfg.get("grid_blocks", 0)),
-               horizon=int(cfg.get("horizon", 0)))
+               horizon=int(cfg.get("horizon", 0)), packed=bool(cfg.get("packed", False)))
     if "adj_delta" in cfg:
         out.update(adj_delta=cfg["adj_delta"], adj_tile=tuple(cfg["adj_tile"]),
                    adj_grid_blocks=int(cfg.get("adj_grid_blocks", 0)))
@@ -102,7 +102,7 @@ def test_uneven_full_batch(gpu, O):
     t = torch.empty(b.npts, dtype=torch.float64, device="cuda")
     par = torch.empty(b.npts, dtype=torch.uint8, device="cuda")
     gpu.solve_packed(b, t, par, cfg["delta"], cfg["tile"], grid_blocks=cfg["grid_blocks"],
-                     horizon=cfg["horizon"])
+                     horizon=cfg["horizon"], packed=cfg["packed"])
     gpu.status()
     rng = np.random.default_rng(12)
     small = [i for i, p in enumerate(shots) if p.npts == 128 ** 3][:2]
