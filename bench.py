@@ -568,7 +568,8 @@ def main() -> int:
     args.adj_cfg = {}
     if tcfg and "adj_delta" in tcfg:
         args.adj_cfg = dict(adj_delta=tcfg["adj_delta"], adj_tile=tuple(tcfg["adj_tile"]),
-                            adj_grid_blocks=int(tcfg.get("adj_grid_blocks", 0)))
+                            adj_grid_blocks=int(tcfg.get("adj_grid_blocks", 0)),
+                            adj_packed=bool(tcfg.get("adj_packed", False)))
     # the per-shot baseline runs with the single-shot tuning (its best), not the batch's
     scfg = autotune.lookup((128, 256, 256), "slowness")
     args.shot_cfg = (dict(delta=scfg["delta"], tile=tuple(scfg["tile"]), grid_blocks=int(scfg.get("grid_blocks", 0)),

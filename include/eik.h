@@ -66,14 +66,15 @@ extern "C" {
 #define EIK_FLAG_TRACK_CHANGE 8u  /* eik_opts.flags, ablation operators only: re-activate the
                                      neighbours when a value changes, not only when it decreases
                                      (the precision section's change tracking) */
-#define EIK_FLAG_PACKED 32u       /* eik_opts.flags, forward solves with EIK_OP_DBAR: each
-                                     relaxation pass first compacts the tile's dirty points
-                                     into a dense list (256-thread workgroups); without it
-                                     every thread relaxes its own point (one thread per
-                                     point, up to 1024).  Same result either way; the packed
-                                     form does fewer operator evaluations per wave and wins
-                                     when the device is full of work (batches of shots), the
-                                     default has lower latency per pass (single solves). */
+#define EIK_FLAG_PACKED 32u       /* eik_opts.flags, forward solves with EIK_OP_DBAR and
+                                     adjoints: each relaxation (adjoint: readiness) pass
+                                     first compacts the tile's dirty points into a dense
+                                     list (256-thread workgroups); without it every thread
+                                     handles its own point (one thread per point, up to
+                                     1024).  Same result either way; the packed form does
+                                     fewer evaluations per wave and can win when the device
+                                     is full of work (batches of shots), the default has
+                                     lower latency per pass (single solves). */
 #define EIK_FLAG_WARM_START 16u   /* eik_opts.flags, forward solves with EIK_OP_DBAR: resume from
                                      the times already in t_out instead of +inf.  They must be
                                      an upper bound of the solution at every point (>= +0, not

@@ -234,7 +234,7 @@ def adjoint(field: torch.Tensor, h: float, t: torch.Tensor, parents: torch.Tenso
             tile: Optional[Sequence[int]] = None, grid_blocks: int = 0,
             out: Optional[torch.Tensor] = None, mu_out: Optional[torch.Tensor] = None,
             check_status: bool = True, stream=None, time_kernels: bool = False,
-            lookahead: int = 0) -> torch.Tensor:
+            lookahead: int = 0, packed: bool = False) -> torch.Tensor:
     """d loss / d slowness from d loss / d t through the recorded upwind parents."""
     for a in (field, t, dL_dt):
         _check_field(a)
@@ -254,7 +254,7 @@ def adjoint(field: torch.Tensor, h: float, t: torch.Tensor, parents: torch.Tenso
     L = _lib.load()
     g = _grid_of(field.shape, h, kind)
     grad = out if out is not None else torch.empty_like(field)
-    o = make_opts(delta, tile, grid_blocks, 0, time_kernels, lookahead)
+    o = make_opts(delta, tile, grid_blocks, 0, time_kernels, lookahead, packed=packed)
     rc = L.eik_adjoint(ctypes.byref(g), field.data_ptr(), t.data_ptr(), parents.data_ptr(),
                        dL_dt.data_ptr(), grad.data_ptr(),
                        mu_out.data_ptr() if mu_out is not None else None, ctypes.byref(o),
@@ -375,7 +375,7 @@ def solve_packed(b: Batch, t_packed: torch.Tensor, par_packed: Optional[torch.Te
 def adjoint_packed(b: Batch, t_packed: torch.Tensor, par_packed: torch.Tensor, g_packed: torch.Tensor,
                    grad_packed: torch.Tensor, mu_packed: Optional[torch.Tensor] = None, delta: float = 0.0,
                    tile=None, grid_blocks: int = 0, stream=None, time_kernels: bool = False,
-                   lookahead: int = 0) -> None:
+                   lookahead: int = 0, packed: bool = False) -> None:
     """Enqueue one batched adjoint launch (no host synchronisation)."""
     dev = b.field.device
     _check_buf(t_packed, "t_packed", torch.float64, b.npts, dev)
@@ -385,7 +385,7 @@ def adjoint_packed(b: Batch, t_packed: torch.Tensor, par_packed: torch.Tensor, g
     if mu_packed is not None:
         _check_buf(mu_packed, "mu_packed", torch.float64, b.npts, dev)
     L = _lib.load()
-    o = make_opts(delta, tile, grid_blocks, 0, time_kernels, lookahead)
+    o = make_opts(delta, tile, grid_blocks, 0, time_kernels, lookahead, packed=packed)
     check(L.eik_adjoint_batched(b.nprob, b.grids, b.offsets, b.field.data_ptr(), t_packed.data_ptr(),
                                 par_packed.data_ptr(), g_packed.data_ptr(), grad_packed.data_ptr(),
                                 mu_packed.data_ptr() if mu_packed is not None else None,

@@ -185,35 +185,37 @@ def tune_batch(fields: Sequence[torch.Tensor], h: float, sources, receivers, kin
     adj: List[dict] = []
     gref = None
 
-    def run_adj(tile, fac, gb):
+    def run_adj(tile, fac, gb, pk):
         nonlocal gref
         delta = fac * qmed * min(tile[:nd])
-        fn = lambda: api.adjoint_packed(b, t, par, g, grad, delta=delta, tile=tile, grid_blocks=gb)
+        fn = lambda: api.adjoint_packed(b, t, par, g, grad, delta=delta, tile=tile, grid_blocks=gb, packed=pk)
         fn()
         api.status()
         if gref is None:
             gref = grad.clone()
         elif not torch.equal(gref, grad):
-            raise RuntimeError(f"batch adjoint tile={tile} delta={delta} grid={gb} changed the result")
+            raise RuntimeError(f"batch adjoint tile={tile} delta={delta} grid={gb} packed={pk} changed the result")
         sec = _time(fn, reps)
         api.status()
-        adj.append({"tile": list(tile), "delta": delta, "delta_factor": fac, "grid_blocks": gb,
+        adj.append({"tile": list(tile), "delta": delta, "delta_factor": fac, "grid_blocks": gb, "packed": pk,
                     "ms": sec * 1e3})
-        log(f"  batch adjoint tile {tile} delta {delta:.4g} grid {gb}: {sec * 1e3:.2f} ms")
+        log(f"  batch adjoint tile {tile} delta {delta:.4g} grid {gb} packed {pk}: {sec * 1e3:.2f} ms")
 
     for tile in tiles:
         for fac in adj_delta_factors:
             for gb in grid_blocks:
-                run_adj(tile, fac, gb)
+                for pk in packed:
+                    run_adj(tile, fac, gb, pk)
     ba = min(adj, key=lambda r: r["ms"])
     if ba["delta_factor"] > 0:
         for step in (2.0 ** -0.5, 2.0 ** 0.5):
-            run_adj(tuple(ba["tile"]), ba["delta_factor"] * step, ba["grid_blocks"])
+            run_adj(tuple(ba["tile"]), ba["delta_factor"] * step, ba["grid_blocks"], ba["packed"])
     bf = min(fwd, key=lambda r: r["ms"])
     ba = min(adj, key=lambda r: r["ms"])
     entry = {"tile": bf["tile"], "delta": bf["delta"], "grid_blocks": bf["grid_blocks"], "horizon": 0,
              "packed": bf["packed"],
              "adj_tile": ba["tile"], "adj_delta": ba["delta"], "adj_grid_blocks": ba["grid_blocks"],
+             "adj_packed": ba["packed"],
              "ms": bf["ms"] + ba["ms"], "forward_ms": bf["ms"], "adjoint_ms": ba["ms"], "qmed": qmed,
              "forward_candidates": fwd, "adjoint_candidates": adj}
     if save:

@@ -26,13 +26,15 @@ class ShotBatch:
                  t_obs: Optional[Sequence[torch.Tensor]] = None, kind: str = "slowness",
                  delta: float = 0.0, tile=None, stream: Optional[torch.cuda.Stream] = None,
                  grid_blocks: int = 0, horizon: int = 0, adj_delta: Optional[float] = None,
-                 adj_tile=None, adj_grid_blocks: Optional[int] = None, packed: bool = False):
+                 adj_tile=None, adj_grid_blocks: Optional[int] = None, packed: bool = False,
+                 adj_packed: bool = False):
         self.kind = kind
         self.delta = delta
         self.tile = tile
         self.grid_blocks = grid_blocks
         self.horizon = horizon
         self.packed = packed
+        self.adj_packed = adj_packed
         # the adjoint is readiness-driven and may prefer other launch parameters
         self.adj_delta = delta if adj_delta is None else adj_delta
         self.adj_tile = tile if adj_tile is None else adj_tile
@@ -68,7 +70,7 @@ class ShotBatch:
         self.g.zero_()
         self.g.index_copy_(0, self.rec, self.t.index_select(0, self.rec) - self.t_obs)
         api.adjoint_packed(self.b, self.t, self.par, self.g, self.grad, self.mu, self.adj_delta, self.adj_tile,
-                           grid_blocks=self.adj_grid_blocks, stream=self.stream)
+                           grid_blocks=self.adj_grid_blocks, stream=self.stream, packed=self.adj_packed)
 
     def step(self) -> None:
         """Enqueue one batched forward + adjoint (eager launches).  The batch's
@@ -111,7 +113,8 @@ class ShotBatch:
     def plain_step(self, t_out: torch.Tensor, grad_out: torch.Tensor, delta: Optional[float] = None,
                    tile=None, grid_blocks: Optional[int] = None, horizon: Optional[int] = None,
                    adj_delta: Optional[float] = None, adj_tile=None,
-                   adj_grid_blocks: Optional[int] = None, packed: Optional[bool] = None) -> None:
+                   adj_grid_blocks: Optional[int] = None, packed: Optional[bool] = None,
+                   adj_packed: Optional[bool] = None) -> None:
         """Per-shot eik_solve + eik_adjoint launches on the current stream,
         writing into packed outputs.  The launch parameters default to the
         batch's; a single shot may prefer others (it has far less parallel
@@ -121,6 +124,7 @@ class ShotBatch:
         grid_blocks = self.grid_blocks if grid_blocks is None else grid_blocks
         horizon = self.horizon if horizon is None else horizon
         packed = self.packed if packed is None else packed
+        adj_packed = self.adj_packed if adj_packed is None else adj_packed
         adj_delta = self.adj_delta if adj_delta is None else adj_delta
         adj_tile = self.adj_tile if adj_tile is None else adj_tile
         adj_grid_blocks = self.adj_grid_blocks if adj_grid_blocks is None else adj_grid_blocks
@@ -138,7 +142,8 @@ class ShotBatch:
             gvv[i].view(-1).index_copy_(0, r, t.view(-1).index_select(0, r) - self.t_obs[rec_off:rec_off + nr])
             rec_off += nr
             api.adjoint(self.fields[i], self.hs[i], t, par, gvv[i], kind=self.kind, delta=adj_delta,
-                        tile=adj_tile, grid_blocks=adj_grid_blocks, out=gv[i], check_status=False)
+                        tile=adj_tile, grid_blocks=adj_grid_blocks, out=gv[i], packed=adj_packed,
+                        check_status=False)
 
     def shot_views(self, packed: torch.Tensor) -> List[torch.Tensor]:
         return self.b.views(packed)

@@ -98,20 +98,22 @@ struct AdjArgs {
     Sched s;
 };
 
-// Registers are capped for three waves per SIMD: with the staging loads all in
-// flight at once the largest tiles would otherwise drop to two, which costs
-// more than the few spills the cap brings.
-template <int TX, int TY, int TZ, int NT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_adjoint(AdjArgs A) {
+// Registers are capped for three waves per SIMD with blocks of up to 256
+// threads (with the staging loads all in flight at once the largest tiles would
+// otherwise drop to two) and four with larger blocks (the direct form: one
+// thread per point).
+template <int TX, int TY, int TZ, int NT, bool PACK = false>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 256 ? 4 : 3))) k_adjoint(AdjArgs A) {
     using C = TileCfg<TX, TY, TZ, NT>;
     constexpr int NPT = C::NPT;
     __shared__ double sT[C::NLDS];
     __shared__ double sM[C::NLDS];
     __shared__ uint8_t sP[C::NLDS];
     __shared__ double sG[C::NP];               // dL/dt of the tile's points
-    __shared__ uint16_t sList[C::NP];          // the pass's dirty points, compacted
+    __shared__ uint16_t sList[PACK ? C::NP : 1];  // PACK: the pass's dirty points, compacted
     __shared__ __align__(4) uint8_t sDirty[2][C::NP];  // layout of didx()
     __shared__ int s_cnt[2];
+    __shared__ int s_more[3];  // direct form, per pass (mod 3): some point completed with an in-tile parent
     __shared__ int s_tile;
     __shared__ int64_t s_bucket;
     __shared__ uint32_t s_state;
@@ -124,6 +126,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const unsigned long long lanes_below = (1ull << lane) - 1ull;
+    (void)lanes_below;
     const Sched& S = A.s;
     const double tref = as_f64(*A.tref_bits);
     constexpr int PSTEP[3] = {1, TX, TX * TY};
@@ -191,6 +194,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
             s_done = 0u;
             s_cnt[0] = 0;
             s_cnt[1] = 0;
+            s_more[1] = 0;
+            s_more[2] = 0;
         }
 
         // stage own points and the halo: every load goes out before any is used
@@ -314,119 +319,231 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) k_
         }
 
         // Evaluate points whose children are all done, until no point is left
-        // to look at.  As in the forward solver, each pass first compacts the
-        // points marked dirty into a list (per-point ballots place them, one
-        // LDS atomic per wave reserves the wave's segment), so a lane evaluates
-        // at most one point per round instead of walking all its own points.
-        // A point that becomes done marks its in-tile parents for the next
-        // pass; a point that is not ready yet is marked again by the child
-        // that completes it.
+        // to look at (two pass structures with the same result, as in the
+        // forward solver: PACK compacts the dirty points first).
         int cb = 0;
         int passes = 0;
-        for (;;) {
-            {
-                uint8_t* df = sDirty[cb] + tid * NPT;
-                const uint32_t fl = ld_flags<NPT>(df);
-                if (fl) st_flags<NPT>(df, 0u);
-                uint32_t m = 0;
-#pragma unroll
-                for (int j = 0; j < NPT; ++j) m |= ((fl >> (8 * j)) & 1u) << j;
-                m &= live;
-                unsigned long long B[NPT];
-                int tot = 0;
-#pragma unroll
-                for (int j = 0; j < NPT; ++j) {
-                    B[j] = __ballot((m >> j) & 1u);
-                    tot += __popcll(B[j]);
-                }
-                if (tot) {
-                    int base = 0;
-                    if (lane == 0) base = atomicAdd(&s_cnt[cb], tot);
-                    base = __shfl(base, 0);
-#pragma unroll
+        if constexpr (PACK) {
+            // Evaluate points whose children are all done, until no point is left
+            // to look at.  As in the forward solver, each pass first compacts the
+            // points marked dirty into a list (per-point ballots place them, one
+            // LDS atomic per wave reserves the wave's segment), so a lane evaluates
+            // at most one point per round instead of walking all its own points.
+            // A point that becomes done marks its in-tile parents for the next
+            // pass; a point that is not ready yet is marked again by the child
+            // that completes it.
+            for (;;) {
+                {
+                    uint8_t* df = sDirty[cb] + tid * NPT;
+                    const uint32_t fl = ld_flags<NPT>(df);
+                    if (fl) st_flags<NPT>(df, 0u);
+                    uint32_t m = 0;
+    #pragma unroll
+                    for (int j = 0; j < NPT; ++j) m |= ((fl >> (8 * j)) & 1u) << j;
+                    m &= live;
+                    unsigned long long B[NPT];
+                    int tot = 0;
+    #pragma unroll
                     for (int j = 0; j < NPT; ++j) {
-                        if ((m >> j) & 1u) sList[base + __popcll(B[j] & lanes_below)] = (uint16_t)(tid + j * NT);
-                        base += __popcll(B[j]);
+                        B[j] = __ballot((m >> j) & 1u);
+                        tot += __popcll(B[j]);
                     }
-                }
-            }
-            __syncthreads();
-            const int n = s_cnt[cb];
-            if (n == 0) break;
-            // the other counter was last read before the previous barrier and is
-            // next filled after the coming one
-            if (tid == 0) s_cnt[cb ^ 1] = 0;
-            for (int i = tid; i < n; i += NT) {
-                const int p = sList[i];
-                const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
-                const int L = C::lds(lx, ly, lz);
-                // every LDS read of the point and its neighbours goes out at once
-                const uint8_t pn = sP[L];
-                const double mself = sM[L];
-                const double tn = sT[L];
-                uint8_t pm[2 * NAX];
-                double mm[2 * NAX], tm[2 * NAX];
-#pragma unroll
-                for (int k = 0; k < NAX; ++k) {
-#pragma unroll
-                    for (int side = 0; side < 2; ++side) {
-                        const int Lm = side ? L + LSTEP[k] : L - LSTEP[k];
-                        pm[2 * k + side] = sP[Lm];
-                        mm[2 * k + side] = sM[Lm];
-                        tm[2 * k + side] = sT[Lm];
-                    }
-                }
-                if (!(mself != mself)) continue;  // already done
-                bool ready = true;
-                double lam = sG[p];
-                // children in neighbour order x-, x+, y-, y+, z-, z+
-#pragma unroll
-                for (int k = 0; k < NAX; ++k) {
-#pragma unroll
-                    for (int side = 0; side < 2; ++side) {
-                        const uint8_t pmk = pm[2 * k + side];
-                        // the minus-side neighbour is a child if its plus-side parent is n
-                        const uint32_t want = side ? 1u : 2u;
-                        if (!(pmk & 0x80) && ((pmk >> (2 * k)) & 3u) == want) {
-                            const double mmk = mm[2 * k + side];
-                            if (mmk != mmk) {
-                                ready = false;
-                            } else {
-                                double w = tm[2 * k + side] - tn;
-                                lam = lam + mmk * w;
-                            }
+                    if (tot) {
+                        int base = 0;
+                        if (lane == 0) base = atomicAdd(&s_cnt[cb], tot);
+                        base = __shfl(base, 0);
+    #pragma unroll
+                        for (int j = 0; j < NPT; ++j) {
+                            if ((m >> j) & 1u) sList[base + __popcll(B[j] & lanes_below)] = (uint16_t)(tid + j * NT);
+                            base += __popcll(B[j]);
                         }
                     }
                 }
-                if (!ready) continue;
-                double wk[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-                for (int k = 0; k < NAX; ++k) {
-                    const uint32_t code = (pn >> (2 * k)) & 3u;
-                    if (code == 1u) wk[k] = tn - tm[2 * k];
-                    else if (code == 2u) wk[k] = tn - tm[2 * k + 1];
+                __syncthreads();
+                const int n = s_cnt[cb];
+                if (n == 0) break;
+                // the other counter was last read before the previous barrier and is
+                // next filled after the coming one
+                if (tid == 0) s_cnt[cb ^ 1] = 0;
+                for (int i = tid; i < n; i += NT) {
+                    const int p = sList[i];
+                    const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+                    const int L = C::lds(lx, ly, lz);
+                    // every LDS read of the point and its neighbours goes out at once
+                    const uint8_t pn = sP[L];
+                    const double mself = sM[L];
+                    const double tn = sT[L];
+                    uint8_t pm[2 * NAX];
+                    double mm[2 * NAX], tm[2 * NAX];
+    #pragma unroll
+                    for (int k = 0; k < NAX; ++k) {
+    #pragma unroll
+                        for (int side = 0; side < 2; ++side) {
+                            const int Lm = side ? L + LSTEP[k] : L - LSTEP[k];
+                            pm[2 * k + side] = sP[Lm];
+                            mm[2 * k + side] = sM[Lm];
+                            tm[2 * k + side] = sT[Lm];
+                        }
+                    }
+                    if (!(mself != mself)) continue;  // already done
+                    bool ready = true;
+                    double lam = sG[p];
+                    // children in neighbour order x-, x+, y-, y+, z-, z+
+    #pragma unroll
+                    for (int k = 0; k < NAX; ++k) {
+    #pragma unroll
+                        for (int side = 0; side < 2; ++side) {
+                            const uint8_t pmk = pm[2 * k + side];
+                            // the minus-side neighbour is a child if its plus-side parent is n
+                            const uint32_t want = side ? 1u : 2u;
+                            if (!(pmk & 0x80) && ((pmk >> (2 * k)) & 3u) == want) {
+                                const double mmk = mm[2 * k + side];
+                                if (mmk != mmk) {
+                                    ready = false;
+                                } else {
+                                    double w = tm[2 * k + side] - tn;
+                                    lam = lam + mmk * w;
+                                }
+                            }
+                        }
+                    }
+                    if (!ready) continue;
+                    double wk[3] = {0.0, 0.0, 0.0};
+    #pragma unroll
+                    for (int k = 0; k < NAX; ++k) {
+                        const uint32_t code = (pn >> (2 * k)) & 3u;
+                        if (code == 1u) wk[k] = tn - tm[2 * k];
+                        else if (code == 2u) wk[k] = tn - tm[2 * k + 1];
+                    }
+                    double W = wk[0] + wk[1];
+                    W = W + wk[2];
+                    const double mun = lam / W;
+                    sM[L] = mun;
+                    // parents inside the tile may now be ready
+                    uint8_t* nd = sDirty[cb ^ 1];
+    #pragma unroll
+                    for (int k = 0; k < NAX; ++k) {
+                        const uint32_t code = (pn >> (2 * k)) & 3u;
+                        const int c = k == 0 ? lx : (k == 1 ? ly : lz);
+                        const int lim = k == 0 ? TX : (k == 1 ? TY : TZ);
+                        if (code == 1u && c > 0) nd[didx<NT, NPT>(p - PSTEP[k])] = 1;
+                        if (code == 2u && c < lim - 1) nd[didx<NT, NPT>(p + PSTEP[k])] = 1;
+                    }
                 }
-                double W = wk[0] + wk[1];
-                W = W + wk[2];
-                const double mun = lam / W;
-                sM[L] = mun;
-                // parents inside the tile may now be ready
-                uint8_t* nd = sDirty[cb ^ 1];
-#pragma unroll
-                for (int k = 0; k < NAX; ++k) {
-                    const uint32_t code = (pn >> (2 * k)) & 3u;
-                    const int c = k == 0 ? lx : (k == 1 ? ly : lz);
-                    const int lim = k == 0 ? TX : (k == 1 ? TY : TZ);
-                    if (code == 1u && c > 0) nd[didx<NT, NPT>(p - PSTEP[k])] = 1;
-                    if (code == 2u && c < lim - 1) nd[didx<NT, NPT>(p + PSTEP[k])] = 1;
+                ++passes;
+                __syncthreads();
+                cb ^= 1;
+                if (passes > (1 << 20)) {
+                    if (tid == 0) set_flag(S, kFlagWatchdog);
+                    break;
                 }
             }
-            ++passes;
-            __syncthreads();
-            cb ^= 1;
-            if (passes > (1 << 20)) {
-                if (tid == 0) set_flag(S, kFlagWatchdog);
-                break;
+        } else {
+            static_assert(PACK || NPT == 1, "the direct form has one point per thread");
+            // Direct form: each thread owns one point (NT == NP) and keeps its
+            // state in registers; only the neighbours come from LDS.  A pass
+            // evaluates each dirty point once and marks the in-tile parents of
+            // the points it completed in the other flag buffer, so one barrier
+            // per pass orders the marks before the next pass's reads.
+            {
+                const int p = tid;
+                const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+                const int L = C::lds(lx, ly, lz);
+                const uint8_t pn = sP[L];
+                const double tn = sT[L];
+                const double gn = sG[p];
+                bool done = was_done[0];
+                uint32_t dirty = 0;
+                {
+                    const uint32_t fl = ld_flags<NPT>(sDirty[0] + tid * NPT);
+                    dirty = fl & 1u & live;
+                    st_flags<NPT>(sDirty[0] + tid * NPT, 0u);
+                }
+                for (;;) {
+                    if (tid == 0) s_more[(passes + 1) % 3] = 0;  // written next pass; last read two barriers ago
+                    bool marked = false;
+                    uint8_t* nd = sDirty[cb ^ 1];
+                    if (dirty && !done) {
+                        uint8_t pm[2 * NAX];
+                        double mm[2 * NAX], tm[2 * NAX];
+    #pragma unroll
+                        for (int k = 0; k < NAX; ++k) {
+    #pragma unroll
+                            for (int side = 0; side < 2; ++side) {
+                                const int Lm = side ? L + LSTEP[k] : L - LSTEP[k];
+                                pm[2 * k + side] = sP[Lm];
+                                mm[2 * k + side] = sM[Lm];
+                                tm[2 * k + side] = sT[Lm];
+                            }
+                        }
+                        bool ready = true;
+                        double lam = gn;
+                        // children in neighbour order x-, x+, y-, y+, z-, z+
+    #pragma unroll
+                        for (int k = 0; k < NAX; ++k) {
+    #pragma unroll
+                            for (int side = 0; side < 2; ++side) {
+                                const uint8_t pmk = pm[2 * k + side];
+                                // the minus-side neighbour is a child if its plus-side parent is n
+                                const uint32_t want = side ? 1u : 2u;
+                                if (!(pmk & 0x80) && ((pmk >> (2 * k)) & 3u) == want) {
+                                    const double mmk = mm[2 * k + side];
+                                    if (mmk != mmk) {
+                                        ready = false;
+                                    } else {
+                                        double w = tm[2 * k + side] - tn;
+                                        lam = lam + mmk * w;
+                                    }
+                                }
+                            }
+                        }
+                        if (ready) {
+                            double wk[3] = {0.0, 0.0, 0.0};
+    #pragma unroll
+                            for (int k = 0; k < NAX; ++k) {
+                                const uint32_t code = (pn >> (2 * k)) & 3u;
+                                if (code == 1u) wk[k] = tn - tm[2 * k];
+                                else if (code == 2u) wk[k] = tn - tm[2 * k + 1];
+                            }
+                            double W = wk[0] + wk[1];
+                            W = W + wk[2];
+                            const double mun = lam / W;
+                            sM[L] = mun;
+                            done = true;
+                            // parents inside the tile may now be ready
+    #pragma unroll
+                            for (int k = 0; k < NAX; ++k) {
+                                const uint32_t code = (pn >> (2 * k)) & 3u;
+                                const int c = k == 0 ? lx : (k == 1 ? ly : lz);
+                                const int lim = k == 0 ? TX : (k == 1 ? TY : TZ);
+                                if (code == 1u && c > 0) {
+                                    nd[didx<NT, NPT>(p - PSTEP[k])] = 1;
+                                    marked = true;
+                                }
+                                if (code == 2u && c < lim - 1) {
+                                    nd[didx<NT, NPT>(p + PSTEP[k])] = 1;
+                                    marked = true;
+                                }
+                            }
+                        }
+                    }
+                    if (__ballot(marked) && lane == 0) s_more[passes % 3] = 1;
+                    __syncthreads();
+                    const bool more = s_more[passes % 3] != 0;
+                    ++passes;
+                    if (!more) break;
+                    cb ^= 1;
+                    {
+                        uint8_t* df = sDirty[cb] + tid * NPT;
+                        const uint32_t fl = ld_flags<NPT>(df);
+                        dirty = fl & 1u & live;
+                        if (fl) st_flags<NPT>(df, 0u);
+                    }
+                    if (passes > (1 << 20)) {
+                        if (tid == 0) set_flag(S, kFlagWatchdog);
+                        break;
+                    }
+                }
             }
         }
 

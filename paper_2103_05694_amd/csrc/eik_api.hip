@@ -610,15 +610,21 @@ int adjoint(Workspace& w, const std::vector<Prob>& probs, int64_t ntiles, int64_
     a.tkey = w.tkey;
     a.tref_bits = tref;
     a.s = s;
+    // two pass structures as in the forward solver: one thread per point
+    // (default) or compacted pass lists on 256-thread blocks (EIK_FLAG_PACKED)
+    constexpr int nt = solve_threads<TX, TY, TZ>();
+    constexpr int ntp = tile_threads<TX, TY, TZ>();
+    const bool pack = o && (o->flags & EIK_FLAG_PACKED);
+    const void* kern = pack ? (const void*)k_adjoint<TX, TY, TZ, ntp, true> : (const void*)k_adjoint<TX, TY, TZ, nt>;
+    const int threads = pack ? ntp : nt;
     int grid = 0;
-    constexpr int nt = tile_threads<TX, TY, TZ>();
-    if ((rc = occupancy_grid((const void*)k_adjoint<TX, TY, TZ, nt>, nt, &grid))) return rc;
+    if ((rc = occupancy_grid(kern, threads, &grid))) return rc;
     if (o && o->grid_blocks > 0) grid = std::min(grid, o->grid_blocks);
     if ((int64_t)grid > ntiles) grid = (int)ntiles;
     if (grid < 1) grid = 1;
     if ((rc = timing_begin(w, o))) return rc;
-    hipLaunchKernelGGL((k_adjoint<TX, TY, TZ, nt>), dim3(grid), dim3(nt), 0, st, a);
-    HIP_TRY(hipGetLastError());
+    void* kargs[] = {(void*)&a};
+    HIP_TRY(hipLaunchKernel(kern, dim3(grid), dim3(threads), kargs, 0, st));
     if ((rc = timing_end(w, o))) return rc;
     w.last_kind = 2;
     w.last_ntiles = ntiles;

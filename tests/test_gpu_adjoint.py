@@ -62,14 +62,14 @@ def test_adjoint_matches_oracle(gpu, O, case):
     ref_grad, ref_mu = O.adjoint(t, par, f, h, g, return_mu=True)
     tiles = [(64, 16), (32, 32), (16, 16)] if f.shape[0] == 1 else [(32, 8, 4), (8, 8, 8), (64, 4, 4), (16, 8, 8)]
     for tile in tiles:
-        for delta in (0.0, 1.0):
+        for delta, pk in ((0.0, False), (1.0, False), (0.0, True), (1.0, True)):
             mu = torch.empty(f.shape, dtype=torch.float64, device="cuda")
             grad = gpu.adjoint(to_gpu(f), h, to_gpu(t), to_gpu(par), to_gpu(g), tile=tile, delta=delta,
-                               mu_out=mu.view(to_gpu(f).shape))
+                               mu_out=mu.view(to_gpu(f).shape), packed=pk)
             gr = grad.cpu().numpy().reshape(f.shape)
-            assert_close_or_equal(gr, ref_grad, f"{name} grad tile {tile}")
+            assert_close_or_equal(gr, ref_grad, f"{name} grad tile {tile} packed {pk}")
             m = mu.cpu().numpy()
-            assert_close_or_equal(m, ref_mu, f"{name} mu tile {tile}")
+            assert_close_or_equal(m, ref_mu, f"{name} mu tile {tile} packed {pk}")
 
 
 def test_adjoint_end_to_end_from_gpu_forward(gpu, O):
@@ -141,6 +141,10 @@ def test_batched_adjoint_equals_per_problem(gpu, O):
     grad = torch.empty_like(t)
     gpu.adjoint_packed(b, t, par, gp, grad)
     gpu.status()
+    grad2 = torch.empty_like(t)
+    gpu.adjoint_packed(b, t, par, gp, grad2, packed=True, tile=(8, 8, 8), delta=0.3)
+    gpu.status()
+    assert torch.equal(grad, grad2)
     for (f, s), g, gr in zip(shots, gs, b.views(grad)):
         tr = O.fmm(f, 1.0, s)
         ref = O.adjoint(tr, O.parents(tr, s), f, 1.0, g)
@@ -161,8 +165,8 @@ def test_adjoint_degenerate_gradients(gpu, O):
             g.reshape(-1)[src] = rng.standard_normal(src.size)
         ref = O.adjoint(t, par, f, 1.0, g)
         assert not np.any(ref)
-        for tile in ((8, 8, 8), (16, 8, 8)):
-            grad = gpu.adjoint(to_gpu(f), 1.0, to_gpu(t), to_gpu(par), to_gpu(g), tile=tile)
+        for tile, pk in (((8, 8, 8), False), ((16, 8, 8), True), ((16, 8, 8), False)):
+            grad = gpu.adjoint(to_gpu(f), 1.0, to_gpu(t), to_gpu(par), to_gpu(g), tile=tile, packed=pk)
             got = grad.cpu().numpy().reshape(f.shape)
             assert np.array_equal(got, ref), (name, tile)
 
@@ -177,7 +181,7 @@ def test_graph_capture_with_different_forward_and_adjoint_tiles(gpu, O):
     fields = [to_gpu(1.0 / f) for f, _ in shots]
     srcs = [torch.as_tensor(s) for _, s in shots]
     recs = [torch.arange(0, f.size, 7, device="cuda") for f, _ in shots]
-    sb = ShotBatch(fields, 1.0, srcs, recs, kind="slowness", delta=0.3, tile=(16, 8, 8),
+    sb = ShotBatch(fields, 1.0, srcs, recs, kind="slowness", delta=0.3, tile=(16, 8, 8), packed=True,
                    adj_delta=0.6, adj_tile=(8, 8, 8))
     sb.capture()
     t_plain = torch.empty_like(sb.t)

@@ -38,7 +38,7 @@ def tuned(shape, kind, default_tile, default_delta, nshots=32):
                horizon=int(cfg.get("horizon", 0)), packed=bool(cfg.get("packed", False)))
     if "adj_delta" in cfg:
         out.update(adj_delta=cfg["adj_delta"], adj_tile=tuple(cfg["adj_tile"]),
-                   adj_grid_blocks=int(cfg.get("adj_grid_blocks", 0)))
+                   adj_grid_blocks=int(cfg.get("adj_grid_blocks", 0)), adj_packed=bool(cfg.get("adj_packed", False)))
     return out
 
 
@@ -120,7 +120,8 @@ def test_uneven_full_batch(gpu, O):
         gv[i].copy_(torch.from_numpy(gi).reshape(gv[i].shape))
     grad = torch.empty_like(t)
     gpu.adjoint_packed(b, t, par, g, grad, delta=cfg.get("adj_delta", cfg["delta"]),
-                       tile=cfg.get("adj_tile", cfg["tile"]), grid_blocks=cfg.get("adj_grid_blocks", cfg["grid_blocks"]))
+                       tile=cfg.get("adj_tile", cfg["tile"]), grid_blocks=cfg.get("adj_grid_blocks", cfg["grid_blocks"]),
+                       packed=cfg.get("adj_packed", False))
     gpu.status()
     tv, pv, grv = b.views(t), b.views(par), b.views(grad)
     for i in small:
