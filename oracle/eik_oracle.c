@@ -39,6 +39,7 @@
 #define OP_DHAT 1   /* reordered explicit formula (2D only) */
 #define OP_DTILDE 2 /* textbook explicit formula (2D only) */
 #define OP_NEWTON 3 /* Newton on the root function from the d-hat guess (2D only) */
+#define OP_RECT 4   /* exact monotone rounding on a rectilinear grid (see below) */
 
 static uint64_t bits_of(double x) { uint64_t u; memcpy(&u, &x, 8); return u; }
 static double double_of(uint64_t u) { double x; memcpy(&x, &u, 8); return x; }
@@ -133,6 +134,136 @@ int orc_reaches(double r, const double a_in[3], double c) {
     return reaches(r, as, c);
 }
 
+/* ------------------------------------------------------------------------- */
+/* the operator on a rectilinear grid                                         */
+/* ------------------------------------------------------------------------- */
+
+/* A rectilinear grid has strictly increasing coordinates x_i, y_j, z_k per
+ * axis, so the spacing differs between points and between the two sides of a
+ * point.  The first-order upwind scheme then compares, per axis, the two
+ * one-sided differences (t - t_minus)/h_minus and (t - t_plus)/h_plus and
+ * keeps the larger positive one (the Godunov choice); their squares sum to
+ * the squared slowness.  Following the construction of the section "Achieving
+ * Exact Monotonicity with Finite Precision Arithmetic" -- the result is the
+ * smallest float satisfying a predicate that is monotone in floating point --
+ * with w = fl(1 / fl(x_i - x_{i-1})) (and likewise on the plus side):
+ *   m_k(r) = max(fl(fl(r - am_k) * wm_k), fl(fl(r - ap_k) * wp_k)),
+ *   T_k(r) = fl(m_k * m_k) when m_k > 0, else +0,
+ *   S(r)   = the T_k summed in ascending order of a_k = min(am_k, ap_k)
+ *            (ties in axis order): fl(fl(T_(0) + T_(1)) + T_(2)),
+ *   c      = fl(s * s), s the slowness (fl(1 / v) for a speed field),
+ *   result = the smallest binary64 r >= min_k a_k with S(r) >= c.
+ * Every operation is monotone in r and anti-monotone in each neighbour value,
+ * so S is too, and the result is monotone and causal: Theorem 1 applies.  With
+ * unit spacing, m_k = fl(r - a_k) and the definition is the uniform one with
+ * h = 1 bit for bit; with any power-of-two spacing it is the uniform one
+ * scaled exactly. */
+
+typedef struct {
+    const double *wm[3], *wp[3];   /* per axis and index: 1 / spacing to the minus / plus side */
+} rect_t;
+
+static const rect_t *g_rect = NULL;  /* set only while a rectilinear entry point runs */
+
+static double rect_term(double r, double am, double ap, double wm, double wp) {
+    double d1 = (r - am) * wm;
+    double d2 = (r - ap) * wp;
+    double m = d1 > d2 ? d1 : d2;
+    return m > 0.0 ? m * m : 0.0;
+}
+
+/* axes in ascending order of a_k (ties: axis order) */
+static void rect_order(const double a[3], int ord[3]) {
+    ord[0] = 0; ord[1] = 1; ord[2] = 2;
+    for (int i = 1; i < 3; ++i)
+        for (int j = i; j > 0 && a[ord[j]] < a[ord[j - 1]]; --j) {
+            int t = ord[j]; ord[j] = ord[j - 1]; ord[j - 1] = t;
+        }
+}
+
+static int reaches_rect(double r, const double am[3], const double ap[3], const double wm[3],
+                        const double wp[3], const int ord[3], double c) {
+    double T[3];
+    for (int j = 0; j < 3; ++j) {
+        int k = ord[j];
+        T[j] = rect_term(r, am[k], ap[k], wm[k], wp[k]);
+    }
+    double s = T[0] + T[1];
+    s = s + T[2];
+    return s >= c;
+}
+
+/* The rectilinear d-bar.  Axes absent from the grid have am = ap = +inf.
+ * Found like orc_dbar: a guess (the real-arithmetic root with each axis
+ * using the weight of its smaller neighbour), exponential search and
+ * bisection on the integer image; the invariant reaches(L) == 0,
+ * reaches(H) == 1 fixes the result whatever the guess. */
+double orc_dbar_rect(const double am[3], const double ap[3], const double wm[3], const double wp[3],
+                     double c) {
+    double a[3], w[3];
+    for (int k = 0; k < 3; ++k) {
+        a[k] = am[k] <= ap[k] ? am[k] : ap[k];
+        w[k] = am[k] <= ap[k] ? wm[k] : wp[k];
+    }
+    int ord[3];
+    rect_order(a, ord);
+    const double amin = a[ord[0]];
+    if (!(amin < INFINITY)) return INFINITY;
+    double A = 0.0, B = 0.0, C = -c, g = INFINITY;
+    for (int j = 0; j < 3; ++j) {
+        int k = ord[j];
+        if (!(a[k] < INFINITY)) break;
+        double w2 = w[k] * w[k];
+        A += w2;
+        B += w2 * a[k];
+        C += w2 * a[k] * a[k];
+        double disc = B * B - A * C;
+        g = (B + sqrt(disc > 0.0 ? disc : 0.0)) / A;
+        if (j == 2 || !(g > a[ord[j + 1]])) break;
+    }
+    const uint64_t A0 = bits_of(amin);
+    const uint64_t INF = bits_of(INFINITY);
+    uint64_t G;
+    if (!(g > amin)) G = A0 + 1;
+    else if (!(g < INFINITY)) G = INF;
+    else G = bits_of(g);
+    uint64_t L, H;
+    if (reaches_rect(double_of(G), am, ap, wm, wp, ord, c)) {
+        H = G;
+        uint64_t step = 1;
+        for (;;) {
+            L = (H - A0 > step) ? G - step : A0;
+            if (L == A0 || !reaches_rect(double_of(L), am, ap, wm, wp, ord, c)) break;
+            H = L;
+            step <<= 1;
+        }
+    } else {
+        L = G;
+        uint64_t step = 1;
+        for (;;) {
+            H = (INF - G > step) ? G + step : INF;
+            if (H == INF || reaches_rect(double_of(H), am, ap, wm, wp, ord, c)) break;
+            L = H;
+            step <<= 1;
+        }
+    }
+    while (H - L > 1) {
+        uint64_t M = L + (H - L) / 2;
+        if (reaches_rect(double_of(M), am, ap, wm, wp, ord, c)) H = M; else L = M;
+    }
+    return double_of(H);
+}
+
+/* Exported single predicate evaluation, for tests. */
+int orc_reaches_rect(double r, const double am[3], const double ap[3], const double wm[3],
+                     const double wp[3], double c) {
+    double a[3];
+    for (int k = 0; k < 3; ++k) a[k] = am[k] <= ap[k] ? am[k] : ap[k];
+    int ord[3];
+    rect_order(a, ord);
+    return reaches_rect(r, am, ap, wm, wp, ord, c);
+}
+
 /* The two explicit 2D formulas the paper analyses, with q = fl(h/v), c = fl(q*q).
  * Two-sided branch when |tH - tV| < q, else min(tH, tV) + q. */
 double orc_dtilde(double tH, double tV, double c, double q) {
@@ -223,7 +354,26 @@ double orc_newton(double tH, double tV, double c, double q) {
 }
 
 /* Apply the chosen operator at point i; returns the candidate value. */
+/* Neighbour values on both sides of each axis and the spacing weights at i
+ * (rectilinear operator; +inf off the grid and for absent axes). */
+static double apply_rect(const grid_t *g, const double *t, const double *q, int64_t i) {
+    const int64_t n[3] = {g->nx, g->ny, g->nz};
+    const int64_t stride[3] = {1, g->nx, g->nx * g->ny};
+    const int64_t coord[3] = {i % g->nx, (i / g->nx) % g->ny, i / (g->nx * g->ny)};
+    double am[3] = {INFINITY, INFINITY, INFINITY}, ap[3] = {INFINITY, INFINITY, INFINITY};
+    double wm[3] = {1.0, 1.0, 1.0}, wp[3] = {1.0, 1.0, 1.0};
+    for (int k = 0; k < g->ndim; ++k) {
+        if (coord[k] > 0) am[k] = t[i - stride[k]];
+        if (coord[k] < n[k] - 1) ap[k] = t[i + stride[k]];
+        wm[k] = g_rect->wm[k][coord[k]];
+        wp[k] = g_rect->wp[k][coord[k]];
+    }
+    double qi = q[i];
+    return orc_dbar_rect(am, ap, wm, wp, qi * qi);
+}
+
 static double apply_op(const grid_t *g, const double *t, const double *q, int64_t i, int op) {
+    if (op == OP_RECT) return apply_rect(g, t, q, i);
     double a[3];
     neighbour_minima(g, t, i, a);
     double qi = q[i];
@@ -562,6 +712,87 @@ done:
     free(q);
     free(fixed);
     return rc;
+}
+
+/* Entry points for rectilinear grids: coordinates per axis (xs: nx values,
+ * ys: ny, zs: nz or NULL in 2D), strictly increasing and finite, with
+ * finite reciprocal spacings.  They run the schedules above with the
+ * rectilinear operator and q = fl(1/v) or s (spacing lives in the weights).
+ * -6: bad coordinates. */
+int64_t orc_residual(int ndim, int64_t nx, int64_t ny, int64_t nz, double h, const double *field, int kind,
+                     int64_t nsrc, const int64_t *src, const double *t, int op, double *maxrel);
+
+typedef int (*rect_body)(int ndim, int64_t nx, int64_t ny, int64_t nz, void *ctx);
+
+static int with_rect(int ndim, int64_t nx, int64_t ny, int64_t nz, const double *xs, const double *ys,
+                     const double *zs, rect_body body, void *ctx) {
+    const int64_t n[3] = {nx, ny, nz};
+    const double *xyz[3] = {xs, ys, zs};
+    double *buf = (double *)malloc(sizeof(double) * 2 * (size_t)(nx + ny + nz));
+    if (!buf) return -2;
+    rect_t r;
+    double *p = buf;
+    int rc = 0;
+    for (int k = 0; k < 3; ++k) {
+        double *wm = p, *wp = p + n[k];
+        p += 2 * n[k];
+        r.wm[k] = wm;
+        r.wp[k] = wp;
+        for (int64_t i = 0; i < n[k]; ++i) { wm[i] = 1.0; wp[i] = 1.0; }
+        if (k >= ndim) continue;
+        for (int64_t i = 0; i < n[k]; ++i) {
+            if (!(xyz[k][i] > -INFINITY) || !(xyz[k][i] < INFINITY)) { rc = -6; goto done; }
+            if (i > 0) {
+                double hm = xyz[k][i] - xyz[k][i - 1];
+                double w = 1.0 / hm;
+                if (!(hm > 0.0) || !(w < INFINITY)) { rc = -6; goto done; }
+                wm[i] = w;
+                wp[i - 1] = w;
+            }
+        }
+    }
+    g_rect = &r;
+    rc = body(ndim, nx, ny, nz, ctx);
+    g_rect = NULL;
+done:
+    free(buf);
+    return rc;
+}
+
+typedef struct {
+    const double *field; int kind; int64_t nsrc; const int64_t *src; const double *t0;
+    double *t; int64_t *stats; int which; uint64_t seed; double *maxrel; int64_t count;
+} rect_ctx;
+
+static int rect_run(int ndim, int64_t nx, int64_t ny, int64_t nz, void *vctx) {
+    rect_ctx *c = (rect_ctx *)vctx;
+    switch (c->which) {
+        case 0: return orc_fmm(ndim, nx, ny, nz, 1.0, c->field, c->kind, c->nsrc, c->src, c->t0, OP_RECT, c->t, c->stats);
+        case 1: return orc_sweep_all(ndim, nx, ny, nz, 1.0, c->field, c->kind, c->nsrc, c->src, c->t0, OP_RECT, c->t, c->stats);
+        case 2: return orc_fsm(ndim, nx, ny, nz, 1.0, c->field, c->kind, c->nsrc, c->src, c->t0, OP_RECT, c->t, c->stats);
+        case 3: return orc_async_random(ndim, nx, ny, nz, 1.0, c->field, c->kind, c->nsrc, c->src, c->t0, OP_RECT,
+                                        c->seed, 0, c->t, c->stats);
+        default:
+            c->count = orc_residual(ndim, nx, ny, nz, 1.0, c->field, c->kind, c->nsrc, c->src, c->t, OP_RECT, c->maxrel);
+            return c->count < 0 ? -1 : 0;
+    }
+}
+
+/* which: 0 fast marching, 1 topology-driven rounds, 2 fast sweeping, 3 random-order worklist. */
+int orc_solve_rect(int which, int ndim, int64_t nx, int64_t ny, int64_t nz, const double *xs, const double *ys,
+                   const double *zs, const double *field, int kind, int64_t nsrc, const int64_t *src,
+                   const double *t0, uint64_t seed, double *t, int64_t *stats) {
+    rect_ctx c = {field, kind, nsrc, src, t0, t, stats, which, seed, NULL, 0};
+    return with_rect(ndim, nx, ny, nz, xs, ys, zs, rect_run, &c);
+}
+
+/* Residual of a state on a rectilinear grid (as orc_residual); < 0 on error. */
+int64_t orc_residual_rect(int ndim, int64_t nx, int64_t ny, int64_t nz, const double *xs, const double *ys,
+                          const double *zs, const double *field, int kind, int64_t nsrc, const int64_t *src,
+                          const double *t, double *maxrel) {
+    rect_ctx c = {field, kind, nsrc, src, NULL, (double *)t, NULL, 4, 0, maxrel, 0};
+    int rc = with_rect(ndim, nx, ny, nz, xs, ys, zs, rect_run, &c);
+    return rc ? rc : c.count;
 }
 
 /* Residual metric (Table "tab:error"): re-apply the operator at every non-source

@@ -21,6 +21,10 @@ Each function cites the passage of the paper it follows:
                          "tab:prec_2".
   * ``newton``        -- Newton's method on the root function from the d-hat
                          guess (the precision section's practical variant).
+  * ``dbar_rect``/``solve_rect``/``residual_rect`` -- the same exact-rounding
+                         construction on a rectilinear grid (spacing varying
+                         per axis and index): the irregular-grid case the
+                         conclusion names as the next step.
   * ``parents``/``adjoint`` -- the paper is silent; implicit differentiation of
                          the discrete equations (Eq. "difference_as_root")
                          over the recorded upwind parents.
@@ -73,6 +77,16 @@ def lib():
         L.orc_async_random.restype = _int
         L.orc_async_random.argtypes = [_int, _i64, _i64, _i64, _d, _ptr, _int, _i64, _ptr, _ptr,
                                        _int, ctypes.c_uint64, _int, _ptr, _ptr]
+        L.orc_dbar_rect.restype = _d
+        L.orc_dbar_rect.argtypes = [ctypes.POINTER(_d)] * 4 + [_d]
+        L.orc_reaches_rect.restype = _int
+        L.orc_reaches_rect.argtypes = [_d] + [ctypes.POINTER(_d)] * 4 + [_d]
+        L.orc_solve_rect.restype = _int
+        L.orc_solve_rect.argtypes = [_int, _int, _i64, _i64, _i64, _ptr, _ptr, _ptr, _ptr, _int, _i64, _ptr, _ptr,
+                                     ctypes.c_uint64, _ptr, _ptr]
+        L.orc_residual_rect.restype = _i64
+        L.orc_residual_rect.argtypes = [_int, _i64, _i64, _i64, _ptr, _ptr, _ptr, _ptr, _int, _i64, _ptr, _ptr,
+                                        ctypes.POINTER(_d)]
         L.orc_fmm_resume.restype = _int
         L.orc_fmm_resume.argtypes = [_int, _i64, _i64, _i64, _d, _ptr, _int, _i64, _ptr, _ptr, _i64,
                                      _ptr, _ptr]
@@ -258,6 +272,74 @@ def adjoint(t, par, field, h, g, kind=SPEED, ndim=None, return_mu=False):
                            _p(grad), _p(mu))
     _check(rc, "adjoint")
     return (grad, mu) if return_mu else grad
+
+
+# ---------------------------------------------------------------------------
+# rectilinear grids (per-axis coordinates; the irregular-grid operator)
+# ---------------------------------------------------------------------------
+
+def _arr3(v):
+    return (_d * 3)(*([float(x) for x in v] + [np.inf] * (3 - len(v))))
+
+
+def dbar_rect(am, ap, wm, wp, c: float) -> float:
+    """Smallest binary64 r >= min(a) with S(r) >= c, S summing per axis the
+    square of max(fl(fl(r - am)*wm), fl(fl(r - ap)*wp), 0) in ascending order
+    of min(am, ap) (up to three axes; missing axes are +inf with weight 1)."""
+    w1 = lambda v: (_d * 3)(*([float(x) for x in v] + [1.0] * (3 - len(v))))
+    return lib().orc_dbar_rect(_arr3(am), _arr3(ap), w1(wm), w1(wp), float(c))
+
+
+def reaches_rect(r: float, am, ap, wm, wp, c: float) -> bool:
+    w1 = lambda v: (_d * 3)(*([float(x) for x in v] + [1.0] * (3 - len(v))))
+    return bool(lib().orc_reaches_rect(float(r), _arr3(am), _arr3(ap), w1(wm), w1(wp), float(c)))
+
+
+def _rect_prep(field, xs, ys, zs):
+    field = _f64(field)
+    if field.ndim == 2:
+        field = field.reshape((1,) + field.shape)
+    nz, ny, nx = field.shape
+    xs = _f64(xs).reshape(-1)
+    ys = _f64(ys).reshape(-1)
+    ndim = 2 if zs is None else 3
+    zs = _f64(zs).reshape(-1) if zs is not None else None
+    if xs.size != nx or ys.size != ny or (zs is not None and zs.size != nz) or (zs is None and nz != 1):
+        raise ValueError("coordinates must match the field's shape")
+    return field, nx, ny, nz, ndim, xs, ys, zs
+
+
+_RECT_SCHEDULES = {"fmm": 0, "sweep_all": 1, "fsm": 2, "async_random": 3}
+
+
+def solve_rect(field, xs, ys, zs, src, t0=None, kind=SPEED, schedule: str = "fmm", seed: int = 0):
+    """Arrival times on a rectilinear grid (coordinates xs, ys[, zs]; zs None
+    for 2D) with the rectilinear exact operator, by the named schedule:
+    fast marching, topology-driven rounds, fast sweeping or a random-order
+    worklist."""
+    field, nx, ny, nz, ndim, xs, ys, zs = _rect_prep(field, xs, ys, zs)
+    src = np.ascontiguousarray(np.atleast_1d(src), dtype=np.int64)
+    t0 = None if t0 is None else _f64(np.atleast_1d(t0))
+    t = np.empty_like(field)
+    stats = np.zeros(3, dtype=np.int64)
+    rc = lib().orc_solve_rect(_RECT_SCHEDULES[schedule], ndim, nx, ny, nz, _p(xs), _p(ys), _p(zs), _p(field), kind,
+                              src.size, _p(src), _p(t0), ctypes.c_uint64(seed), _p(t), _p(stats))
+    if rc == -6:
+        raise OracleError("solve_rect: coordinates must increase strictly with finite reciprocal spacings")
+    _check(rc, "solve_rect")
+    return t
+
+
+def residual_rect(t, field, xs, ys, zs, src, kind=SPEED) -> Tuple[int, float]:
+    field, nx, ny, nz, ndim, xs, ys, zs = _rect_prep(field, xs, ys, zs)
+    src = np.ascontiguousarray(np.atleast_1d(src), dtype=np.int64)
+    t = _f64(t).reshape(field.shape)
+    worst = _d(0.0)
+    n = lib().orc_residual_rect(ndim, nx, ny, nz, _p(xs), _p(ys), _p(zs), _p(field), kind, src.size, _p(src),
+                                _p(t), ctypes.byref(worst))
+    if n < 0:
+        raise OracleError("residual_rect: bad field or coordinates")
+    return int(n), float(worst.value)
 
 
 # ---------------------------------------------------------------------------

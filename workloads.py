@@ -287,6 +287,19 @@ def tomography(nx: int = 256, ny: int = 256, nz: int = 128, h: float = 10.0,
                           receivers.astype(np.int64), c)
 
 
+def stretched_coords(n: int, h0: float, ratio: float, x0: float = 0.0) -> np.ndarray:
+    """n increasing coordinates from x0 whose spacing grows geometrically from
+    h0 by `ratio` per cell (ratio 1: uniform spacing h0)."""
+    steps = h0 * ratio ** np.arange(n - 1, dtype=np.float64)
+    return x0 + np.concatenate([[0.0], np.cumsum(steps)])
+
+
+def jittered_coords(n: int, h: float, rng: np.random.Generator, jitter: float = 0.3) -> np.ndarray:
+    """n increasing coordinates with spacings h * (1 + U(-jitter, jitter))."""
+    steps = h * (1.0 + rng.uniform(-jitter, jitter, n - 1))
+    return np.concatenate([[0.0], np.cumsum(steps)])
+
+
 def random_field(shape: Tuple[int, int, int], rng: np.random.Generator,
                  lo: float = 0.5, hi: float = 5.0, block: int = 1) -> np.ndarray:
     """Uniform random speeds in [lo, hi), constant over ``block``-sized cubes."""
