@@ -184,6 +184,34 @@ int eik_solve(const eik_grid* g, const double* field, int64_t nsrc, const int64_
               const double* src_t0, double* t_out, uint8_t* parents_out,
               const eik_opts* opts, void* stream);
 
+/* Forward solve on a rectilinear grid: the spacing varies per axis and per
+ * index, given by the points' coordinates.  The scheme is the first-order
+ * upwind one with, per axis, the larger of the two one-sided differences
+ * (t - t_minus)/h_minus and (t - t_plus)/h_plus (when positive); rounding
+ * follows the exactly monotone construction of the section "Achieving Exact
+ * Monotonicity with Finite Precision Arithmetic", applied to this scheme (the
+ * irregular-grid case the paper's conclusion points to): with
+ * w = fl(1 / fl(x_i - x_{i-1})) per side, m_k(r) = max(fl(fl(r - am)*wm),
+ * fl(fl(r - ap)*wp)), T_k = fl(m_k^2) when m_k > 0 else +0, S(r) the T_k summed
+ * in ascending order of min(am, ap) (ties in axis order) and c = fl(s^2) for
+ * the slowness s = 1/v (speed field) or s, each point's value is the smallest
+ * binary64 r >= min of its neighbours with S(r) >= c.  The operator is monotone
+ * and causal, so the result is schedule-independent (Theorem 1); with unit
+ * spacing it equals eik_solve with h = 1 bit for bit.
+ *   xs_host, ys_host, zs_host  host arrays of nx, ny, nz coordinates, strictly
+ *            increasing and finite (zs_host ignored for 2D grids); g->h is
+ *            ignored.  EIK_EINVAL otherwise.  The first call with given
+ *            coordinates on a stream uploads their reciprocal spacings
+ *            (synchronising the stream).
+ *   field, nsrc, src_idx, src_t0, t_out, stream: as for eik_solve.
+ *   opts     as for eik_solve, except: op must be EIK_OP_DBAR, and
+ *            EIK_FLAG_PACKED, EIK_FLAG_TRACK_CHANGE and work_ref are not
+ *            available (EIK_ENOTSUP).  EIK_FLAG_WARM_START works as for
+ *            eik_solve.  No parent record (the adjoint is for uniform grids). */
+int eik_solve_rect(const eik_grid* g, const double* xs_host, const double* ys_host, const double* zs_host,
+                   const double* field, int64_t nsrc, const int64_t* src_idx, const double* src_t0,
+                   double* t_out, const eik_opts* opts, void* stream);
+
 /* Allocation-free forward solve.  For callers that cannot allocate device
  * memory: code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc.  Same arguments, results (bit for bit), options and errors

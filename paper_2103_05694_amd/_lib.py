@@ -36,7 +36,7 @@ EIK_FLAG_PACKED = 32
 EXPORTED = (
     "eik_solve", "eik_parents", "eik_adjoint", "eik_solve_batched", "eik_adjoint_batched",
     "eik_reserve", "eik_num_tiles", "eik_status", "eik_strerror", "eik_last_error",
-    "eik_release", "eik_version", "eik_timeline", "eik_residual", "eik_solve_noalloc",
+    "eik_release", "eik_version", "eik_timeline", "eik_residual", "eik_solve_noalloc", "eik_solve_rect",
 )
 
 
@@ -89,6 +89,8 @@ def load() -> ctypes.CDLL:
     L = ctypes.CDLL(LIB_PATH)
     L.eik_solve.restype = _i32
     L.eik_solve.argtypes = [_gp, _vp, _i64, _vp, _vp, _vp, _vp, _op, _vp]
+    L.eik_solve_rect.restype = _i32
+    L.eik_solve_rect.argtypes = [_gp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _op, _vp]
     L.eik_solve_noalloc.restype = _i32
     L.eik_solve_noalloc.argtypes = [_gp, _vp, _i64, _vp, _vp, _vp, _vp, _op, _vp]
     L.eik_parents.restype = _i32

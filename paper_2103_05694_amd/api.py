@@ -218,6 +218,51 @@ def solve(field: torch.Tensor, h: float, sources, t0: Optional[torch.Tensor] = N
     return (t, par) if parents else t
 
 
+def solve_rect(field: torch.Tensor, xs, ys, zs=None, sources=None, t0=None, kind: str = "speed",
+               delta: float = 0.0, tile: Optional[Sequence[int]] = None, grid_blocks: int = 0,
+               max_tile_visits: int = 0, out: Optional[torch.Tensor] = None, check_status: bool = True,
+               stream=None, time_kernels: bool = False, lookahead: int = 0, horizon: int = 0,
+               warm_start: bool = False) -> torch.Tensor:
+    """First-arrival times on a rectilinear grid: xs, ys[, zs] are the
+    coordinates of the points along each axis (host sequences or CPU tensors,
+    strictly increasing), so the spacing may vary per axis and index."""
+    import numpy as np
+    _check_field(field)
+    if sources is None:
+        raise ValueError("sources are required")
+    if warm_start and out is None:
+        raise ValueError("warm_start needs the starting times in `out`")
+    L = _lib.load()
+    g = _grid_of(field.shape, 1.0, kind)
+    coords = [np.ascontiguousarray(np.asarray(c, dtype=np.float64).reshape(-1)) for c in (xs, ys)]
+    if g.ndim == 3:
+        if zs is None:
+            raise ValueError("a 3D field needs z coordinates")
+        coords.append(np.ascontiguousarray(np.asarray(zs, dtype=np.float64).reshape(-1)))
+    for c, n in zip(coords, (g.nx, g.ny, g.nz)):
+        if c.size != n:
+            raise ValueError("coordinate arrays must match the field's shape")
+    src = source_indices(sources, field.shape, field.device)
+    t0d = None
+    if t0 is not None:
+        t0d = torch.as_tensor(t0, dtype=torch.float64).reshape(-1).to(field.device).contiguous()
+        if t0d.numel() != src.numel():
+            raise ValueError("t0 needs one value per source")
+    if out is not None:
+        _check_buf(out, "out", torch.float64, field.numel(), field.device)
+    t = out if out is not None else torch.empty_like(field)
+    o = make_opts(delta, tile, grid_blocks, max_tile_visits, time_kernels, lookahead, horizon=horizon,
+                  warm_start=warm_start)
+    rc = L.eik_solve_rect(ctypes.byref(g), coords[0].ctypes.data, coords[1].ctypes.data,
+                          coords[2].ctypes.data if len(coords) == 3 else None, field.data_ptr(), src.numel(),
+                          src.data_ptr(), t0d.data_ptr() if t0d is not None else None, t.data_ptr(),
+                          ctypes.byref(o), ctypes.c_void_p(_stream_handle(stream)))
+    check(rc)
+    if check_status:
+        status(stream)
+    return t
+
+
 def parents_of(t: torch.Tensor, sources, stream=None) -> torch.Tensor:
     _check_field(t)
     L = _lib.load()

@@ -85,6 +85,10 @@ struct Workspace {
     // device problem tables of batched calls (problem list + source offsets),
     // one per distinct layout, kept until eik_release
     std::vector<Table> tables;
+    // rectilinear grids: reciprocal spacings on the device, and what they are
+    double* rw = nullptr;
+    int64_t rw_cap = 0;
+    std::vector<double> rw_host;
     // adjoint scratch
     double* mu = nullptr;
     int64_t mu_cap = 0;
@@ -446,7 +450,7 @@ int blocks_for(int64_t n, int threads, int cap = 65536) {
 template <int TX, int TY, int TZ, int OP = 0>
 int forward_seq(const Bufs& b, const ProbTable& T, int64_t nsrc, int64_t ntiles, int64_t npts_total,
                 const double* field, const int64_t* src_idx, const double* src_t0, double* t, uint8_t* par,
-                const eik_opts* o, Workspace* tw, bool cached) {
+                const eik_opts* o, Workspace* tw, bool cached, const double* rw = nullptr) {
     int rc;
     const bool warm = o && (o->flags & EIK_FLAG_WARM_START);
     hipStream_t st = b.stream;
@@ -479,6 +483,7 @@ int forward_seq(const Bufs& b, const ProbTable& T, int64_t nsrc, int64_t ntiles,
     a.t = t;
     a.tkey = b.tkey;
     a.work_ref = o ? o->work_ref : nullptr;
+    a.rw = rw;
     a.s = s;
     // the two pass structures of k_solve: one thread per point (default) or
     // compacted pass lists on 256-thread blocks (EIK_FLAG_PACKED, d-bar only)
@@ -523,7 +528,7 @@ int forward_seq(const Bufs& b, const ProbTable& T, int64_t nsrc, int64_t ntiles,
 template <int TX, int TY, int TZ, int OP = 0>
 int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int64_t>& src_off,
             int64_t ntiles, int64_t npts_total, const double* field, const int64_t* src_idx,
-            const double* src_t0, double* t, uint8_t* par, const eik_opts* o) {
+            const double* src_t0, double* t, uint8_t* par, const eik_opts* o, const double* rw = nullptr) {
     int rc;
     const int64_t nsrc = src_off.back();
     if ((rc = ensure_tiles(w, ntiles))) return rc;
@@ -531,7 +536,7 @@ int forward(Workspace& w, const std::vector<Prob>& probs, const std::vector<int6
     ProbTable T;
     if ((rc = make_table(w, probs, &src_off, &T))) return rc;
     if ((rc = forward_seq<TX, TY, TZ, OP>(bufs_of(w), T, nsrc, ntiles, npts_total, field, src_idx, src_t0, t,
-                                          par, o, &w, true)))
+                                          par, o, &w, true, rw)))
         return rc;
     w.last_kind = 1;
     w.last_ntiles = ntiles;
@@ -640,6 +645,60 @@ int adjoint_run(Workspace& w, TileShape ts, const std::vector<Prob>& probs, int6
     EIK_TILES_3D(EIK_CASE)
     EIK_TILES_2D(EIK_CASE)
 #undef EIK_CASE
+    return fail(EIK_ENOTSUP, "unsupported tile shape");
+}
+
+// Rectilinear grids: the reciprocal spacings of the coordinates (the same
+// definition the operator is stated with, w = fl(1 / fl(x_i - x_{i-1})), and
+// 1 at the ends, where the neighbour is off the grid), laid out
+// [wm_x, wp_x, wm_y, wp_y, wm_z, wp_z].  EIK_EINVAL unless every axis is
+// strictly increasing and finite with finite reciprocal spacings.
+int rect_weights(const eik_grid& g, const double* xs, const double* ys, const double* zs, std::vector<double>* out) {
+    const int64_t n[3] = {g.nx, g.ny, g.nz};
+    const double* c[3] = {xs, ys, g.ndim == 3 ? zs : nullptr};
+    out->assign((size_t)(2 * (n[0] + n[1] + n[2])), 1.0);
+    size_t off = 0;
+    for (int k = 0; k < 3; ++k) {
+        double* wm = out->data() + off;
+        double* wp = wm + n[k];
+        off += (size_t)(2 * n[k]);
+        if (k >= g.ndim) continue;
+        if (!c[k]) return fail(EIK_EINVAL, "coordinates missing for an axis");
+        for (int64_t i = 0; i < n[k]; ++i) {
+            if (!std::isfinite(c[k][i])) return fail(EIK_EINVAL, "coordinates must be finite");
+            if (i == 0) continue;
+            const double h = c[k][i] - c[k][i - 1];
+            const double w = 1.0 / h;
+            if (!(h > 0.0) || !std::isfinite(w))
+                return fail(EIK_EINVAL, "coordinates must increase strictly (with finite reciprocal spacings)");
+            wm[i] = w;
+            wp[i - 1] = w;
+        }
+    }
+    return EIK_OK;
+}
+
+// Puts the weights on the device (synchronising the stream) unless the same
+// ones are there already, so repeated calls on one grid enqueue only kernels.
+int upload_weights(Workspace& w, const std::vector<double>& rw) {
+    if (w.rw && w.rw_host == rw) return EIK_OK;
+    int rc;
+    if ((rc = grow(&w.rw, &w.rw_cap, (int64_t)rw.size(), w.stream))) return rc;
+    HIP_TRY(hipStreamSynchronize(w.stream));
+    HIP_TRY(hipMemcpy(w.rw, rw.data(), sizeof(double) * rw.size(), hipMemcpyHostToDevice));
+    w.rw_host = rw;
+    return EIK_OK;
+}
+
+int dispatch_rect(TileShape ts, Workspace& w, const std::vector<Prob>& probs, const std::vector<int64_t>& src_off,
+                  int64_t ntiles, int64_t npts, const double* field, const int64_t* src_idx, const double* src_t0,
+                  double* t, const eik_opts* o) {
+#define EIK_RCASE(a, b, c)                                                                                    \
+    if (ts.x == a && ts.y == b && ts.z == c)                                                                  \
+        return forward<a, b, c, 4>(w, probs, src_off, ntiles, npts, field, src_idx, src_t0, t, nullptr, o, w.rw);
+    EIK_TILES_3D(EIK_RCASE)
+    EIK_TILES_2D(EIK_RCASE)
+#undef EIK_RCASE
     return fail(EIK_ENOTSUP, "unsupported tile shape");
 }
 
@@ -886,6 +945,32 @@ int eik_solve_noalloc(const eik_grid* g, const double* field, int64_t nsrc, cons
     return EIK_OK;
 }
 
+int eik_solve_rect(const eik_grid* g, const double* xs_host, const double* ys_host, const double* zs_host,
+                   const double* field, int64_t nsrc, const int64_t* src_idx, const double* src_t0, double* t_out,
+                   const eik_opts* opts, void* stream) {
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (nsrc < 1) return fail(EIK_EINVAL, "nsrc must be >= 1");
+    if (!field || !src_idx || !t_out) return fail(EIK_EINVAL, "NULL device pointer");
+    if ((rc = check_opts(opts))) return rc;
+    if (opts && (opts->op != EIK_OP_DBAR || opts->work_ref || (opts->flags & (EIK_FLAG_PACKED | EIK_FLAG_TRACK_CHANGE))))
+        return fail(EIK_ENOTSUP, "rectilinear grids run the exact operator, per-thread passes, no work classification");
+    std::vector<double> rw;
+    if ((rc = rect_weights(*g, xs_host, ys_host, zs_host, &rw))) return rc;
+    const TileShape ts = pick_tile(g->ndim, opts);
+    if (!tile_supported(g->ndim, ts.x, ts.y, ts.z)) return fail(EIK_ENOTSUP, "unsupported tile shape for this ndim");
+    eik_grid gu = *g;
+    gu.h = 1.0;  // the spacing lives in the weights; q = 1 / v or s
+    std::vector<Prob> probs{make_prob(gu, ts, 0, 0)};
+    std::vector<int64_t> soff{0, nsrc};
+    const int64_t ntiles = tiles_of(probs[0]);
+    const int64_t npts = (int64_t)g->nx * g->ny * g->nz;
+    Workspace* w = nullptr;
+    if ((rc = get_ws((hipStream_t)stream, &w))) return rc;
+    if ((rc = upload_weights(*w, rw))) return rc;
+    return dispatch_rect(ts, *w, probs, soff, ntiles, npts, field, src_idx, src_t0, t_out, opts);
+}
+
 int eik_parents(const eik_grid* g, const double* t, int64_t nsrc, const int64_t* src_idx,
                 uint8_t* parents_out, void* stream) {
     int rc = check_grid(g);
@@ -1111,6 +1196,7 @@ void eik_release(void) {
         (void)hipFree(w->scal);
         (void)hipFree(w->counters);
         (void)hipFree(w->srclist);
+        (void)hipFree(w->rw);
         for (Table& tb : w->tables) {
             (void)hipFree(tb.d_probs);
             (void)hipFree(tb.d_src_off);

@@ -47,6 +47,9 @@ struct SolveArgs {
     double* t;
     uint64_t* tkey;          // [ntiles] pending requeue key (bits of a positive double)
     const double* work_ref;  // NULL, or the final times: classify every evaluation
+    // rectilinear grids (OP 4): reciprocal spacings per axis and index, laid
+    // out [wm_x (nx), wp_x (nx), wm_y (ny), wp_y (ny), wm_z (nz), wp_z (nz)]
+    const double* rw;
     Sched s;
 };
 
@@ -461,6 +464,21 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 25
         double t_in[NPT];   // the values staged (what the run started from)
         double t_own[NPT];  // the thread's points' current values
         double q_own[NPT];  // and their constants (0: not relaxed)
+        double w_own[OP == 4 ? NPT : 1][6];  // rectilinear grids: reciprocal spacings to the six neighbours
+        if constexpr (OP == 4) {
+#pragma unroll
+            for (int j = 0; j < NPT; ++j) {
+                const int p = tid + j * NT;
+                const int x = min(x0 + p % TX, P.nx - 1), y = min(y0 + (p / TX) % TY, P.ny - 1);
+                const int z = min(z0 + p / (TX * TY), P.nz - 1);
+                w_own[j][0] = A.rw[x];
+                w_own[j][1] = A.rw[P.nx + x];
+                w_own[j][2] = A.rw[2 * P.nx + y];
+                w_own[j][3] = A.rw[2 * P.nx + P.ny + y];
+                w_own[j][4] = C::D3 ? A.rw[2 * (P.nx + P.ny) + z] : 1.0;
+                w_own[j][5] = C::D3 ? A.rw[2 * (P.nx + P.ny) + P.nz + z] : 1.0;
+            }
+        }
         uint32_t live = 0;  // bit j: point j is in the grid and not a source
         {
             constexpr int NXF = 2 * TY * TZ, NYF = 2 * TX * TZ, NZF = C::D3 ? 2 * TX * TY : 0;
@@ -702,7 +720,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 25
                 __syncthreads();
                 if (tid == 0) ph[5] += wall_clock64() - tg;
                 cb ^= 1;
-                if (OP != 0 && passes >= (1 << 16)) {  // an ablation operator may not settle
+                if (OP != 0 && OP != 4 && passes >= (1 << 16)) {  // an ablation operator may not settle
                     if (tid == 0) set_flag(S, kFlagLimit);
                     break;
                 }
@@ -754,8 +772,13 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 25
                         const double ax = fmin(nxm, nxp), ay = fmin(nym, nyp), az = fmin(nzm, nzp);
                         bool mark;
                         double r;
-                        if constexpr (OP == 0) {
-                            r = update<C::D3>(ax, ay, az, q, q * q, tc, ch);
+                        if constexpr (OP == 0 || OP == 4) {
+                            if constexpr (OP == 0) {
+                                r = update<C::D3>(ax, ay, az, q, q * q, tc, ch);
+                            } else {
+                                const double nb6[6] = {nxm, nxp, nym, nyp, nzm, nzp};
+                                r = update_rect<C::D3>(nb6, w_own[j], q * q, tc, ch);
+                            }
                             // held back: its bucket lies at or beyond the horizon (a
                             // value whose bucket index overflows the range is settled
                             // at once, so the requeue can never repeat forever)
@@ -789,7 +812,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 25
                             // below r needs no look.  The ablation operators mark every
                             // neighbour.  Six unconditional stores, unwanted ones into
                             // this thread's sink byte (no divergent branches).
-                            constexpr bool kAll = OP != 0;
+                            constexpr bool kAll = OP != 0 && OP != 4;
                             nd[(lx > 0 && (kAll || nxm > r)) ? didx<NT, NPT>(p - 1) : sink] = 1;
                             nd[(lx < TX - 1 && (kAll || nxp > r)) ? didx<NT, NPT>(p + 1) : sink] = 1;
                             nd[(ly > 0 && (kAll || nym > r)) ? didx<NT, NPT>(p - TX) : sink] = 1;
@@ -824,7 +847,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 25
                     if (fl) st_flags<NPT>(df, 0u);
                     dirty &= live;
                 }
-                if (OP != 0 && passes >= (1 << 16)) {  // an ablation operator may not settle
+                if (OP != 0 && OP != 4 && passes >= (1 << 16)) {  // an ablation operator may not settle
                     if (tid == 0) set_flag(S, kFlagLimit);
                     break;
                 }
@@ -861,7 +884,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 25
                     // it is below the neighbour's own value there (its halo
                     // cell here, as staged; values only decrease): the
                     // operator ignores a neighbour above the point it updates
-                    constexpr bool kAny = OP != 0;  // not causal: every lowered face value
+                    constexpr bool kAny = OP != 0 && OP != 4;  // not causal: every lowered face value
                     if (lx == 0 && (kAny || v < nxm)) fmin_[0] = fmin(fmin_[0], v);
                     if (lx == TX - 1 && (kAny || v < nxp)) fmin_[1] = fmin(fmin_[1], v);
                     if (ly == 0 && (kAny || v < nym)) fmin_[2] = fmin(fmin_[2], v);
@@ -870,7 +893,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 25
                         if (lz == 0 && (kAny || v < nzm)) fmin_[4] = fmin(fmin_[4], v);
                         if (lz == TZ - 1 && (kAny || v < nzp)) fmin_[5] = fmin(fmin_[5], v);
                     }
-                } else if (OP != 0 && v != t_in[j]) {
+                } else if (OP != 0 && OP != 4 && v != t_in[j]) {
                     // an ablation operator raised the value: store it, and with
                     // change tracking activate the neighbours across its faces
                     tstore(A.t + P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x, v);

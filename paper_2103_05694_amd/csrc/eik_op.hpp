@@ -192,6 +192,133 @@ __device__ __forceinline__ double update(double x, double y, double z, double q,
     return as_f64(G + 2 - (uint64_t)cnt);
 }
 
+// ---------------------------------------------------------------------------
+// rectilinear grids: spacing varying per axis and index
+// ---------------------------------------------------------------------------
+// Per axis k the two neighbours am, ap and the reciprocal spacings wm, wp to
+// them (w = fl(1 / fl(x_i - x_{i-1})) and likewise on the plus side):
+//   m_k(r) = max(fl(fl(r - am) * wm), fl(fl(r - ap) * wp)),
+//   T_k(r) = fl(m_k * m_k) when m_k > 0, else +0,
+//   S(r)   = the T_k summed in ascending order of a_k = min(am, ap), ties in
+//            axis order: fl(fl(T0 + T1) + T2),
+//   result = the smallest binary64 r >= min_k a_k with S(r) >= c,
+// c = fl(s * s) for the slowness s.  Each step is monotone in r and
+// anti-monotone in the neighbours, so the result is monotone and causal
+// (the construction of section "Achieving Exact Monotonicity with Finite
+// Precision Arithmetic" applied to the irregular-grid scheme).  With unit
+// spacing it is the uniform operator bit for bit.
+
+struct RAxis {
+    double a, am, ap, wm, wp;  // a = min(am, ap)
+};
+
+__device__ __forceinline__ void rswap(RAxis& x, RAxis& y) {
+    // stable: only a strictly smaller key moves forward
+    const bool s = y.a < x.a;
+    const RAxis lo = s ? y : x, hi = s ? x : y;
+    x = lo;
+    y = hi;
+}
+
+__device__ __forceinline__ double rterm(double r, const RAxis& k) {
+    const double d1 = (r - k.am) * k.wm;
+    const double d2 = (r - k.ap) * k.wp;
+    const double m = d1 > d2 ? d1 : d2;
+    return m > 0.0 ? m * m : 0.0;
+}
+
+template <bool D3>
+__device__ __forceinline__ bool reaches_rect(double r, const RAxis& x0, const RAxis& x1, const RAxis& x2, double c) {
+    double s = rterm(r, x0) + rterm(r, x1);
+    if constexpr (D3) s = s + rterm(r, x2);
+    return s >= c;
+}
+
+// Serial search for the rare inputs whose guess misses the window (unit
+// steps from G, then bisection with reaches(L) false, reaches(H) true).
+template <bool D3>
+__device__ __noinline__ double search_slow_rect(const RAxis x0, const RAxis x1, const RAxis x2, double c,
+                                                uint64_t A0, uint64_t G, uint64_t tcb) {
+    uint64_t L, H;
+    bool ok = false;
+    if (reaches_rect<D3>(as_f64(G), x0, x1, x2, c)) {
+        H = G;
+        for (int i = 0; i < 4; ++i) {
+            uint64_t P = H - 1;
+            if (P == A0 || !reaches_rect<D3>(as_f64(P), x0, x1, x2, c)) { ok = true; break; }
+            H = P;
+        }
+        L = A0;
+    } else {
+        L = G;
+        H = tcb - 1;
+        for (int i = 0; i < 4; ++i) {
+            uint64_t N = L + 1;
+            if (reaches_rect<D3>(as_f64(N), x0, x1, x2, c)) { H = N; ok = true; break; }
+            L = N;
+        }
+    }
+    if (!ok) {
+        while (H - L > 1) {
+            uint64_t M = L + ((H - L) >> 1);
+            if (reaches_rect<D3>(as_f64(M), x0, x1, x2, c)) H = M; else L = M;
+        }
+    }
+    return as_f64(H);
+}
+
+// The rectilinear operator; returns the new value if it is < tcur, else tcur.
+// n[6] = neighbours x-, x+, y-, y+, z-, z+ (+inf off the grid), w[6] the
+// reciprocal spacings to them, c = fl(q * q).  The guess is the real root of
+// sum_k w_k^2 (r - a_k)^2 = c over the upwind axes, each with the weight of
+// its smaller neighbour; the predicate at G-1, G, G+1 decides as for d-bar.
+template <bool D3 = true>
+__device__ __forceinline__ double update_rect(const double* n, const double* w, double c, double tcur,
+                                              bool& changed) {
+    changed = false;
+    RAxis x0{fmin(n[0], n[1]), n[0], n[1], w[0], w[1]};
+    RAxis x1{fmin(n[2], n[3]), n[2], n[3], w[2], w[3]};
+    RAxis x2{inf64(), inf64(), inf64(), 1.0, 1.0};
+    if constexpr (D3) x2 = RAxis{fmin(n[4], n[5]), n[4], n[5], w[4], w[5]};
+    rswap(x0, x1);
+    if constexpr (D3) {
+        rswap(x1, x2);
+        rswap(x0, x1);
+    }
+    const double a0 = x0.a;
+    const uint64_t tcb = as_u64(tcur);
+    const bool can = (a0 < tcur) & reaches_rect<D3>(as_f64(tcb - 1), x0, x1, x2, c);
+    // guess: add axes while the root lies above the next minimum
+    double A = 0.0, B = 0.0, C = -c, g = inf64();
+    bool go = true;
+#pragma unroll
+    for (int j = 0; j < (D3 ? 3 : 2); ++j) {
+        const RAxis& k = j == 0 ? x0 : (j == 1 ? x1 : x2);
+        const double wk = k.am <= k.ap ? k.wm : k.wp;
+        const double nxt = j == 0 ? x1.a : (j == 1 ? x2.a : inf64());
+        if (go && k.a < inf64()) {
+            const double w2 = wk * wk;
+            A = A + w2;
+            B = B + w2 * k.a;
+            C = C + (w2 * k.a) * k.a;
+            const double disc = B * B - A * C;
+            g = (B + __builtin_sqrt(fmax(disc, 0.0))) / A;
+            go = g > nxt;
+        }
+    }
+    const uint64_t A0 = as_u64(a0);
+    uint64_t G = as_u64(g);
+    if (!(G >= A0 + 2)) G = A0 + 2;
+    if (G > tcb - 1) G = tcb - 1;
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) cnt += reaches_rect<D3>(as_f64(G - 1 + (uint64_t)k), x0, x1, x2, c) ? 1 : 0;
+    if (!can) return tcur;
+    changed = true;
+    if (cnt == 0 || cnt == 3) return search_slow_rect<D3>(x0, x1, x2, c, A0, G, tcb);
+    return as_f64(G + 2 - (uint64_t)cnt);
+}
+
 // The paper's two explicit two-dimensional formulas (the d-tilde and d-hat
 // columns of Tables "tab:prec_1" and "tab:prec_2"), kept for the precision
 // ablation: they are not monotone in floating point, so an asynchronous solve

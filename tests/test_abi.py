@@ -115,6 +115,32 @@ def test_solve_rejects_bad_counts_and_options(L):
     assert L.eik_solve(ctypes.byref(g2), dummy, 1, dummy, None, dummy, None, ctypes.byref(o), None) == -6
 
 
+def test_rect_rejects_bad_coordinates_and_options(L):
+    from paper_2103_05694_amd._lib import eik_opts
+    g = _grid(ndim=2, nx=5, ny=4, nz=1)
+    dummy = ctypes.c_void_p(16)
+
+    def arr(v):
+        return (ctypes.c_double * len(v))(*v)
+
+    ys = arr([0.0, 1.0, 2.0, 3.0])
+    for xs in ([0.0, 1.0, 1.0, 2.0, 3.0], [0.0, 1.0, 0.5, 2.0, 3.0], [0.0, 1.0, float("nan"), 2.0, 3.0],
+               [0.0, 1.0, float("inf"), 2.0, 3.0], [0.0, 5e-324, 1.0, 2.0, 3.0]):
+        rc = L.eik_solve_rect(ctypes.byref(g), arr(xs), ys, None, dummy, 1, dummy, None, dummy, None, None)
+        assert rc == -1, xs
+        assert b"coordinates" in L.eik_last_error()
+    assert L.eik_solve_rect(ctypes.byref(g), None, ys, None, dummy, 1, dummy, None, dummy, None, None) == -1
+    g3 = _grid(ndim=3, nx=5, ny=4, nz=3)
+    xs = arr([0.0, 1.0, 2.0, 3.0, 4.0])
+    assert L.eik_solve_rect(ctypes.byref(g3), xs, ys, None, dummy, 1, dummy, None, dummy, None, None) == -1
+    assert L.eik_solve_rect(ctypes.byref(g), xs, ys, None, dummy, 0, dummy, None, dummy, None, None) == -1
+    for op, flags in ((2, 0), (0, 32), (0, 8)):   # ablation operator, packed passes, change tracking
+        o = eik_opts()
+        o.op, o.flags = op, flags
+        rc = L.eik_solve_rect(ctypes.byref(g), xs, ys, None, dummy, 1, dummy, None, dummy, ctypes.byref(o), None)
+        assert rc in (-1, -6), (op, flags)
+
+
 def test_residual_rejects_bad_arguments(L):
     g = _grid()
     dummy = ctypes.c_void_p(16)
