@@ -24,7 +24,10 @@ Also reported on the same JSON line:
     recipe (512x512x128), and the tomography step (forward, parents, adjoint)
     for one shot per host core, all cores in parallel;
   * batched: forward + adjoint shots/s for a tomography batch, one graph replay
-    of two persistent launches vs one plain solve + adjoint per shot.
+    of two persistent launches vs one plain solve + adjoint per shot;
+  * the same model on a rectilinear grid (depth spacing stretched 5 -> 20 m),
+    the paper's grid shape in 2D, the schedule comparison and the precision
+    ablation, as extra entries.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -472,6 +475,36 @@ def bench_paper_scale(args, torch, eik, W) -> dict:
             "residual_points": res[0]}
 
 
+def bench_rect(args, torch, eik, W) -> dict:
+    """The benchmark's 512x512x256 layered model on a rectilinear grid:
+    10 m in x and y, depth spacing stretched geometrically from 5 m to about
+    20 m (eik_solve_rect), same source; 8x8x4 tiles and a 0.01 s bucket width,
+    the best of a sweep over five tile shapes and three widths."""
+    import numpy as np
+    p = W.layered_3d()
+    f = torch.from_numpy(p.field).cuda()
+    src = torch.as_tensor(p.src).cuda()
+    nz, ny, nx = p.field.shape
+    xs, ys = np.arange(nx) * p.h, np.arange(ny) * p.h
+    zs = W.stretched_coords(nz, 5.0, 4.0 ** (1.0 / (nz - 2)))
+    out = torch.empty_like(f)
+    kw = dict(tile=(8, 8, 4), delta=0.01, out=out, check_status=False)
+    eik.solve_rect(f, xs, ys, zs, src, **kw)
+    eik.status()
+    reps = 5
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        eik.solve_rect(f, xs, ys, zs, src, **kw)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    st = eik.status()
+    return {"workload": "3D 512x512x256 layered speed on a rectilinear grid (dx = dy = 10 m, dz 5 -> 20 m "
+                        "geometric), one surface-centre source",
+            "points": p.npts, "ms_per_solve": ms, "points_per_s": p.npts / (ms * 1e-3), "tile": [8, 8, 4],
+            "delta": 0.01, "visits_per_tile": st.tile_visits / max(st.ntiles, 1), "max_time_s": float(out.max())}
+
+
 def profile_mode(args, torch, eik, W) -> None:
     """A short run for rocprofv3: kernels of known traffic for the counter
     calibration -- a plain 1 GiB device copy (reads and writes 1 GiB), the
@@ -520,6 +553,7 @@ def main() -> int:
     ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--no-schedules", action="store_true")
     ap.add_argument("--no-paper-scale", action="store_true")
+    ap.add_argument("--no-rect", action="store_true")
     ap.add_argument("--profile-mode", action="store_true")
     ap.add_argument("--cpu-baseline-worker", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
@@ -597,6 +631,10 @@ def main() -> int:
         log("paper-scale 2D grid")
         extra["paper_scale_2d"] = bench_paper_scale(args, torch, eik, W)
         log(json.dumps(extra["paper_scale_2d"]))
+    if not args.no_rect:
+        log("rectilinear grid")
+        extra["rect_3d"] = bench_rect(args, torch, eik, W)
+        log(json.dumps(extra["rect_3d"]))
     if not args.no_schedules:
         log("schedule comparison")
         extra["schedules"] = bench_schedules(args, torch, eik, W)

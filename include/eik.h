@@ -147,7 +147,8 @@ typedef struct {
     int64_t ntiles;          /* tiles in the problem(s) */
     int64_t relax_passes;    /* in-tile relaxation passes (adjoint: readiness passes), summed
                                 over visits */
-    uint32_t flags;          /* raw device flags (bit0 domain, bit1 limit, bit2 bad source, bit3 watchdog) */
+    uint32_t flags;          /* raw device flags (bit0 domain, bit1 limit, bit2 bad source, bit3 watchdog,
+                                bit4 invalid warm-start value) */
     int32_t status;          /* the EIK_* code these flags map to */
     double kernel_ms;        /* mean duration of the timed persistent kernels, or -1 */
     int64_t kernel_launches; /* how many launches kernel_ms averages */
@@ -193,7 +194,7 @@ int eik_solve(const eik_grid* g, const double* field, int64_t nsrc, const int64_
  * irregular-grid case the paper's conclusion points to): with
  * w = fl(1 / fl(x_i - x_{i-1})) per side, m_k(r) = max(fl(fl(r - am)*wm),
  * fl(fl(r - ap)*wp)), T_k = fl(m_k^2) when m_k > 0 else +0, S(r) the T_k summed
- * in ascending order of min(am, ap) (ties in axis order) and c = fl(s^2) for
+ * largest first (fl(fl(T_hi + T_mid) + T_lo)) and c = fl(s^2) for
  * the slowness s = 1/v (speed field) or s, each point's value is the smallest
  * binary64 r >= min of its neighbours with S(r) >= c.  The operator is monotone
  * and causal, so the result is schedule-independent (Theorem 1); with unit

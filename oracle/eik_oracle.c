@@ -149,15 +149,22 @@ int orc_reaches(double r, const double a_in[3], double c) {
  * with w = fl(1 / fl(x_i - x_{i-1})) (and likewise on the plus side):
  *   m_k(r) = max(fl(fl(r - am_k) * wm_k), fl(fl(r - ap_k) * wp_k)),
  *   T_k(r) = fl(m_k * m_k) when m_k > 0, else +0,
- *   S(r)   = the T_k summed in ascending order of a_k = min(am_k, ap_k)
- *            (ties in axis order): fl(fl(T_(0) + T_(1)) + T_(2)),
+ *   S(r)   = the T_k summed largest first: fl(fl(T_hi + T_mid) + T_lo),
  *   c      = fl(s * s), s the slowness (fl(1 / v) for a speed field),
  *   result = the smallest binary64 r >= min_k a_k with S(r) >= c.
- * Every operation is monotone in r and anti-monotone in each neighbour value,
- * so S is too, and the result is monotone and causal: Theorem 1 applies.  With
- * unit spacing, m_k = fl(r - a_k) and the definition is the uniform one with
- * h = 1 bit for bit; with any power-of-two spacing it is the uniform one
- * scaled exactly. */
+ * Each T_k is monotone in r and anti-monotone in its neighbour values.  The
+ * largest-first sum is a symmetric function of the three terms that is
+ * monotone in each of them (within one ordering of the terms it is a chain of
+ * rounded additions; where two terms are equal both orderings give the same
+ * bits), so S is monotone in r and anti-monotone in every neighbour, and the
+ * result is monotone and causal: Theorem 1 applies.  (Ordering the terms by
+ * their neighbour values instead, as the uniform operator may, is not
+ * monotone here: with unequal weights that order is not the order of the
+ * terms, and a one-ulp change of a neighbour that swaps it can move the sum
+ * the wrong way.)  With unit spacing, m_k = fl(r - a_k), the largest term is
+ * that of the smallest a_k, and the definition is the uniform one with h = 1
+ * bit for bit; with any power-of-two spacing it is the uniform one scaled
+ * exactly. */
 
 typedef struct {
     const double *wm[3], *wp[3];   /* per axis and index: 1 / spacing to the minus / plus side */
@@ -172,7 +179,7 @@ static double rect_term(double r, double am, double ap, double wm, double wp) {
     return m > 0.0 ? m * m : 0.0;
 }
 
-/* axes in ascending order of a_k (ties: axis order) */
+/* axes in ascending order of a_k (ties: axis order), for the guess */
 static void rect_order(const double a[3], int ord[3]) {
     ord[0] = 0; ord[1] = 1; ord[2] = 2;
     for (int i = 1; i < 3; ++i)
@@ -182,14 +189,16 @@ static void rect_order(const double a[3], int ord[3]) {
 }
 
 static int reaches_rect(double r, const double am[3], const double ap[3], const double wm[3],
-                        const double wp[3], const int ord[3], double c) {
+                        const double wp[3], double c) {
     double T[3];
-    for (int j = 0; j < 3; ++j) {
-        int k = ord[j];
-        T[j] = rect_term(r, am[k], ap[k], wm[k], wp[k]);
-    }
-    double s = T[0] + T[1];
-    s = s + T[2];
+    for (int k = 0; k < 3; ++k) T[k] = rect_term(r, am[k], ap[k], wm[k], wp[k]);
+    /* largest first: put the smallest term last */
+    int lo = 0;
+    for (int k = 1; k < 3; ++k)
+        if (T[k] < T[lo]) lo = k;
+    const double p = T[(lo + 1) % 3], q = T[(lo + 2) % 3];
+    double s = p + q;
+    s = s + T[lo];
     return s >= c;
 }
 
@@ -228,12 +237,12 @@ double orc_dbar_rect(const double am[3], const double ap[3], const double wm[3],
     else if (!(g < INFINITY)) G = INF;
     else G = bits_of(g);
     uint64_t L, H;
-    if (reaches_rect(double_of(G), am, ap, wm, wp, ord, c)) {
+    if (reaches_rect(double_of(G), am, ap, wm, wp, c)) {
         H = G;
         uint64_t step = 1;
         for (;;) {
             L = (H - A0 > step) ? G - step : A0;
-            if (L == A0 || !reaches_rect(double_of(L), am, ap, wm, wp, ord, c)) break;
+            if (L == A0 || !reaches_rect(double_of(L), am, ap, wm, wp, c)) break;
             H = L;
             step <<= 1;
         }
@@ -242,14 +251,14 @@ double orc_dbar_rect(const double am[3], const double ap[3], const double wm[3],
         uint64_t step = 1;
         for (;;) {
             H = (INF - G > step) ? G + step : INF;
-            if (H == INF || reaches_rect(double_of(H), am, ap, wm, wp, ord, c)) break;
+            if (H == INF || reaches_rect(double_of(H), am, ap, wm, wp, c)) break;
             L = H;
             step <<= 1;
         }
     }
     while (H - L > 1) {
         uint64_t M = L + (H - L) / 2;
-        if (reaches_rect(double_of(M), am, ap, wm, wp, ord, c)) H = M; else L = M;
+        if (reaches_rect(double_of(M), am, ap, wm, wp, c)) H = M; else L = M;
     }
     return double_of(H);
 }
@@ -257,11 +266,7 @@ double orc_dbar_rect(const double am[3], const double ap[3], const double wm[3],
 /* Exported single predicate evaluation, for tests. */
 int orc_reaches_rect(double r, const double am[3], const double ap[3], const double wm[3],
                      const double wp[3], double c) {
-    double a[3];
-    for (int k = 0; k < 3; ++k) a[k] = am[k] <= ap[k] ? am[k] : ap[k];
-    int ord[3];
-    rect_order(a, ord);
-    return reaches_rect(r, am, ap, wm, wp, ord, c);
+    return reaches_rect(r, am, ap, wm, wp, c);
 }
 
 /* The two explicit 2D formulas the paper analyses, with q = fl(h/v), c = fl(q*q).

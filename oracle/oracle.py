@@ -284,8 +284,8 @@ def _arr3(v):
 
 def dbar_rect(am, ap, wm, wp, c: float) -> float:
     """Smallest binary64 r >= min(a) with S(r) >= c, S summing per axis the
-    square of max(fl(fl(r - am)*wm), fl(fl(r - ap)*wp), 0) in ascending order
-    of min(am, ap) (up to three axes; missing axes are +inf with weight 1)."""
+    square of max(fl(fl(r - am)*wm), fl(fl(r - ap)*wp), 0), largest term first
+    (up to three axes; missing axes are +inf with weight 1)."""
     w1 = lambda v: (_d * 3)(*([float(x) for x in v] + [1.0] * (3 - len(v))))
     return lib().orc_dbar_rect(_arr3(am), _arr3(ap), w1(wm), w1(wp), float(c))
 

@@ -502,6 +502,14 @@ int forward_seq(const Bufs& b, const ProbTable& T, int64_t nsrc, int64_t ntiles,
             kern = count ? (const void*)k_solve<TX, TY, TZ, nt, OP, true>
                          : (const void*)k_solve<TX, TY, TZ, nt, OP>;
         }
+    } else if constexpr (OP == 4) {
+        // the rectilinear operator holds both neighbours and weights of each
+        // axis: in 3D it does not fit the 128 registers of a 1024-thread
+        // block, so 3D tiles run on blocks of at most 512 threads with the
+        // register budget of two waves per SIMD
+        constexpr int ntr = (TZ > 1 && nt > 512) ? 512 : nt;
+        threads = ntr;
+        kern = (const void*)k_solve<TX, TY, TZ, ntr, OP>;
     } else {
         kern = (const void*)k_solve<TX, TY, TZ, nt, OP>;
     }

@@ -332,7 +332,8 @@ __device__ __forceinline__ void st_flags(uint8_t* f, uint32_t v) {
 // threads (three blocks per compute unit) and four with larger blocks (two
 // 512-thread blocks or one 1024-thread block per compute unit).
 template <int TX, int TY, int TZ, int NT, int OP = 0, bool COUNT = false, bool PACK = false>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 256 ? 4 : 3))) k_solve(SolveArgs A) {
+__global__ void __launch_bounds__(NT)
+    __attribute__((amdgpu_waves_per_eu(OP == 4 && TZ > 1 && NT == 512 ? 2 : (NT > 256 ? 4 : 3)))) k_solve(SolveArgs A) {
     using C = TileCfg<TX, TY, TZ, NT>;
     constexpr int NPT = C::NPT;
     static_assert(NPT == 1 || NPT == 2 || NPT == 4, "1, 2 or 4 points per thread");
@@ -346,6 +347,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 25
     // store without branching
     __shared__ __align__(4) uint8_t sDirty[2][C::NP + NT];
     __shared__ int s_more[3];  // per pass (mod 3): some wave marked a point
+    // rectilinear grids: the tile's reciprocal spacings, [wm_x | wp_x | wm_y |
+    // wp_y | wm_z | wp_z] over its TX, TY, TZ coordinates
+    __shared__ double sW[OP == 4 ? 2 * (TX + TY + TZ) : 1];
     __shared__ int s_tile;
     __shared__ int64_t s_bucket;
     __shared__ uint32_t s_state;
@@ -464,19 +468,28 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 25
         double t_in[NPT];   // the values staged (what the run started from)
         double t_own[NPT];  // the thread's points' current values
         double q_own[NPT];  // and their constants (0: not relaxed)
-        double w_own[OP == 4 ? NPT : 1][6];  // rectilinear grids: reciprocal spacings to the six neighbours
         if constexpr (OP == 4) {
-#pragma unroll
-            for (int j = 0; j < NPT; ++j) {
-                const int p = tid + j * NT;
-                const int x = min(x0 + p % TX, P.nx - 1), y = min(y0 + (p / TX) % TY, P.ny - 1);
-                const int z = min(z0 + p / (TX * TY), P.nz - 1);
-                w_own[j][0] = A.rw[x];
-                w_own[j][1] = A.rw[P.nx + x];
-                w_own[j][2] = A.rw[2 * P.nx + y];
-                w_own[j][3] = A.rw[2 * P.nx + P.ny + y];
-                w_own[j][4] = C::D3 ? A.rw[2 * (P.nx + P.ny) + z] : 1.0;
-                w_own[j][5] = C::D3 ? A.rw[2 * (P.nx + P.ny) + P.nz + z] : 1.0;
+            // the weights of the tile's coordinates (clamped past the grid's
+            // end, where no point is relaxed); read-only, ordered for the
+            // relaxation by the barrier that ends the stage
+            constexpr int NW = 2 * (TX + TY + TZ);
+            for (int w = tid; w < NW; w += NT) {
+                int k = w, axis = 0;
+                if (k >= 2 * TX) {
+                    k -= 2 * TX;
+                    axis = 1;
+                    if (k >= 2 * TY) {
+                        k -= 2 * TY;
+                        axis = 2;
+                    }
+                }
+                const int n = axis == 0 ? TX : (axis == 1 ? TY : TZ);
+                const int side = k >= n ? 1 : 0;
+                const int i = k - side * n;
+                const int g0 = axis == 0 ? x0 : (axis == 1 ? y0 : z0);
+                const int gn = axis == 0 ? P.nx : (axis == 1 ? P.ny : P.nz);
+                const int base = axis == 0 ? 0 : (axis == 1 ? 2 * P.nx : 2 * (P.nx + P.ny));
+                sW[w] = A.rw[base + side * gn + min(g0 + i, gn - 1)];
             }
         }
         uint32_t live = 0;  // bit j: point j is in the grid and not a source
@@ -777,7 +790,10 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 25
                                 r = update<C::D3>(ax, ay, az, q, q * q, tc, ch);
                             } else {
                                 const double nb6[6] = {nxm, nxp, nym, nyp, nzm, nzp};
-                                r = update_rect<C::D3>(nb6, w_own[j], q * q, tc, ch);
+                                const double w6[6] = {sW[lx], sW[TX + lx], sW[2 * TX + ly], sW[2 * TX + TY + ly],
+                                                      C::D3 ? sW[2 * (TX + TY) + lz] : 1.0,
+                                                      C::D3 ? sW[2 * (TX + TY) + TZ + lz] : 1.0};
+                                r = update_rect<C::D3>(nb6, w6, q * q, tc, ch);
                             }
                             // held back: its bucket lies at or beyond the horizon (a
                             // value whose bucket index overflows the range is settled

@@ -199,26 +199,21 @@ __device__ __forceinline__ double update(double x, double y, double z, double q,
 // them (w = fl(1 / fl(x_i - x_{i-1})) and likewise on the plus side):
 //   m_k(r) = max(fl(fl(r - am) * wm), fl(fl(r - ap) * wp)),
 //   T_k(r) = fl(m_k * m_k) when m_k > 0, else +0,
-//   S(r)   = the T_k summed in ascending order of a_k = min(am, ap), ties in
-//            axis order: fl(fl(T0 + T1) + T2),
+//   S(r)   = the T_k summed largest first: fl(fl(T_hi + T_mid) + T_lo),
 //   result = the smallest binary64 r >= min_k a_k with S(r) >= c,
-// c = fl(s * s) for the slowness s.  Each step is monotone in r and
-// anti-monotone in the neighbours, so the result is monotone and causal
-// (the construction of section "Achieving Exact Monotonicity with Finite
-// Precision Arithmetic" applied to the irregular-grid scheme).  With unit
-// spacing it is the uniform operator bit for bit.
+// c = fl(s * s) for the slowness s.  Each T_k is monotone in r and
+// anti-monotone in its neighbours, and the largest-first sum is symmetric and
+// monotone in each term, so the result is monotone and causal (the
+// construction of section "Achieving Exact Monotonicity with Finite Precision
+// Arithmetic" applied to the irregular-grid scheme).  The order of the
+// neighbour values would not do here: with unequal weights it is not the
+// order of the terms, and a swap can move the sum the wrong way.  With unit
+// spacing the largest term is that of the smallest neighbour and the operator
+// is the uniform one bit for bit.
 
 struct RAxis {
-    double a, am, ap, wm, wp;  // a = min(am, ap)
+    double am, ap, wm, wp;  // the two neighbours and the reciprocal spacings to them
 };
-
-__device__ __forceinline__ void rswap(RAxis& x, RAxis& y) {
-    // stable: only a strictly smaller key moves forward
-    const bool s = y.a < x.a;
-    const RAxis lo = s ? y : x, hi = s ? x : y;
-    x = lo;
-    y = hi;
-}
 
 __device__ __forceinline__ double rterm(double r, const RAxis& k) {
     const double d1 = (r - k.am) * k.wm;
@@ -227,95 +222,123 @@ __device__ __forceinline__ double rterm(double r, const RAxis& k) {
     return m > 0.0 ? m * m : 0.0;
 }
 
+// The predicate is symmetric in the axes, so they come in grid order.
 template <bool D3>
 __device__ __forceinline__ bool reaches_rect(double r, const RAxis& x0, const RAxis& x1, const RAxis& x2, double c) {
-    double s = rterm(r, x0) + rterm(r, x1);
-    if constexpr (D3) s = s + rterm(r, x2);
-    return s >= c;
+    const double t0 = rterm(r, x0), t1 = rterm(r, x1);
+    if constexpr (D3) {
+        // the terms are >= +0 and never NaN; the smallest goes last
+        const double t2 = rterm(r, x2);
+        const double lo01 = fmin(t0, t1), hi01 = fmax(t0, t1);
+        const double lo = fmin(lo01, t2);
+        const double mid = fmax(lo01, t2);
+        return (hi01 + mid) + lo >= c;
+    } else {
+        return t0 + t1 >= c;
+    }
 }
 
-// Serial search for the rare inputs whose guess misses the window (unit
-// steps from G, then bisection with reaches(L) false, reaches(H) true).
+// Search for the rare inputs whose guess misses the window: steps of doubling
+// size from G until the predicate flips, then bisection between the last two
+// points (reaches(L) false, reaches(H) true; reaches(A0) is false since
+// c > 0, and reaches(tcb - 1) is true when called).
 template <bool D3>
 __device__ __noinline__ double search_slow_rect(const RAxis x0, const RAxis x1, const RAxis x2, double c,
                                                 uint64_t A0, uint64_t G, uint64_t tcb) {
     uint64_t L, H;
-    bool ok = false;
     if (reaches_rect<D3>(as_f64(G), x0, x1, x2, c)) {
         H = G;
-        for (int i = 0; i < 4; ++i) {
-            uint64_t P = H - 1;
-            if (P == A0 || !reaches_rect<D3>(as_f64(P), x0, x1, x2, c)) { ok = true; break; }
+        L = A0;
+        for (uint64_t step = 1; H - A0 > step; step <<= 1) {
+            const uint64_t P = H - step;
+            if (!reaches_rect<D3>(as_f64(P), x0, x1, x2, c)) { L = P; break; }
             H = P;
         }
-        L = A0;
     } else {
         L = G;
         H = tcb - 1;
-        for (int i = 0; i < 4; ++i) {
-            uint64_t N = L + 1;
-            if (reaches_rect<D3>(as_f64(N), x0, x1, x2, c)) { H = N; ok = true; break; }
+        for (uint64_t step = 1; tcb - 1 - L > step; step <<= 1) {
+            const uint64_t N = L + step;
+            if (reaches_rect<D3>(as_f64(N), x0, x1, x2, c)) { H = N; break; }
             L = N;
         }
     }
-    if (!ok) {
-        while (H - L > 1) {
-            uint64_t M = L + ((H - L) >> 1);
-            if (reaches_rect<D3>(as_f64(M), x0, x1, x2, c)) H = M; else L = M;
-        }
+    while (H - L > 1) {
+        const uint64_t M = L + ((H - L) >> 1);
+        if (reaches_rect<D3>(as_f64(M), x0, x1, x2, c)) H = M; else L = M;
     }
     return as_f64(H);
+}
+
+// (a, w) pairs in ascending a: the guess adds axes in that order
+__device__ __forceinline__ void pswap(double& a0, double& w0, double& a1, double& w1) {
+    const bool s = a1 < a0;
+    const double la = s ? a1 : a0, lw = s ? w1 : w0, ha = s ? a0 : a1, hw = s ? w0 : w1;
+    a0 = la;
+    w0 = lw;
+    a1 = ha;
+    w1 = hw;
 }
 
 // The rectilinear operator; returns the new value if it is < tcur, else tcur.
 // n[6] = neighbours x-, x+, y-, y+, z-, z+ (+inf off the grid), w[6] the
 // reciprocal spacings to them, c = fl(q * q).  The guess is the real root of
 // sum_k w_k^2 (r - a_k)^2 = c over the upwind axes, each with the weight of
-// its smaller neighbour; the predicate at G-1, G, G+1 decides as for d-bar.
+// its smaller neighbour, solved for u = r - a0 with b_k = a_k - a0 (the
+// unshifted quadratic cancels badly when the a_k are close relative to their
+// size); the predicate at G-1, G, G+1 decides as for d-bar.
 template <bool D3 = true>
 __device__ __forceinline__ double update_rect(const double* n, const double* w, double c, double tcur,
                                               bool& changed) {
     changed = false;
-    RAxis x0{fmin(n[0], n[1]), n[0], n[1], w[0], w[1]};
-    RAxis x1{fmin(n[2], n[3]), n[2], n[3], w[2], w[3]};
-    RAxis x2{inf64(), inf64(), inf64(), 1.0, 1.0};
-    if constexpr (D3) x2 = RAxis{fmin(n[4], n[5]), n[4], n[5], w[4], w[5]};
-    rswap(x0, x1);
+    const RAxis X{n[0], n[1], w[0], w[1]};
+    const RAxis Y{n[2], n[3], w[2], w[3]};
+    const RAxis Z = D3 ? RAxis{n[4], n[5], w[4], w[5]} : RAxis{inf64(), inf64(), 1.0, 1.0};
+    double s0 = fmin(n[0], n[1]), v0 = n[0] <= n[1] ? w[0] : w[1];
+    double s1 = fmin(n[2], n[3]), v1 = n[2] <= n[3] ? w[2] : w[3];
+    double s2 = inf64(), v2 = 1.0;
     if constexpr (D3) {
-        rswap(x1, x2);
-        rswap(x0, x1);
+        s2 = fmin(n[4], n[5]);
+        v2 = n[4] <= n[5] ? w[4] : w[5];
     }
-    const double a0 = x0.a;
+    pswap(s0, v0, s1, v1);
+    if constexpr (D3) {
+        pswap(s1, v1, s2, v2);
+        pswap(s0, v0, s1, v1);
+    }
+    const double a0 = s0;
     const uint64_t tcb = as_u64(tcur);
-    const bool can = (a0 < tcur) & reaches_rect<D3>(as_f64(tcb - 1), x0, x1, x2, c);
+    const bool can = (a0 < tcur) & reaches_rect<D3>(as_f64(tcb - 1), X, Y, Z, c);
     // guess: add axes while the root lies above the next minimum
-    double A = 0.0, B = 0.0, C = -c, g = inf64();
+    double A = 0.0, B = 0.0, C = -c, u = inf64();
     bool go = true;
 #pragma unroll
     for (int j = 0; j < (D3 ? 3 : 2); ++j) {
-        const RAxis& k = j == 0 ? x0 : (j == 1 ? x1 : x2);
-        const double wk = k.am <= k.ap ? k.wm : k.wp;
-        const double nxt = j == 0 ? x1.a : (j == 1 ? x2.a : inf64());
-        if (go && k.a < inf64()) {
+        const double ak = j == 0 ? s0 : (j == 1 ? s1 : s2);
+        const double wk = j == 0 ? v0 : (j == 1 ? v1 : v2);
+        const double nxt = (j == 0 ? s1 : (j == 1 ? s2 : inf64())) - a0;
+        if (go && ak < inf64()) {
+            const double b = ak - a0;
             const double w2 = wk * wk;
             A = A + w2;
-            B = B + w2 * k.a;
-            C = C + (w2 * k.a) * k.a;
+            B = B + w2 * b;
+            C = C + (w2 * b) * b;
             const double disc = B * B - A * C;
-            g = (B + __builtin_sqrt(fmax(disc, 0.0))) / A;
-            go = g > nxt;
+            u = (B + __builtin_sqrt(fmax(disc, 0.0))) / A;
+            go = u > nxt;
         }
     }
+    const double g = a0 + u;
     const uint64_t A0 = as_u64(a0);
     uint64_t G = as_u64(g);
     if (!(G >= A0 + 2)) G = A0 + 2;
     if (G > tcb - 1) G = tcb - 1;
     int cnt = 0;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) cnt += reaches_rect<D3>(as_f64(G - 1 + (uint64_t)k), x0, x1, x2, c) ? 1 : 0;
+    for (int k = 0; k < 3; ++k) cnt += reaches_rect<D3>(as_f64(G - 1 + (uint64_t)k), X, Y, Z, c) ? 1 : 0;
     if (!can) return tcur;
     changed = true;
-    if (cnt == 0 || cnt == 3) return search_slow_rect<D3>(x0, x1, x2, c, A0, G, tcb);
+    if (cnt == 0 || cnt == 3) return search_slow_rect<D3>(X, Y, Z, c, A0, G, tcb);
     return as_f64(G + 2 - (uint64_t)cnt);
 }
 

@@ -11,6 +11,11 @@ sampled shots the oracle computes one by one.
   persistent forward launch and one adjoint launch; one sampled shot of each
   size (two of 128^3) checked the same way, and every ninth shot through the
   oracle's residual on a host copy (zero, hence the unique fixed point).
+* Run-to-run determinism at full size: five solves of the 512x512x256
+  layered benchmark in its tuned launch configuration (the first against the
+  oracle's stored hash), and three graph replays of the tomography step, all
+  bit for bit equal (Theorem 1 makes any schedule reach the same state, so a
+  difference would expose a lost or torn update between workgroups).
 * The paper's grid shape, 2D 11204 x 54404 (609M points, folded layers): a
   scaled-down version of the same recipe bitwise against the oracle, and the
   full size through the oracle's residual on a host copy of the GPU result.
@@ -90,6 +95,55 @@ def test_tomography_full_batch(gpu, O):
         got = gv[i].cpu().numpy()
         if not np.array_equal(got, ref_grad):
             assert rel_err(got, ref_grad) <= 1e-12, f"shot {i} gradient"
+
+
+def test_full_size_determinism(gpu, O):
+    import hashlib
+    import json
+    import os
+    from paper_2103_05694_amd.batch import ShotBatch
+    p = W.layered_3d()
+    with open(os.path.join(os.path.dirname(__file__), "golden", "layered_512x512x256_seed2.json")) as fh:
+        golden = json.load(fh)
+    assert p.sha256() == golden["input_sha256_16"]
+    from paper_2103_05694_amd import autotune
+    c = autotune.lookup(p.field.shape, "speed") or {}
+    cfg = dict(tile=tuple(c.get("tile", (8, 8, 8))), delta=c.get("delta", 0.02), grid_blocks=int(c.get("grid_blocks", 0)),
+               horizon=int(c.get("horizon", 0)), packed=bool(c.get("packed", False)))
+    f = torch.from_numpy(p.field).cuda()
+    src = torch.as_tensor(p.src)
+    t1 = gpu.solve(f, p.h, src, **cfg)
+    h = hashlib.sha256(np.ascontiguousarray(t1.cpu().numpy(), dtype="<f8").tobytes()).hexdigest()
+    assert h == golden["times_sha256"]
+    t = torch.empty_like(t1)
+    for k in range(4):
+        gpu.solve(f, p.h, src, out=t, **cfg)
+        assert torch.equal(t, t1), f"full-size solve {k + 2} differs"
+    del f, t, t1
+    case = W.tomography(256, 256, 128, nshots=32, seed=5)
+    tcfg = tuned((128, 256, 256), "slowness", (16, 8, 8), 0.02)
+    rec = torch.as_tensor(case.receivers).cuda()
+    srcs = [torch.tensor([int(s)]) for s in case.sources]
+    obs = ShotBatch([torch.from_numpy(case.s_true).cuda()] * 32, case.h, srcs, [rec] * 32, kind="slowness", **tcfg)
+    obs.step()
+    obs.sync()
+    gpu.status(obs.stream)
+    t_obs = [v.reshape(-1).index_select(0, rec).clone() for v in obs.shot_views(obs.t)]
+    del obs
+    sb = ShotBatch([torch.from_numpy(case.s0).cuda()] * 32, case.h, srcs, [rec] * 32, t_obs=t_obs,
+                   kind="slowness", **tcfg)
+    sb.capture()
+    first = None
+    for k in range(3):
+        sb.replay()
+        sb.sync()
+        gpu.status(sb.stream)
+        got = (sb.t.clone(), sb.par.clone(), sb.grad.clone())
+        if first is None:
+            first = got
+        else:
+            for a_, b_, what in zip(got, first, ("times", "parents", "gradient")):
+                assert torch.equal(a_, b_), f"tomography replay {k + 1}: {what} differ"
 
 
 def test_uneven_full_batch(gpu, O):

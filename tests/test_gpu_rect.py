@@ -119,7 +119,8 @@ def test_schedule_options_and_warm_start(gpu, O):
 
 def test_medium_grid_residual_is_zero(gpu, O):
     """96x80x64 stretched grid with many tiles: the oracle re-applies the
-    operator at every point of the GPU result and finds nothing to change."""
+    operator at every point of the GPU result and finds nothing to change, and
+    the result is the oracle's fast marching bit for bit."""
     rng = np.random.default_rng(9)
     f = W.random_field((64, 80, 96), rng, 1500.0, 6000.0, block=8)
     xs, ys, zs = W.stretched_coords(96, 5.0, 1.01), W.jittered_coords(80, 8.0, rng), W.stretched_coords(64, 2.0, 1.03)
@@ -127,6 +128,7 @@ def test_medium_grid_residual_is_zero(gpu, O):
     t = gpu_rect(gpu, f, xs, ys, zs, src, delta=0.002)
     assert np.all(np.isfinite(t))
     assert O.residual_rect(t, f, xs, ys, zs, src) == (0, 0.0)
+    assert_bitwise(t, O.solve_rect(f, xs, ys, zs, src), "96x80x64 stretched")
 
 
 def test_bad_coordinates_raise(gpu):

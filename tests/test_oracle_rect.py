@@ -14,6 +14,11 @@ case the conclusion names).  Pinned by:
 * the search against a plain bisection of the predicate over the whole range
   of doubles, and monotonicity / causality of the predicate's root under
   perturbations of each input;
+* the order of the sum: S adds the squared terms largest first, a symmetric
+  function, so permuting the axes (neighbours and weights together) never
+  changes the result, ties included; and one-ulp changes of a neighbour that
+  swap two axes near a source never raise the result (ordering the terms by
+  their neighbour values instead fails this fuzz);
 * closed forms and limits: a stretched 1-D line accumulates h_i / v, and a
   point source on stretched grids converges to r / v at first order.
 """
@@ -135,6 +140,45 @@ def test_operator_is_the_smallest_root_and_monotone(O):
         for k in range(nax):
             if am[k] >= r:
                 assert O.dbar_rect(am[:k] + [np.inf] + am[k + 1:], ap, wm, wp, c) == r
+
+
+def test_result_is_invariant_under_axis_permutation(O):
+    import itertools
+    rng = np.random.default_rng(31)
+    for trial in range(400):
+        scale = 10.0 ** rng.uniform(-5, 1)
+        am = list(rng.uniform(0.0, 1.0, 3) * scale)
+        ap = list(rng.uniform(0.0, 1.0, 3) * scale)
+        if trial % 2:   # exact ties between axes, with different weights
+            am[1] = am[0]
+            ap[1] = ap[0] = np.inf
+            ap[2] = am[0] if trial % 4 == 1 else ap[2]
+        wm = list(10.0 ** rng.uniform(-2, 2, 3))
+        wp = list(10.0 ** rng.uniform(-2, 2, 3))
+        c = float((scale * rng.uniform(0.2, 3.0)) ** 2 * 10.0 ** rng.uniform(-2, 2))
+        ref = O.dbar_rect(am, ap, wm, wp, c)
+        for perm in itertools.permutations(range(3)):
+            pa = lambda v: [v[k] for k in perm]
+            assert O.dbar_rect(pa(am), pa(ap), pa(wm), pa(wp), c) == ref, (trial, perm)
+
+
+def test_one_ulp_swaps_near_a_source_never_raise_the_result(O):
+    """Lower a neighbour by two ulps so that it passes another axis's value:
+    the terms change by about as much as one rounding of the sum, which is
+    where a sum ordered by neighbour values goes the wrong way."""
+    rng = np.random.default_rng(3)
+    for trial in range(20000):
+        scale = 10.0 ** rng.uniform(-6, 0)
+        a = list(rng.uniform(0.0, 1.0, 3) * scale)
+        k, j = rng.choice(3, 2, replace=False)
+        a[k] = float(np.nextafter(a[j], 2.0))
+        wm = list(10.0 ** rng.uniform(-2, 2, 3))
+        inf3 = [np.inf] * 3
+        c = float((scale * rng.uniform(0.2, 3.0)) ** 2 * 10.0 ** rng.uniform(-2, 2))
+        r = O.dbar_rect(a, inf3, wm, [1.0] * 3, c)
+        lower = list(a)
+        lower[k] = float(np.nextafter(a[j], 0.0))
+        assert O.dbar_rect(lower, inf3, wm, [1.0] * 3, c) <= r, trial
 
 
 def test_stretched_line_accumulates_spacing_over_speed(O):
