@@ -127,11 +127,12 @@ __device__ __noinline__ double search_slow(double a0, double a1, double a2, doub
 // Preconditions: q > 0, c = fl(q*q) in (0, inf), tcur >= 0 (may be +inf).
 // `x`, `y`, `z` are the axis minima in any order (+inf where absent).
 //
-// First r < tcur  <=>  S(prev(tcur)) >= c (S is monotone), so one predicate
-// rejects every non-improving update.  Then the predicate is evaluated at
-// G-1, G, G+1 around the guess G as three independent chains; the answer is G
-// or G+1 when it is the first of them that satisfies it while the one below
-// does not.  (Measured over whole solves, the guess is never more than one
+// The predicate is evaluated at G-1, G, G+1 around the guess G as three
+// independent chains; the answer is G or G+1 when it is the first of them
+// that satisfies it while the one below does not, and comparing it with tcur
+// decides whether the point improves (first r < tcur <=> S(prev(tcur)) >= c,
+// since S is monotone, which is evaluated only when the window lies wholly
+// below the answer).  (Measured over whole solves, the guess is never more than one
 // ulp below the answer and never above it, so this window decides every
 // case; the serial search covers the rest.)  G is clamped to
 // [A0 + 2, prev(tcur)], so G - 1 > A0.
@@ -154,11 +155,6 @@ __device__ __forceinline__ double update(double x, double y, double z, double q,
         a2 = inf64();
     }
     const uint64_t tcb = as_u64(tcur);
-    // Whether the point can improve at all: its value would be > a0 >= tcur,
-    // or S(prev(tcur)) < c.  Both tests and the guess below are independent,
-    // so they are computed side by side (the improving case, which dominates
-    // a relaxation, then waits for one chain instead of two).
-    const bool can = (a0 < tcur) & reaches<D3>(as_f64(tcb - 1), a0, a1, a2, c);
     const uint64_t A0 = as_u64(a0);
     uint64_t G = as_u64(guess<D3>(a0, a1, a2, q, c));
     if (!(G >= A0 + 2)) G = A0 + 2;                // also catches a NaN pattern
@@ -185,11 +181,20 @@ __device__ __forceinline__ double update(double x, double y, double z, double q,
     int cnt = 0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) cnt += sm[k] >= c ? 1 : 0;
-    if (!can) return tcur;
-    // reaches(tcb - 1) is false whenever tcb - 1 <= A0, so here tcb - 1 > A0
+    // Nothing lies below tcur when a0 >= tcur (the answer exceeds a0).
+    // Otherwise the window decides whether the answer is below tcur: with
+    // cnt 1 or 2 it is G + 2 - cnt itself; with 3 it is below G - 1 <= prev(tcur);
+    // with 0 it is above G + 1, so below tcur only if G + 1 < prev(tcur) and
+    // S(prev(tcur)) >= c -- then the search runs between G and prev(tcur).
+    if (!(a0 < tcur)) return tcur;
+    if (cnt == 1 || cnt == 2) {
+        const uint64_t ans = G + 2 - (uint64_t)cnt;
+        changed = ans < tcb;
+        return changed ? as_f64(ans) : tcur;
+    }
+    if (cnt == 0 && !(G + 1 < tcb - 1 && reaches<D3>(as_f64(tcb - 1), a0, a1, a2, c))) return tcur;
     changed = true;
-    if (cnt == 0 || cnt == 3) return search_slow(a0, a1, a2, c, A0, G, tcb);
-    return as_f64(G + 2 - (uint64_t)cnt);
+    return search_slow(a0, a1, a2, c, A0, G, tcb);
 }
 
 // ---------------------------------------------------------------------------
@@ -308,7 +313,6 @@ __device__ __forceinline__ double update_rect(const double* n, const double* w, 
     }
     const double a0 = s0;
     const uint64_t tcb = as_u64(tcur);
-    const bool can = (a0 < tcur) & reaches_rect<D3>(as_f64(tcb - 1), X, Y, Z, c);
     // guess: add axes while the root lies above the next minimum
     double A = 0.0, B = 0.0, C = -c, u = inf64();
     bool go = true;
@@ -336,10 +340,17 @@ __device__ __forceinline__ double update_rect(const double* n, const double* w, 
     int cnt = 0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) cnt += reaches_rect<D3>(as_f64(G - 1 + (uint64_t)k), X, Y, Z, c) ? 1 : 0;
-    if (!can) return tcur;
+    // as for d-bar: the window decides, prev(tcur) is tested only when the
+    // answer lies above the window
+    if (!(a0 < tcur)) return tcur;
+    if (cnt == 1 || cnt == 2) {
+        const uint64_t ans = G + 2 - (uint64_t)cnt;
+        changed = ans < tcb;
+        return changed ? as_f64(ans) : tcur;
+    }
+    if (cnt == 0 && !(G + 1 < tcb - 1 && reaches_rect<D3>(as_f64(tcb - 1), X, Y, Z, c))) return tcur;
     changed = true;
-    if (cnt == 0 || cnt == 3) return search_slow_rect<D3>(X, Y, Z, c, A0, G, tcb);
-    return as_f64(G + 2 - (uint64_t)cnt);
+    return search_slow_rect<D3>(X, Y, Z, c, A0, G, tcb);
 }
 
 // The paper's two explicit two-dimensional formulas (the d-tilde and d-hat
