@@ -156,7 +156,6 @@ typedef struct {
                                 wall clock): [0] claiming / waiting for work, [1] staging a
                                 tile and its halo in LDS, [2] relaxing (adjoint: readiness
                                 passes), [3] write-back + publish */
-    double process_us;       /* part of phase_us[2] spent applying the operator to the pass lists */
     int64_t workgroups;      /* persistent workgroups of the last launch */
     int64_t bucket_advances; /* times the lowest open priority bucket moved on */
     int64_t handoffs;        /* runs that started on a neighbour handed on by the previous run */

@@ -57,7 +57,7 @@ class eik_stats(ctypes.Structure):
                 ("ntiles", ctypes.c_int64), ("relax_passes", ctypes.c_int64),
                 ("flags", ctypes.c_uint32), ("status", ctypes.c_int32),
                 ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_int64),
-                ("phase_us", ctypes.c_double * 4), ("process_us", ctypes.c_double),
+                ("phase_us", ctypes.c_double * 4),
                 ("workgroups", ctypes.c_int64), ("bucket_advances", ctypes.c_int64),
                 ("handoffs", ctypes.c_int64), ("evaluations", ctypes.c_int64), ("improving", ctypes.c_int64),
                 ("final_updates", ctypes.c_int64)]

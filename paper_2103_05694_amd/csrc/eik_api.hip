@@ -1143,7 +1143,6 @@ int eik_status(void* stream, eik_stats* out) {
         out->kernel_ms = -1.0;
         out->kernel_launches = w ? (int64_t)w->ev_used : 0;
         for (int i = 0; i < 4; ++i) out->phase_us[i] = (double)ctr[5 + i] / 100.0;  // 100 MHz clock
-        out->process_us = (double)ctr[9] / 100.0;
         out->workgroups = (int64_t)ctr[10];
         out->bucket_advances = (int64_t)ctr[11];
         out->handoffs = (int64_t)ctr[12];

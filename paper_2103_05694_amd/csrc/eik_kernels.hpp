@@ -368,7 +368,7 @@ __global__ void __launch_bounds__(NT)
     // per-workgroup statistics, flushed once at exit; the phase times use the
     // 100 MHz wall clock: [0] claim, [1] stage, [2] relax, [3] write + publish
     unsigned long long my_visits = 0, my_updates = 0, my_passes = 0, my_cont = 0;
-    unsigned long long ph[6] = {0, 0, 0, 0, 0, 0};
+    unsigned long long ph[4] = {0, 0, 0, 0};
     // per-wave work classification (with A.work_ref): operator evaluations,
     // those that lowered the value, those that set the final value
     unsigned long long w_eval = 0, w_imp = 0, w_good = 0;
@@ -663,8 +663,6 @@ __global__ void __launch_bounds__(NT)
                     }
                 }
                 __syncthreads();
-                unsigned long long tg = 0;
-                if (tid == 0) tg = wall_clock64();
                 const int n = s_cnt[cb];
                 if (n == 0) break;
                 // the other counter was last read before the previous barrier and is
@@ -731,7 +729,6 @@ __global__ void __launch_bounds__(NT)
                 }
                 ++passes;
                 __syncthreads();
-                if (tid == 0) ph[5] += wall_clock64() - tg;
                 cb ^= 1;
                 if (OP != 0 && OP != 4 && passes >= (1 << 16)) {  // an ablation operator may not settle
                     if (tid == 0) set_flag(S, kFlagLimit);
@@ -762,11 +759,7 @@ __global__ void __launch_bounds__(NT)
                 dirty &= live;
             }
             for (;;) {
-                unsigned long long tg = 0;
-                if (tid == 0) {
-                    tg = wall_clock64();
-                    s_more[(passes + 1) % 3] = 0;  // written next pass; last read two barriers ago
-                }
+                if (tid == 0) s_more[(passes + 1) % 3] = 0;  // written next pass; last read two barriers ago
                 bool marked = false;
                 uint8_t* nd = sDirty[cb ^ 1];
                 const int sink = C::NP + tid;
@@ -849,14 +842,17 @@ __global__ void __launch_bounds__(NT)
                 }
                 if (__ballot(marked) && lane == 0) s_more[passes % 3] = 1;
                 __syncthreads();
-                const bool more = s_more[passes % 3] != 0;
+                // the pass flag and the thread's next flags are read together
+                // (one LDS round trip); when nothing was marked the flags are
+                // all clear and the read is simply unused
+                uint8_t* df = sDirty[cb ^ 1] + tid * NPT;
+                const int more = s_more[passes % 3];
+                const uint32_t fl = ld_flags<NPT>(df);
+                asm volatile("" ::"v"(fl));  // keeps the flag read ahead of the branch
                 ++passes;
-                if (tid == 0) ph[5] += wall_clock64() - tg;
                 if (!more) break;
                 cb ^= 1;
                 {
-                    uint8_t* df = sDirty[cb] + tid * NPT;
-                    const uint32_t fl = ld_flags<NPT>(df);
                     dirty = 0;
     #pragma unroll
                     for (int j = 0; j < NPT; ++j) dirty |= ((fl >> (8 * j)) & 1u) << j;
@@ -974,7 +970,6 @@ __global__ void __launch_bounds__(NT)
         ph[0] += wall_clock64() - tm;
         for (int i = 0; i < 4; ++i)
             __hip_atomic_fetch_add(S.counters + 5 + i, ph[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(S.counters + 9, ph[5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(S.counters + 10, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(S.counters + 12, my_cont, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (S.timeline)

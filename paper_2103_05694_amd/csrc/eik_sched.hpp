@@ -69,7 +69,7 @@ __device__ __forceinline__ void stores_done() { asm volatile("s_waitcnt vmcnt(0)
 constexpr uint32_t kQ = 1u, kR = 2u, kV = 4u, kS = 8u;
 // statistics words (64-bit, cleared by every reset): [0] visits [1] point
 // updates [2] relax passes [3] visit-cap count [4] adjoint reference time
-// [5..8] phase clocks [9] operator clock [10] workgroups [11] bucket advances
+// [5..8] phase clocks [9] unused [10] workgroups [11] bucket advances
 // [12] hand-offs [13..15] residual accumulators [16] operator evaluations
 // [17] improving evaluations [18] evaluations that set the final value
 constexpr int kCounters = 24;
