@@ -248,6 +248,12 @@ def bench_single(args, torch, eik, W) -> dict:
         "output": {"status": int(st.status), "times_sha256": digest,
                    "oracle_sha256": golden["times_sha256"] if golden else None, "validated": validated},
     }
+    if traffic is not None:
+        # the counters' HBM bytes over the same mean duration, and their
+        # multiple of the algorithmic bytes (re-reads of re-run tiles, halos)
+        res["roofline"]["traffic_gbs"] = traffic / (kernel_ms * 1e-3) / 1e9
+        res["roofline"]["traffic_frac"] = res["roofline"]["traffic_gbs"] / HBM_PEAK_GBS
+        res["roofline"]["traffic_over_algorithmic"] = traffic / algo_bytes
     lat = latency_estimate(args, torch, eik, W, p.shape, (p.nx // 2, p.ny // 2, 0))
     res["roofline"].update(lat)
     res["roofline"]["latency_frac"] = lat["latency_bound_ms"] / kernel_ms

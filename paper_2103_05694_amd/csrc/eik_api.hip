@@ -690,6 +690,7 @@ int rect_weights(const eik_grid& g, const double* xs, const double* ys, const do
 // ones are there already, so repeated calls on one grid enqueue only kernels.
 int upload_weights(Workspace& w, const std::vector<double>& rw) {
     if (w.rw && w.rw_host == rw) return EIK_OK;
+    w.rw_host.clear();  // the device copy is stale until the upload below completes
     int rc;
     if ((rc = grow(&w.rw, &w.rw_cap, (int64_t)rw.size(), w.stream))) return rc;
     HIP_TRY(hipStreamSynchronize(w.stream));
