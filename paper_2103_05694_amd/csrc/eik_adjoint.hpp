@@ -576,15 +576,17 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 25
             }
             if (done_now && !(pn & 0x80)) {
                 ++ndone;
-                const double kt = tref - sT[L];
-                // a face point whose parent lies across that face unblocks the neighbour
-                if (lx == 0 && ((pn >> 0) & 3u) == 1u) fkey[0] = fmin(fkey[0], kt);
-                if (lx == TX - 1 && ((pn >> 0) & 3u) == 2u) fkey[1] = fmin(fkey[1], kt);
-                if (ly == 0 && ((pn >> 2) & 3u) == 1u) fkey[2] = fmin(fkey[2], kt);
-                if (ly == TY - 1 && ((pn >> 2) & 3u) == 2u) fkey[3] = fmin(fkey[3], kt);
+                // a face point whose parent lies across that face unblocks the
+                // neighbour; the neighbour is keyed by the parent's own time, the
+                // earliest bucket in which that parent can be taken (its other
+                // children, later in time, are then mostly done as well)
+                if (lx == 0 && ((pn >> 0) & 3u) == 1u) fkey[0] = fmin(fkey[0], tref - sT[L - 1]);
+                if (lx == TX - 1 && ((pn >> 0) & 3u) == 2u) fkey[1] = fmin(fkey[1], tref - sT[L + 1]);
+                if (ly == 0 && ((pn >> 2) & 3u) == 1u) fkey[2] = fmin(fkey[2], tref - sT[L - C::SY]);
+                if (ly == TY - 1 && ((pn >> 2) & 3u) == 2u) fkey[3] = fmin(fkey[3], tref - sT[L + C::SY]);
                 if (C::D3) {
-                    if (lz == 0 && ((pn >> 4) & 3u) == 1u) fkey[4] = fmin(fkey[4], kt);
-                    if (lz == TZ - 1 && ((pn >> 4) & 3u) == 2u) fkey[5] = fmin(fkey[5], kt);
+                    if (lz == 0 && ((pn >> 4) & 3u) == 1u) fkey[4] = fmin(fkey[4], tref - sT[L - C::SZ]);
+                    if (lz == TZ - 1 && ((pn >> 4) & 3u) == 2u) fkey[5] = fmin(fkey[5], tref - sT[L + C::SZ]);
                 }
             }
         }
