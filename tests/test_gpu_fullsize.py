@@ -16,6 +16,9 @@ sampled shots the oracle computes one by one.
   oracle's stored hash), and three graph replays of the tomography step, all
   bit for bit equal (Theorem 1 makes any schedule reach the same state, so a
   difference would expose a lost or torn update between workgroups).
+* The rectilinear leg of the benchmark (512x512x256, depth spacing stretched
+  5 -> 20 m) through the oracle's rectilinear residual on a host copy, and a
+  scaled-down grid of the same recipe bitwise against the oracle.
 * The paper's grid shape, 2D 11204 x 54404 (609M points, folded layers): a
   scaled-down version of the same recipe bitwise against the oracle, and the
   full size through the oracle's residual on a host copy of the GPU result.
@@ -217,3 +220,32 @@ def test_paper_scale_2d(gpu, O):
     assert np.all(np.isfinite(th))
     # the oracle re-applies the operator at all 609M points of the GPU result
     assert O.residual(th[None], p.field, p.h, p.src) == (0, 0.0)
+
+
+def test_rectilinear_full_size(gpu, O):
+    """The benchmark's rectilinear leg at full size (512x512x256, depth
+    spacing stretched 5 -> 20 m, 8x8x4 tiles, delta 0.01 s): the oracle's
+    rectilinear residual on a host copy is zero at every point (the unique
+    fixed point), a second solve is bitwise equal, and a scaled-down grid of
+    the same recipe equals the oracle's fast marching bit for bit."""
+    small = W.layered_3d(96, 80, 48, h=10.0, seed=2)
+    nz, ny, nx = small.field.shape
+    zs = W.stretched_coords(nz, 5.0, 4.0 ** (1.0 / (nz - 2)))
+    xs, ys = np.arange(nx) * small.h, np.arange(ny) * small.h
+    ref = O.solve_rect(small.field, xs, ys, zs, small.src)
+    t = gpu.solve_rect(torch.from_numpy(small.field).cuda(), xs, ys, zs, torch.as_tensor(small.src),
+                       tile=(8, 8, 4), delta=0.01)
+    assert np.array_equal(t.cpu().numpy(), ref), "scaled-down rectilinear grid"
+    p = W.layered_3d()
+    nz, ny, nx = p.field.shape
+    zs = W.stretched_coords(nz, 5.0, 4.0 ** (1.0 / (nz - 2)))
+    xs, ys = np.arange(nx) * p.h, np.arange(ny) * p.h
+    f = torch.from_numpy(p.field).cuda()
+    src = torch.as_tensor(p.src)
+    t1 = gpu.solve_rect(f, xs, ys, zs, src, tile=(8, 8, 4), delta=0.01)
+    t2 = gpu.solve_rect(f, xs, ys, zs, src, tile=(8, 8, 4), delta=0.01)
+    assert torch.equal(t1, t2), "repeat full-size rectilinear solve"
+    th = t1.cpu().numpy()
+    del f, t1, t2
+    assert np.all(np.isfinite(th))
+    assert O.residual_rect(th, p.field, xs, ys, zs, p.src) == (0, 0.0)
