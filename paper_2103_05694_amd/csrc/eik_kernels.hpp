@@ -301,7 +301,7 @@ __device__ __forceinline__ void tstore(double* p, double v) {
 // Minimum over the 64 lanes of a wave (every lane gets it).
 __device__ __forceinline__ double wave_min(double v) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+    for (int off = 32; off > 0; off >>= 1) v = nmin(v, __shfl_xor(v, off));
     return v;
 }
 
@@ -674,9 +674,9 @@ __global__ void __launch_bounds__(NT)
                     const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
                     const int L = C::lds(lx, ly, lz);
                     const double tc = sT[L];
-                    const double ax = fmin(sT[L - 1], sT[L + 1]);
-                    const double ay = fmin(sT[L - C::SY], sT[L + C::SY]);
-                    const double az = C::D3 ? fmin(sT[L - C::SZ], sT[L + C::SZ]) : inf64();
+                    const double ax = nmin(sT[L - 1], sT[L + 1]);
+                    const double ay = nmin(sT[L - C::SY], sT[L + C::SY]);
+                    const double az = C::D3 ? nmin(sT[L - C::SZ], sT[L + C::SZ]) : inf64();
                     bool ch, mark;
                     double r;
                     if constexpr (OP == 0) {
@@ -775,7 +775,7 @@ __global__ void __launch_bounds__(NT)
                         const double tc = t_own[j];
                         const double nxm = sT[L - 1], nxp = sT[L + 1], nym = sT[L - C::SY], nyp = sT[L + C::SY];
                         const double nzm = C::D3 ? sT[L - C::SZ] : inf64(), nzp = C::D3 ? sT[L + C::SZ] : inf64();
-                        const double ax = fmin(nxm, nxp), ay = fmin(nym, nyp), az = fmin(nzm, nzp);
+                        const double ax = nmin(nxm, nxp), ay = nmin(nym, nyp), az = nmin(nzm, nzp);
                         bool mark;
                         double r;
                         if constexpr (OP == 0 || OP == 4) {
@@ -897,13 +897,13 @@ __global__ void __launch_bounds__(NT)
                     // cell here, as staged; values only decrease): the
                     // operator ignores a neighbour above the point it updates
                     constexpr bool kAny = OP != 0 && OP != 4;  // not causal: every lowered face value
-                    if (lx == 0 && (kAny || v < nxm)) fmin_[0] = fmin(fmin_[0], v);
-                    if (lx == TX - 1 && (kAny || v < nxp)) fmin_[1] = fmin(fmin_[1], v);
-                    if (ly == 0 && (kAny || v < nym)) fmin_[2] = fmin(fmin_[2], v);
-                    if (ly == TY - 1 && (kAny || v < nyp)) fmin_[3] = fmin(fmin_[3], v);
+                    if (lx == 0 && (kAny || v < nxm)) fmin_[0] = nmin(fmin_[0], v);
+                    if (lx == TX - 1 && (kAny || v < nxp)) fmin_[1] = nmin(fmin_[1], v);
+                    if (ly == 0 && (kAny || v < nym)) fmin_[2] = nmin(fmin_[2], v);
+                    if (ly == TY - 1 && (kAny || v < nyp)) fmin_[3] = nmin(fmin_[3], v);
                     if (C::D3) {
-                        if (lz == 0 && (kAny || v < nzm)) fmin_[4] = fmin(fmin_[4], v);
-                        if (lz == TZ - 1 && (kAny || v < nzp)) fmin_[5] = fmin(fmin_[5], v);
+                        if (lz == 0 && (kAny || v < nzm)) fmin_[4] = nmin(fmin_[4], v);
+                        if (lz == TZ - 1 && (kAny || v < nzp)) fmin_[5] = nmin(fmin_[5], v);
                     }
                 } else if (OP != 0 && OP != 4 && v != t_in[j]) {
                     // an ablation operator raised the value: store it, and with
@@ -911,10 +911,10 @@ __global__ void __launch_bounds__(NT)
                     tstore(A.t + P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x, v);
                     chg |= 1u << j;
                     if (S.track) {
-                        if (lx == 0) fmin_[0] = fmin(fmin_[0], v);
-                        if (lx == TX - 1) fmin_[1] = fmin(fmin_[1], v);
-                        if (ly == 0) fmin_[2] = fmin(fmin_[2], v);
-                        if (ly == TY - 1) fmin_[3] = fmin(fmin_[3], v);
+                        if (lx == 0) fmin_[0] = nmin(fmin_[0], v);
+                        if (lx == TX - 1) fmin_[1] = nmin(fmin_[1], v);
+                        if (ly == 0) fmin_[2] = nmin(fmin_[2], v);
+                        if (ly == TY - 1) fmin_[3] = nmin(fmin_[3], v);
                     }
                 }
             }

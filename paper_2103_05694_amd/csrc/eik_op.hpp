@@ -47,12 +47,27 @@ __device__ __forceinline__ bool reaches(double r, double a0, double a1, double a
     return s >= c;
 }
 
+// Minimum and maximum of two doubles that are never NaN (arrival times and
+// the squared terms: non-negative or +inf).  fmin / fmax would first
+// canonicalise both operands for NaN semantics, two extra instructions per
+// call on the operator's critical path.
+__device__ __forceinline__ double nmin(double a, double b) {
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ double nmax(double a, double b) {
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 __device__ __forceinline__ void sort3(double& a0, double& a1, double& a2) {
-    double lo = fmin(a0, a1), hi = fmax(a0, a1);
-    double m = fmin(hi, a2);
-    a2 = fmax(hi, a2);
-    a0 = fmin(lo, m);
-    a1 = fmax(lo, m);
+    double lo = nmin(a0, a1), hi = nmax(a0, a1);
+    double m = nmin(hi, a2);
+    a2 = nmax(hi, a2);
+    a0 = nmin(lo, m);
+    a1 = nmax(lo, m);
 }
 
 // Square root for the estimate below: the hardware reciprocal square root
@@ -150,8 +165,8 @@ __device__ __forceinline__ double update(double x, double y, double z, double q,
         a2 = z;
         sort3(a0, a1, a2);
     } else {
-        a0 = fmin(x, y);
-        a1 = fmax(x, y);
+        a0 = nmin(x, y);
+        a1 = nmax(x, y);
         a2 = inf64();
     }
     const uint64_t tcb = as_u64(tcur);
@@ -223,7 +238,7 @@ struct RAxis {
 __device__ __forceinline__ double rterm(double r, const RAxis& k) {
     const double d1 = (r - k.am) * k.wm;
     const double d2 = (r - k.ap) * k.wp;
-    const double m = d1 > d2 ? d1 : d2;
+    const double m = nmax(d1, d2);
     return m > 0.0 ? m * m : 0.0;
 }
 
@@ -234,9 +249,9 @@ __device__ __forceinline__ bool reaches_rect(double r, const RAxis& x0, const RA
     if constexpr (D3) {
         // the terms are >= +0 and never NaN; the smallest goes last
         const double t2 = rterm(r, x2);
-        const double lo01 = fmin(t0, t1), hi01 = fmax(t0, t1);
-        const double lo = fmin(lo01, t2);
-        const double mid = fmax(lo01, t2);
+        const double lo01 = nmin(t0, t1), hi01 = nmax(t0, t1);
+        const double lo = nmin(lo01, t2);
+        const double mid = nmax(lo01, t2);
         return (hi01 + mid) + lo >= c;
     } else {
         return t0 + t1 >= c;
@@ -299,11 +314,11 @@ __device__ __forceinline__ double update_rect(const double* n, const double* w, 
     const RAxis X{n[0], n[1], w[0], w[1]};
     const RAxis Y{n[2], n[3], w[2], w[3]};
     const RAxis Z = D3 ? RAxis{n[4], n[5], w[4], w[5]} : RAxis{inf64(), inf64(), 1.0, 1.0};
-    double s0 = fmin(n[0], n[1]), v0 = n[0] <= n[1] ? w[0] : w[1];
-    double s1 = fmin(n[2], n[3]), v1 = n[2] <= n[3] ? w[2] : w[3];
+    double s0 = nmin(n[0], n[1]), v0 = n[0] <= n[1] ? w[0] : w[1];
+    double s1 = nmin(n[2], n[3]), v1 = n[2] <= n[3] ? w[2] : w[3];
     double s2 = inf64(), v2 = 1.0;
     if constexpr (D3) {
-        s2 = fmin(n[4], n[5]);
+        s2 = nmin(n[4], n[5]);
         v2 = n[4] <= n[5] ? w[4] : w[5];
     }
     pswap(s0, v0, s1, v1);
