@@ -821,14 +821,22 @@ __global__ void __launch_bounds__(NT)
                             // below r needs no look.  The ablation operators mark every
                             // neighbour.  Six unconditional stores, unwanted ones into
                             // this thread's sink byte (no divergent branches).
+                            // (the targets fold the tile's edge into the sink, so a
+                            // mark is one compare and one select)
                             constexpr bool kAll = OP != 0 && OP != 4;
-                            nd[(lx > 0 && (kAll || nxm > r)) ? didx<NT, NPT>(p - 1) : sink] = 1;
-                            nd[(lx < TX - 1 && (kAll || nxp > r)) ? didx<NT, NPT>(p + 1) : sink] = 1;
-                            nd[(ly > 0 && (kAll || nym > r)) ? didx<NT, NPT>(p - TX) : sink] = 1;
-                            nd[(ly < TY - 1 && (kAll || nyp > r)) ? didx<NT, NPT>(p + TX) : sink] = 1;
+                            const int txm = lx > 0 ? didx<NT, NPT>(p - 1) : sink;
+                            const int txp = lx < TX - 1 ? didx<NT, NPT>(p + 1) : sink;
+                            const int tym = ly > 0 ? didx<NT, NPT>(p - TX) : sink;
+                            const int typ = ly < TY - 1 ? didx<NT, NPT>(p + TX) : sink;
+                            nd[(kAll || nxm > r) ? txm : sink] = 1;
+                            nd[(kAll || nxp > r) ? txp : sink] = 1;
+                            nd[(kAll || nym > r) ? tym : sink] = 1;
+                            nd[(kAll || nyp > r) ? typ : sink] = 1;
                             if (C::D3) {
-                                nd[(lz > 0 && (kAll || nzm > r)) ? didx<NT, NPT>(p - TX * TY) : sink] = 1;
-                                nd[(lz < TZ - 1 && (kAll || nzp > r)) ? didx<NT, NPT>(p + TX * TY) : sink] = 1;
+                                const int tzm = lz > 0 ? didx<NT, NPT>(p - TX * TY) : sink;
+                                const int tzp = lz < TZ - 1 ? didx<NT, NPT>(p + TX * TY) : sink;
+                                nd[(kAll || nzm > r) ? tzm : sink] = 1;
+                                nd[(kAll || nzp > r) ? tzp : sink] = 1;
                             }
                             marked = true;
                         }
