@@ -78,6 +78,31 @@ def test_rect_matches_oracle(gpu, O, case):
             assert_bitwise(t, ref, f"{name} tile {tile} delta {delta}")
 
 
+TILES_3D = [(32, 8, 4), (16, 8, 8), (8, 8, 8), (64, 4, 4), (16, 8, 4), (8, 8, 4), (8, 4, 4)]
+TILES_2D = [(64, 16), (32, 32), (128, 8), (16, 16), (16, 8)]
+
+
+def test_every_tile_shape(gpu, O):
+    """Every supported tile shape (3D tiles of 1024 points run on 512-thread
+    blocks, two points a thread), ragged in every direction, with sources at
+    offsets, a slowness field in 2D."""
+    rng = np.random.default_rng(31)
+    f = W.random_field((11, 21, 70), rng, 0.5, 5.0, block=3)
+    xs, ys, zs = W.jittered_coords(70, 1.0, rng), W.stretched_coords(21, 0.6, 1.05), W.jittered_coords(11, 1.5, rng)
+    src = np.array([W.flat_index(40, 3, 9, 70, 21), 17])
+    t0 = np.array([0.0, 2.5])
+    ref = O.solve_rect(f, xs, ys, zs, src, t0=t0)
+    for tile in TILES_3D:
+        assert_bitwise(gpu_rect(gpu, f, xs, ys, zs, src, t0=t0, tile=tile, delta=0.4), ref, f"3D tile {tile}")
+    g = 1.0 / W.random_field((1, 45, 150), rng, 0.5, 5.0, block=5)
+    gx, gy = W.stretched_coords(150, 0.2, 1.01), W.jittered_coords(45, 0.5, rng)
+    gsrc = np.array([W.flat_index(75, 44, 0, 150, 45)])
+    gref = O.solve_rect(g, gx, gy, None, gsrc, kind=1)
+    for tile in TILES_2D:
+        assert_bitwise(gpu_rect(gpu, g, gx, gy, None, gsrc, kind="slowness", tile=tile, delta=0.3), gref,
+                       f"2D tile {tile}")
+
+
 def test_unit_spacing_is_the_uniform_solve(gpu, O):
     rng = np.random.default_rng(7)
     for shape in ((21, 40, 50), (1, 90, 70)):
