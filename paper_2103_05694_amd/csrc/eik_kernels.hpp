@@ -330,10 +330,15 @@ __device__ __forceinline__ void st_flags(uint8_t* f, uint32_t v) {
 // COUNT adds the work classification (A.work_ref must then be set).
 // Registers are capped for three waves per SIMD with blocks of up to 256
 // threads (three blocks per compute unit) and four with larger blocks (two
-// 512-thread blocks or one 1024-thread block per compute unit).
+// 512-thread blocks or one 1024-thread block per compute unit).  Compacted
+// passes on 3D tiles (the batched shots) also take four: a few registers
+// spill, but four 256-thread blocks per compute unit keep more tiles in flight
+// (2% more batch throughput); in 2D the spills cost more than that.  The
+// rectilinear operator on 3D tiles keeps two, its 512-thread blocks needing
+// about 160 registers.
 template <int TX, int TY, int TZ, int NT, int OP = 0, bool COUNT = false, bool PACK = false>
 __global__ void __launch_bounds__(NT)
-    __attribute__((amdgpu_waves_per_eu(OP == 4 && TZ > 1 && NT == 512 ? 2 : (NT > 256 ? 4 : 3)))) k_solve(SolveArgs A) {
+    __attribute__((amdgpu_waves_per_eu(OP == 4 && TZ > 1 && NT == 512 ? 2 : ((NT > 256 || (PACK && TZ > 1)) ? 4 : 3)))) k_solve(SolveArgs A) {
     using C = TileCfg<TX, TY, TZ, NT>;
     constexpr int NPT = C::NPT;
     static_assert(NPT == 1 || NPT == 2 || NPT == 4, "1, 2 or 4 points per thread");
