@@ -9,7 +9,9 @@
 //   lambda_n = g_n + sum over children m (n is m's axis-k parent) of
 //              fl(mu_m * w_{m,k}), summed in neighbour order x-,x+,y-,y+,z-,z+,
 //   mu_n     = fl(lambda_n / W_n),
-//   dL/ds_n  = fl(fl(mu_n * q_n) * h),  sources: 0.
+//   dL/ds_n  = fl(fl(mu_n * q_n) * h),  sources: 0
+// (the last line in a separate elementwise pass, k_adj_grad, once every mu is
+// final: the sweep itself never reads the field).
 // A child always has a strictly larger time than its parent, so the graph is
 // acyclic and mu can be evaluated children-first.
 //
@@ -85,14 +87,34 @@ __global__ void k_adj_push_all(int ntiles, const uint64_t* tile_tmax,
     }
 }
 
+// dL/ds from the final multipliers: fl(fl(mu * q) * h) at non-sources, 0 at
+// sources (mu is 0 there); a field value outside the domain raises the flag.
+// One block per tile, as k_adj_prep.
+template <int TX, int TY, int TZ>
+__global__ void k_adj_grad(ProbTable T, int ntiles, const double* field, const uint8_t* par, const double* mu,
+                           double* grad, uint32_t* flags) {
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const Prob P = prob_of_tile(T, tile);
+        const int tl = tile - P.tile_off;
+        const int tx = tl % P.ntx, ty = (tl / P.ntx) % P.nty, tz = tl / (P.ntx * P.nty);
+        for (int i = threadIdx.x; i < TX * TY * TZ; i += blockDim.x) {
+            const int x = tx * TX + i % TX, y = ty * TY + (i / TX) % TY, z = tz * TZ + i / (TX * TY);
+            if (!(x < P.nx && y < P.ny && z < P.nz)) continue;
+            const int64_t gi = P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x;
+            bool ok;
+            const double q = field_q(field[gi], P.h, P.kind, ok);
+            if (!ok) __hip_atomic_fetch_or(flags, kFlagDomain, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            grad[gi] = (par[gi] & 0x80) ? 0.0 : (mu[gi] * (ok ? q : 0.0)) * P.h;
+        }
+    }
+}
+
 struct AdjArgs {
     ProbTable pt;
-    const double* field;
     const double* t;
     const uint8_t* par;
     const double* g;
     double* mu;
-    double* grad;
     uint64_t* tkey;
     const unsigned long long* tref_bits;
     Sched s;
@@ -221,11 +243,10 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 25
                 return P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x;
             return -1;
         };
-        double gq[NPT];     // q_n, 0 when not an interior point
         bool was_done[NPT];
         uint32_t live = 0;  // bit j: point j is in the grid, not a source, not yet done
         {
-            double tv[NPT], fv[NPT], gv[NPT], mv[NPT];
+            double tv[NPT], gv[NPT], mv[NPT];
             uint8_t pv[NPT];
             double htv[HPT], hmv[HPT];
             uint8_t hpv[HPT];
@@ -236,7 +257,6 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 25
                 const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
                 const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
                 tv[j] = inf64();
-                fv[j] = 1.0;
                 gv[j] = 0.0;
                 mv[j] = qnan64();
                 pv[j] = 0x80;  // outside points act as done sources
@@ -244,7 +264,6 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 25
                     const int64_t gi = P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x;
                     tv[j] = A.t[gi];
                     pv[j] = A.par[gi];
-                    fv[j] = A.field[gi];
                     gv[j] = A.g[gi];
                     mv[j] = as_f64(__hip_atomic_load((const uint64_t*)(A.mu + gi), __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT));
@@ -273,21 +292,12 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 25
                 const int p = tid + j * NT;
                 const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
                 const int L = C::lds(lx, ly, lz);
-                double q = 0.0, m = 0.0;
-                if ((inb >> j) & 1u) {
-                    bool ok;
-                    q = field_q(fv[j], P.h, P.kind, ok);
-                    if (!ok) {
-                        set_flag(S, kFlagDomain);
-                        q = 0.0;
-                    }
-                    m = (pv[j] & 0x80) ? 0.0 : mv[j];
-                }
+                double m = 0.0;
+                if ((inb >> j) & 1u) m = (pv[j] & 0x80) ? 0.0 : mv[j];
                 sT[L] = tv[j];
                 sP[L] = pv[j];
                 sM[L] = m;
                 sG[p] = (inb >> j) & 1u ? gv[j] : 0.0;
-                gq[j] = q;
                 was_done[j] = !(m != m);
                 if (((inb >> j) & 1u) && !(pv[j] & 0x80) && !was_done[j]) live |= 1u << j;
                 // first run: every point (leaves can sit anywhere); later runs:
@@ -570,9 +580,6 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 25
             if (done_now || !visited) {
                 __hip_atomic_store((uint64_t*)(A.mu + gi), as_u64(mv), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
-            }
-            if (done_now || (!visited && (pn & 0x80))) {
-                A.grad[gi] = (pn & 0x80) ? 0.0 : (mv * gq[j]) * P.h;
             }
             if (done_now && !(pn & 0x80)) {
                 ++ndone;

@@ -614,12 +614,10 @@ int adjoint(Workspace& w, const std::vector<Prob>& probs, int64_t ntiles, int64_
     HIP_TRY(hipGetLastError());
     AdjArgs a;
     a.pt = T;
-    a.field = field;
     a.t = t;
     a.par = par;
     a.g = g;
     a.mu = mu;
-    a.grad = grad;
     a.tkey = w.tkey;
     a.tref_bits = tref;
     a.s = s;
@@ -639,6 +637,10 @@ int adjoint(Workspace& w, const std::vector<Prob>& probs, int64_t ntiles, int64_
     void* kargs[] = {(void*)&a};
     HIP_TRY(hipLaunchKernel(kern, dim3(grid), dim3(threads), kargs, 0, st));
     if ((rc = timing_end(w, o))) return rc;
+    // the gradient from the final multipliers (the sweep never reads the field)
+    hipLaunchKernelGGL((k_adj_grad<TX, TY, TZ>), dim3((unsigned)std::min<int64_t>(ntiles, 65536)), dim3(kThreads),
+                       0, st, T, (int)ntiles, field, par, (const double*)mu, grad, s.flags);
+    HIP_TRY(hipGetLastError());
     w.last_kind = 2;
     w.last_ntiles = ntiles;
     w.last_seq = next_seq();
