@@ -190,7 +190,7 @@ def latency_estimate(args, torch, eik, W, shape, src_xyz) -> dict:
     q = W.layered_3d(128, 128, 64, h=10.0, seed=2)
     f = torch.from_numpy(q.field).cuda()
     eik.solve(f, q.h, torch.as_tensor(q.src).cuda(), delta=args.delta, tile=args.tile, grid_blocks=1,
-              horizon=args.horizon, packed=args.packed)
+              horizon=args.horizon, packed=args.packed, lookahead=args.lookahead)
     st = eik.status()
     run_us = (st.phase_us[1] + st.phase_us[2] + st.phase_us[3]) / max(st.tile_visits, 1)
     return {"tile_hops": hops, "run_us_one_workgroup": run_us, "latency_bound_ms": hops * run_us * 1e-3}
@@ -203,7 +203,7 @@ def bench_single(args, torch, eik, W) -> dict:
     src = torch.as_tensor(p.src).cuda()
     out = torch.empty_like(f)
     kw = dict(delta=args.delta, tile=args.tile, grid_blocks=args.grid_blocks, horizon=args.horizon, out=out,
-              packed=args.packed, check_status=False)
+              packed=args.packed, lookahead=args.lookahead, check_status=False)
     for _ in range(args.warmup):
         eik.solve(f, p.h, src, **kw)
     eik.status()
@@ -281,14 +281,16 @@ def bench_tomography(args, torch, eik, W) -> dict:
     rec = torch.as_tensor(case.receivers).cuda()
     obs = ShotBatch([s_true] * args.shots, case.h, srcs, [rec] * args.shots, kind="slowness",
                     delta=args.tomo_delta, tile=args.tomo_tile, grid_blocks=args.tomo_grid_blocks,
-                    horizon=args.tomo_horizon, packed=args.tomo_packed, **args.adj_cfg)
+                    horizon=args.tomo_horizon, packed=args.tomo_packed, lookahead=args.tomo_lookahead,
+                    **args.adj_cfg)
     obs.step()
     obs.sync()
     eik.status(obs.stream)
     t_obs = [v.reshape(-1).index_select(0, rec) for v in obs.shot_views(obs.t)]
     sb = ShotBatch([s0] * args.shots, case.h, srcs, [rec] * args.shots, t_obs=t_obs, kind="slowness",
                    delta=args.tomo_delta, tile=args.tomo_tile, grid_blocks=args.tomo_grid_blocks,
-                   horizon=args.tomo_horizon, packed=args.tomo_packed, **args.adj_cfg)
+                   horizon=args.tomo_horizon, packed=args.tomo_packed, lookahead=args.tomo_lookahead,
+                   **args.adj_cfg)
     sb.capture()
     reps = max(args.steps // 4, 2)
     for _ in range(2):
@@ -343,7 +345,7 @@ def bench_uneven(args, torch, eik, W) -> dict:
     npts = sum(p.npts for p in shots)
     obs = ShotBatch(fields_true, 10.0, srcs, recs, kind="slowness", delta=args.tomo_delta, tile=args.tomo_tile,
                     grid_blocks=args.tomo_grid_blocks, horizon=args.tomo_horizon, packed=args.tomo_packed,
-                    **args.adj_cfg)
+                    lookahead=args.tomo_lookahead, **args.adj_cfg)
     obs.step()
     obs.sync()
     eik.status(obs.stream)
@@ -351,7 +353,7 @@ def bench_uneven(args, torch, eik, W) -> dict:
     del obs
     sb = ShotBatch(fields, 10.0, srcs, recs, t_obs=t_obs, kind="slowness", delta=args.tomo_delta,
                    tile=args.tomo_tile, grid_blocks=args.tomo_grid_blocks, horizon=args.tomo_horizon,
-                   packed=args.tomo_packed, **args.adj_cfg)
+                   packed=args.tomo_packed, lookahead=args.tomo_lookahead, **args.adj_cfg)
     sb.capture()
     reps = max(args.steps // 8, 2)
     sb.replay()
@@ -425,21 +427,21 @@ def bench_schedules(args, torch, eik, W) -> dict:
     f = torch.from_numpy(p.field).cuda()
     src = torch.as_tensor(p.src).cuda()
     kw = dict(tile=args.tile, grid_blocks=args.grid_blocks, packed=args.packed, check_status=False)
-    ref = eik.solve(f, p.h, src, delta=args.delta, horizon=args.horizon, **kw)
+    ref = eik.solve(f, p.h, src, delta=args.delta, horizon=args.horizon, lookahead=args.lookahead, **kw)
     eik.status()
     out = {"workload": "3D 512x512x256 layered model (the headline solve)", "tile": list(args.tile), "rows": []}
-    for name, delta, hz in (("one bucket (FIFO)", 0.0, 0), ("narrow buckets", args.delta / 8.0, 0),
-                            ("tuned", args.delta, args.horizon)):
+    for name, delta, hz, la in (("one bucket (FIFO)", 0.0, 0, 0), ("narrow buckets", args.delta / 8.0, 0, 0),
+                                ("tuned", args.delta, args.horizon, args.lookahead)):
         t = torch.empty_like(f)
-        eik.solve(f, p.h, src, delta=delta, horizon=hz, out=t, **kw)
+        eik.solve(f, p.h, src, delta=delta, horizon=hz, lookahead=la, out=t, **kw)
         eik.status()
         torch.cuda.synchronize()
-        eik.solve(f, p.h, src, delta=delta, horizon=hz, out=t, time_kernels=True, **kw)
+        eik.solve(f, p.h, src, delta=delta, horizon=hz, lookahead=la, out=t, time_kernels=True, **kw)
         ms = eik.status().kernel_ms
-        eik.solve(f, p.h, src, delta=delta, horizon=hz, out=t, work_ref=ref, **kw)
+        eik.solve(f, p.h, src, delta=delta, horizon=hz, lookahead=la, out=t, work_ref=ref, **kw)
         st = eik.status()
         ev, imp, good = st.evaluations, st.improving, st.final_updates
-        out["rows"].append({"schedule": name, "delta": delta, "horizon": hz, "kernel_ms": ms,
+        out["rows"].append({"schedule": name, "delta": delta, "horizon": hz, "lookahead": la, "kernel_ms": ms,
                             "visits_per_tile": st.tile_visits / max(st.ntiles, 1),
                             "evaluations_per_point": ev / p.npts, "empty": (ev - imp) / max(ev, 1),
                             "good": good / max(ev, 1), "bad": (imp - good) / max(ev, 1),
@@ -461,8 +463,10 @@ def bench_paper_scale(args, torch, eik, W) -> dict:
     gb = int(cfg.get("grid_blocks", 0)) if cfg else 0
     hz = int(cfg.get("horizon", 0)) if cfg else 0
     pk = bool(cfg.get("packed", False)) if cfg else False
+    la = int(cfg.get("lookahead", 0)) if cfg else 0
     out = torch.empty_like(f)
-    kw = dict(tile=tile, delta=delta, grid_blocks=gb, horizon=hz, out=out, packed=pk, check_status=False)
+    kw = dict(tile=tile, delta=delta, grid_blocks=gb, horizon=hz, out=out, packed=pk, lookahead=la,
+              check_status=False)
     eik.solve(f, p.h, src, **kw)
     eik.status()
     reps = 3
@@ -477,15 +481,16 @@ def bench_paper_scale(args, torch, eik, W) -> dict:
     return {"workload": "2D 11204x54404 folded layers (the paper's upsampled grid shape), h=0.3125 m",
             "points": p.npts, "ms_per_solve": ms, "kernel_ms": st.kernel_ms,
             "points_per_s": p.npts / (ms * 1e-3), "tile": list(tile), "delta": delta, "grid_blocks": gb,
-            "horizon": hz, "visits_per_tile": st.tile_visits / max(st.ntiles, 1),
+            "horizon": hz, "lookahead": la, "visits_per_tile": st.tile_visits / max(st.ntiles, 1),
             "residual_points": res[0]}
 
 
 def bench_rect(args, torch, eik, W) -> dict:
     """The benchmark's 512x512x256 layered model on a rectilinear grid:
     10 m in x and y, depth spacing stretched geometrically from 5 m to about
-    20 m (eik_solve_rect), same source; 8x8x4 tiles and a 0.01 s bucket width,
-    the best of a sweep over five tile shapes and three widths."""
+    20 m (eik_solve_rect), same source; 8x8x8 tiles, a 0.0025 s bucket width
+    and a lookahead of 16 buckets, the best of a sweep over four tile shapes,
+    three widths and three lookaheads (0, 8, 16)."""
     import numpy as np
     p = W.layered_3d()
     f = torch.from_numpy(p.field).cuda()
@@ -494,7 +499,7 @@ def bench_rect(args, torch, eik, W) -> dict:
     xs, ys = np.arange(nx) * p.h, np.arange(ny) * p.h
     zs = W.stretched_coords(nz, 5.0, 4.0 ** (1.0 / (nz - 2)))
     out = torch.empty_like(f)
-    kw = dict(tile=(8, 8, 4), delta=0.01, out=out, check_status=False)
+    kw = dict(tile=(8, 8, 8), delta=0.0025, lookahead=16, out=out, check_status=False)
     eik.solve_rect(f, xs, ys, zs, src, **kw)
     eik.status()
     reps = 5
@@ -507,8 +512,8 @@ def bench_rect(args, torch, eik, W) -> dict:
     st = eik.status()
     return {"workload": "3D 512x512x256 layered speed on a rectilinear grid (dx = dy = 10 m, dz 5 -> 20 m "
                         "geometric), one surface-centre source",
-            "points": p.npts, "ms_per_solve": ms, "points_per_s": p.npts / (ms * 1e-3), "tile": [8, 8, 4],
-            "delta": 0.01, "visits_per_tile": st.tile_visits / max(st.ntiles, 1), "max_time_s": float(out.max())}
+            "points": p.npts, "ms_per_solve": ms, "points_per_s": p.npts / (ms * 1e-3), "tile": [8, 8, 8],
+            "delta": 0.0025, "lookahead": 16, "visits_per_tile": st.tile_visits / max(st.ntiles, 1), "max_time_s": float(out.max())}
 
 
 def profile_mode(args, torch, eik, W) -> None:
@@ -529,7 +534,8 @@ def profile_mode(args, torch, eik, W) -> None:
     out = torch.empty_like(f)
     for i in range(args.steps):
         eik.solve(f, p.h, src, delta=args.delta, tile=args.tile, grid_blocks=args.grid_blocks,
-                  horizon=args.horizon, packed=args.packed, out=out, check_status=False)
+                  horizon=args.horizon, packed=args.packed, lookahead=args.lookahead, out=out,
+                  check_status=False)
         torch.cuda.synchronize()
         log(f"profile solve {i} done")
     eik.status()
@@ -548,6 +554,8 @@ def main() -> int:
     ap.add_argument("--tile", type=str, default=None, help="e.g. 32x8x4; default from the tuning cache")
     ap.add_argument("--grid-blocks", type=int, default=None, help="persistent workgroups; default from the tuning cache")
     ap.add_argument("--horizon", type=int, default=None, help="bucket horizon 0..4; default from the tuning cache")
+    ap.add_argument("--lookahead", type=int, default=None,
+                    help="buckets a block may take ahead of the lowest open one; default from the tuning cache")
     ap.add_argument("--tomo-delta", type=float, default=None, help="default from the tuning cache")
     ap.add_argument("--tomo-tile", type=str, default=None, help="default from the tuning cache")
     ap.add_argument("--shots", type=int, default=32)
@@ -594,6 +602,8 @@ def main() -> int:
     if args.horizon is None:
         args.horizon = int(cfg.get("horizon", 0)) if cfg else 0
     args.packed = bool(cfg.get("packed", False)) if cfg else False
+    if args.lookahead is None:
+        args.lookahead = int(cfg.get("lookahead", 0)) if cfg else 0
     tcfg = autotune.lookup_batch(args.shots, (128, 256, 256), "slowness") or \
         autotune.lookup((128, 256, 256), "slowness")
     if args.tomo_tile is not None:
@@ -605,15 +615,18 @@ def main() -> int:
     args.tomo_grid_blocks = int(tcfg.get("grid_blocks", 0)) if tcfg else 0
     args.tomo_horizon = int(tcfg.get("horizon", 0)) if tcfg else 0
     args.tomo_packed = bool(tcfg.get("packed", False)) if tcfg else False
+    args.tomo_lookahead = int(tcfg.get("lookahead", 0)) if tcfg else 0
     args.adj_cfg = {}
     if tcfg and "adj_delta" in tcfg:
         args.adj_cfg = dict(adj_delta=tcfg["adj_delta"], adj_tile=tuple(tcfg["adj_tile"]),
                             adj_grid_blocks=int(tcfg.get("adj_grid_blocks", 0)),
-                            adj_packed=bool(tcfg.get("adj_packed", False)))
+                            adj_packed=bool(tcfg.get("adj_packed", False)),
+                            adj_lookahead=int(tcfg.get("adj_lookahead", 0)))
     # the per-shot baseline runs with the single-shot tuning (its best), not the batch's
     scfg = autotune.lookup((128, 256, 256), "slowness")
     args.shot_cfg = (dict(delta=scfg["delta"], tile=tuple(scfg["tile"]), grid_blocks=int(scfg.get("grid_blocks", 0)),
-                          horizon=int(scfg.get("horizon", 0)), packed=bool(scfg.get("packed", False)))
+                          horizon=int(scfg.get("horizon", 0)), packed=bool(scfg.get("packed", False)),
+                          lookahead=int(scfg.get("lookahead", 0)))
                      if scfg else {})
     args.shot_cfg.update(args.adj_cfg)
 
@@ -663,7 +676,7 @@ def main() -> int:
         "config": {"workload": "3D 512x512x256 layered+noise speed (h=10 m, 1500-6000 m/s, 8 layers, "
                                "seed 2), one surface-centre source, single forward solve",
                    "delta": args.delta, "tile": list(args.tile), "grid_blocks": args.grid_blocks,
-                   "horizon": args.horizon, "packed": args.packed,
+                   "horizon": args.horizon, "packed": args.packed, "lookahead": args.lookahead,
                    "points": single["npts"]},
         "roofline": single["roofline"],
         "cpu_baseline": cpu,

@@ -120,7 +120,7 @@ typedef struct {
                                 since the previous eik_status (at most 4096 launches in
                                 between).  EIK_FLAG_TIMELINE, EIK_FLAG_TRACK_CHANGE,
                                 EIK_FLAG_WARM_START, EIK_FLAG_PACKED: above */
-    int32_t lookahead;       /* 0..8: work may be taken from the lowest non-drained bucket
+    int32_t lookahead;       /* 0..16: work may be taken from the lowest non-drained bucket
                                 and this many buckets above it (0 = strict bucket order) */
     int32_t horizon;         /* 0 => off; k in 1..4: a run of a tile claimed from bucket b
                                 settles only values r with floor(r / delta) < b + k and requeues

@@ -1,5 +1,6 @@
-"""Autotuner for the persistent solver's two free parameters: the tile shape
-and the priority bucket width delta.
+"""Autotuner for the persistent solver's free parameters: the tile shape, the
+priority bucket width delta, the lookahead window of buckets a workgroup may
+take work from, the bucket horizon and the pass structure.
 
 The paper leaves the priority scale open and notes that the best trade-off
 between priority inversions and contention depends on hardware and input
@@ -33,6 +34,8 @@ DELTA_FACTORS = (0.0, 0.25, 0.5, 1.0, 2.0, 4.0, 8.0)
 GRID_BLOCKS = (0,)       # 0 = as many workgroups as fit on the device
 HORIZONS = (0, 1, 2)     # 0 = off; k = settle values below (bucket + k) only
 PACKED = (False, True)   # relaxation passes: per-thread points, or compacted lists
+LOOKAHEADS = (2, 4, 8, 16)  # second stage: buckets beyond the lowest a claim may take work from
+LOOKAHEAD_FACTORS = (0.0625, 0.125, 0.25, 0.5, 1.0)  # bucket widths tried with a lookahead window
 
 
 def _key(shape: Sequence[int], kind: str) -> str:
@@ -64,9 +67,11 @@ def tune(field: torch.Tensor, h: float, sources, kind: str = "speed",
          tiles: Optional[Iterable[Tuple[int, ...]]] = None,
          delta_factors: Sequence[float] = DELTA_FACTORS, reps: int = 3,
          grid_blocks: Sequence[int] = GRID_BLOCKS, horizons: Sequence[int] = HORIZONS,
-         packed: Sequence[bool] = PACKED, save: bool = True, log=print) -> dict:
-    """Time every (tile, delta, grid size) candidate on this problem; all must
-    agree bitwise."""
+         packed: Sequence[bool] = PACKED, lookaheads: Sequence[int] = LOOKAHEADS,
+         lookahead_factors: Sequence[float] = LOOKAHEAD_FACTORS, save: bool = True, log=print) -> dict:
+    """Time every (tile, delta, grid size, horizon, pass structure) candidate on
+    this problem without a lookahead, then, with the best of them, every
+    (lookahead, narrower delta) pair; all candidates must agree bitwise."""
     nd = field.dim()
     tiles = list(tiles) if tiles is not None else TILES[nd]
     f64 = field.to(torch.float64)
@@ -76,11 +81,11 @@ def tune(field: torch.Tensor, h: float, sources, kind: str = "speed",
     results: List[dict] = []
     out = torch.empty_like(field)
 
-    def run(tile, fac, gb, hz, pk):
+    def run(tile, fac, gb, hz, pk, la=0):
         nonlocal ref
         delta = fac * qmed * min(tile[:nd])
         fn = lambda: api.solve(field, h, sources, kind=kind, delta=delta, tile=tile, out=out,
-                               grid_blocks=gb, horizon=hz, packed=pk, check_status=False)
+                               grid_blocks=gb, horizon=hz, packed=pk, lookahead=la, check_status=False)
         fn()
         api.status()
         t = out.clone()
@@ -88,13 +93,13 @@ def tune(field: torch.Tensor, h: float, sources, kind: str = "speed",
             ref = t
         elif not torch.equal(ref, t):
             raise RuntimeError(f"candidate tile={tile} delta={delta} grid={gb} horizon={hz} packed={pk} "
-                               "changed the result")
+                               f"lookahead={la} changed the result")
         sec = _time(fn, reps)
         api.status()
         results.append({"tile": list(tile), "delta": delta, "delta_factor": fac, "grid_blocks": gb,
-                        "horizon": hz, "packed": pk, "ms": sec * 1e3})
-        log(f"  tile {tile} delta {delta:.4g} ({fac:.3g} x qmed x edge) grid {gb} horizon {hz} packed {pk}: "
-            f"{sec * 1e3:.3f} ms")
+                        "horizon": hz, "packed": pk, "lookahead": la, "ms": sec * 1e3})
+        log(f"  tile {tile} delta {delta:.4g} ({fac:.3g} x qmed x edge) grid {gb} horizon {hz} packed {pk} "
+            f"lookahead {la}: {sec * 1e3:.3f} ms")
 
     for tile in tiles:
         for fac in delta_factors:
@@ -102,16 +107,24 @@ def tune(field: torch.Tensor, h: float, sources, kind: str = "speed",
                 for gb in grid_blocks:
                     for pk in packed:
                         run(tile, fac, gb, hz, pk)
+    # a lookahead window with narrower buckets, on each tile's best of the first
+    # stage (the tile that wins without a window is often not the one that wins
+    # with it: smaller tiles gain more)
+    for tile in tiles:
+        best = min((r for r in results if tuple(r["tile"]) == tuple(tile)), key=lambda r: r["ms"])
+        for la in lookaheads:
+            for fac in lookahead_factors:
+                run(tuple(tile), fac, best["grid_blocks"], best["horizon"], best["packed"], la)
     # refine the best bucket width between its neighbours on the doubling grid
     best = min(results, key=lambda r: r["ms"])
     if best["delta_factor"] > 0:
         for step in (2.0 ** -0.5, 2.0 ** 0.5):
             run(tuple(best["tile"]), best["delta_factor"] * step, best["grid_blocks"], best["horizon"],
-                best["packed"])
+                best["packed"], best["lookahead"])
     best = min(results, key=lambda r: r["ms"])
     entry = {"tile": best["tile"], "delta": best["delta"], "grid_blocks": best["grid_blocks"],
-             "horizon": best["horizon"], "packed": best["packed"], "ms": best["ms"], "qmed": qmed,
-             "candidates": results}
+             "horizon": best["horizon"], "packed": best["packed"], "lookahead": best["lookahead"],
+             "ms": best["ms"], "qmed": qmed, "candidates": results}
     if save:
         cache = _load()
         cache[_key(field.shape, kind)] = entry
@@ -134,6 +147,7 @@ def tune_batch(fields: Sequence[torch.Tensor], h: float, sources, receivers, kin
                delta_factors: Sequence[float] = (0.25, 0.5, 1.0, 2.0, 4.0),
                adj_delta_factors: Sequence[float] = (0.0, 0.5, 1.0, 2.0, 4.0, 8.0),
                grid_blocks: Sequence[int] = (0,), packed: Sequence[bool] = PACKED, reps: int = 2,
+               lookaheads: Sequence[int] = LOOKAHEADS, lookahead_factors: Sequence[float] = LOOKAHEAD_FACTORS,
                save: bool = True, log=print) -> dict:
     """Tune a batch of shots (forward with parents, then the adjoint) in one
     persistent launch each: a batch has many times the parallel work of one
@@ -155,51 +169,61 @@ def tune_batch(fields: Sequence[torch.Tensor], h: float, sources, receivers, kin
     fwd: List[dict] = []
     ref = None
 
-    def run_fwd(tile, fac, gb, pk):
+    def run_fwd(tile, fac, gb, pk, la=0):
         nonlocal ref
         delta = fac * qmed * min(tile[:nd])
-        fn = lambda: api.solve_packed(b, t, par, delta, tile, grid_blocks=gb, packed=pk)
+        fn = lambda: api.solve_packed(b, t, par, delta, tile, grid_blocks=gb, packed=pk, lookahead=la)
         fn()
         api.status()
         if ref is None:
             ref = (t.clone(), par.clone())
         elif not (torch.equal(ref[0], t) and torch.equal(ref[1], par)):
-            raise RuntimeError(f"batch forward tile={tile} delta={delta} grid={gb} packed={pk} changed the result")
+            raise RuntimeError(f"batch forward tile={tile} delta={delta} grid={gb} packed={pk} lookahead={la} "
+                               "changed the result")
         sec = _time(fn, reps)
         api.status()
         fwd.append({"tile": list(tile), "delta": delta, "delta_factor": fac, "grid_blocks": gb, "packed": pk,
-                    "ms": sec * 1e3})
-        log(f"  batch forward tile {tile} delta {delta:.4g} grid {gb} packed {pk}: {sec * 1e3:.2f} ms")
+                    "lookahead": la, "ms": sec * 1e3})
+        log(f"  batch forward tile {tile} delta {delta:.4g} grid {gb} packed {pk} lookahead {la}: "
+            f"{sec * 1e3:.2f} ms")
 
     for tile in tiles:
         for fac in delta_factors:
             for gb in grid_blocks:
                 for pk in packed:
                     run_fwd(tile, fac, gb, pk)
+    for tile in tiles:
+        bt = min((r for r in fwd if tuple(r["tile"]) == tuple(tile)), key=lambda r: r["ms"])
+        for la in lookaheads:
+            for fac in lookahead_factors:
+                run_fwd(tuple(tile), fac, bt["grid_blocks"], bt["packed"], la)
     bf = min(fwd, key=lambda r: r["ms"])
     if bf["delta_factor"] > 0:
         for step in (2.0 ** -0.5, 2.0 ** 0.5):
-            run_fwd(tuple(bf["tile"]), bf["delta_factor"] * step, bf["grid_blocks"], bf["packed"])
+            run_fwd(tuple(bf["tile"]), bf["delta_factor"] * step, bf["grid_blocks"], bf["packed"], bf["lookahead"])
     t.copy_(ref[0])
     par.copy_(ref[1])
     adj: List[dict] = []
     gref = None
 
-    def run_adj(tile, fac, gb, pk):
+    def run_adj(tile, fac, gb, pk, la=0):
         nonlocal gref
         delta = fac * qmed * min(tile[:nd])
-        fn = lambda: api.adjoint_packed(b, t, par, g, grad, delta=delta, tile=tile, grid_blocks=gb, packed=pk)
+        fn = lambda: api.adjoint_packed(b, t, par, g, grad, delta=delta, tile=tile, grid_blocks=gb, packed=pk,
+                                        lookahead=la)
         fn()
         api.status()
         if gref is None:
             gref = grad.clone()
         elif not torch.equal(gref, grad):
-            raise RuntimeError(f"batch adjoint tile={tile} delta={delta} grid={gb} packed={pk} changed the result")
+            raise RuntimeError(f"batch adjoint tile={tile} delta={delta} grid={gb} packed={pk} lookahead={la} "
+                               "changed the result")
         sec = _time(fn, reps)
         api.status()
         adj.append({"tile": list(tile), "delta": delta, "delta_factor": fac, "grid_blocks": gb, "packed": pk,
-                    "ms": sec * 1e3})
-        log(f"  batch adjoint tile {tile} delta {delta:.4g} grid {gb} packed {pk}: {sec * 1e3:.2f} ms")
+                    "lookahead": la, "ms": sec * 1e3})
+        log(f"  batch adjoint tile {tile} delta {delta:.4g} grid {gb} packed {pk} lookahead {la}: "
+            f"{sec * 1e3:.2f} ms")
 
     for tile in tiles:
         for fac in adj_delta_factors:
@@ -207,15 +231,19 @@ def tune_batch(fields: Sequence[torch.Tensor], h: float, sources, receivers, kin
                 for pk in packed:
                     run_adj(tile, fac, gb, pk)
     ba = min(adj, key=lambda r: r["ms"])
+    for la in lookaheads:
+        for fac in (0.5, 1.0, 2.0):
+            run_adj(tuple(ba["tile"]), fac * max(ba["delta_factor"], 0.5), ba["grid_blocks"], ba["packed"], la)
+    ba = min(adj, key=lambda r: r["ms"])
     if ba["delta_factor"] > 0:
         for step in (2.0 ** -0.5, 2.0 ** 0.5):
-            run_adj(tuple(ba["tile"]), ba["delta_factor"] * step, ba["grid_blocks"], ba["packed"])
+            run_adj(tuple(ba["tile"]), ba["delta_factor"] * step, ba["grid_blocks"], ba["packed"], ba["lookahead"])
     bf = min(fwd, key=lambda r: r["ms"])
     ba = min(adj, key=lambda r: r["ms"])
     entry = {"tile": bf["tile"], "delta": bf["delta"], "grid_blocks": bf["grid_blocks"], "horizon": 0,
-             "packed": bf["packed"],
+             "packed": bf["packed"], "lookahead": bf["lookahead"],
              "adj_tile": ba["tile"], "adj_delta": ba["delta"], "adj_grid_blocks": ba["grid_blocks"],
-             "adj_packed": ba["packed"],
+             "adj_packed": ba["packed"], "adj_lookahead": ba["lookahead"],
              "ms": bf["ms"] + ba["ms"], "forward_ms": bf["ms"], "adjoint_ms": ba["ms"], "qmed": qmed,
              "forward_candidates": fwd, "adjoint_candidates": adj}
     if save:

@@ -27,8 +27,10 @@ class ShotBatch:
                  delta: float = 0.0, tile=None, stream: Optional[torch.cuda.Stream] = None,
                  grid_blocks: int = 0, horizon: int = 0, adj_delta: Optional[float] = None,
                  adj_tile=None, adj_grid_blocks: Optional[int] = None, packed: bool = False,
-                 adj_packed: bool = False):
+                 adj_packed: bool = False, lookahead: int = 0, adj_lookahead: Optional[int] = None):
         self.kind = kind
+        self.lookahead = lookahead
+        self.adj_lookahead = lookahead if adj_lookahead is None else adj_lookahead
         self.delta = delta
         self.tile = tile
         self.grid_blocks = grid_blocks
@@ -66,11 +68,12 @@ class ShotBatch:
     # -- one batched step: 2 persistent launches for all shots ----------------
     def _enqueue(self) -> None:
         api.solve_packed(self.b, self.t, self.par, self.delta, self.tile, grid_blocks=self.grid_blocks,
-                         stream=self.stream, horizon=self.horizon, packed=self.packed)
+                         stream=self.stream, horizon=self.horizon, packed=self.packed, lookahead=self.lookahead)
         self.g.zero_()
         self.g.index_copy_(0, self.rec, self.t.index_select(0, self.rec) - self.t_obs)
         api.adjoint_packed(self.b, self.t, self.par, self.g, self.grad, self.mu, self.adj_delta, self.adj_tile,
-                           grid_blocks=self.adj_grid_blocks, stream=self.stream, packed=self.adj_packed)
+                           grid_blocks=self.adj_grid_blocks, stream=self.stream, packed=self.adj_packed,
+                           lookahead=self.adj_lookahead)
 
     def step(self) -> None:
         """Enqueue one batched forward + adjoint (eager launches).  The batch's
@@ -114,7 +117,8 @@ class ShotBatch:
                    tile=None, grid_blocks: Optional[int] = None, horizon: Optional[int] = None,
                    adj_delta: Optional[float] = None, adj_tile=None,
                    adj_grid_blocks: Optional[int] = None, packed: Optional[bool] = None,
-                   adj_packed: Optional[bool] = None) -> None:
+                   adj_packed: Optional[bool] = None, lookahead: Optional[int] = None,
+                   adj_lookahead: Optional[int] = None) -> None:
         """Per-shot eik_solve + eik_adjoint launches on the current stream,
         writing into packed outputs.  The launch parameters default to the
         batch's; a single shot may prefer others (it has far less parallel
@@ -128,6 +132,8 @@ class ShotBatch:
         adj_delta = self.adj_delta if adj_delta is None else adj_delta
         adj_tile = self.adj_tile if adj_tile is None else adj_tile
         adj_grid_blocks = self.adj_grid_blocks if adj_grid_blocks is None else adj_grid_blocks
+        lookahead = self.lookahead if lookahead is None else lookahead
+        adj_lookahead = self.adj_lookahead if adj_lookahead is None else adj_lookahead
         tv = self.b.views(t_out)
         gv = self.b.views(grad_out)
         g = torch.zeros_like(t_out)
@@ -136,14 +142,14 @@ class ShotBatch:
         for i in range(self.nshots):
             t, par = api.solve(self.fields[i], self.hs[i], self.sources[i], kind=self.kind, parents=True,
                                delta=delta, tile=tile, grid_blocks=grid_blocks, horizon=horizon, out=tv[i],
-                               packed=packed, check_status=False)
+                               packed=packed, lookahead=lookahead, check_status=False)
             r = self.rec_local[i]
             nr = r.numel()
             gvv[i].view(-1).index_copy_(0, r, t.view(-1).index_select(0, r) - self.t_obs[rec_off:rec_off + nr])
             rec_off += nr
             api.adjoint(self.fields[i], self.hs[i], t, par, gvv[i], kind=self.kind, delta=adj_delta,
                         tile=adj_tile, grid_blocks=adj_grid_blocks, out=gv[i], packed=adj_packed,
-                        check_status=False)
+                        lookahead=adj_lookahead, check_status=False)
 
     def shot_views(self, packed: torch.Tensor) -> List[torch.Tensor]:
         return self.b.views(packed)

@@ -49,6 +49,10 @@ constexpr int kSolveThreads = EIK_SOLVE_THREADS;
 template <int TX, int TY, int TZ>
 constexpr int solve_threads() { return TX * TY * TZ < kSolveThreads ? TX * TY * TZ : kSolveThreads; }
 constexpr int kRings = 32;
+// A push from a run claimed from bucket b lands at most nrings - 1 - lookahead
+// buckets above b; 16 leaves a push range of 15 buckets.
+constexpr int kMaxLookahead = 16;
+static_assert(kMaxLookahead < kRings && kMaxLookahead < 64, "the claim window is read by one wave");
 constexpr int kScalWords = 192;
 constexpr int kTimelineCap = 1 << 16;
 constexpr int kSCur = 0, kSPending = 64, kSFlags = 128, kSPoisoned = 129, kSSrcCount = 130;
@@ -323,7 +327,8 @@ int check_opts(const eik_opts* o) {
         return fail(EIK_EINVAL, "unknown flags");
     if ((o->flags & EIK_FLAG_PACKED) && o->op != EIK_OP_DBAR)
         return fail(EIK_ENOTSUP, "compacted passes run with d-bar only");
-    if (o->lookahead < 0 || o->lookahead > 8) return fail(EIK_EINVAL, "lookahead must be in 0..8");
+    if (o->lookahead < 0 || o->lookahead > kMaxLookahead)
+        return fail(EIK_EINVAL, "lookahead must be in 0..16");
     if (o->op < EIK_OP_DBAR || o->op > EIK_OP_NEWTON) return fail(EIK_EINVAL, "unknown operator");
     if ((o->flags & EIK_FLAG_TRACK_CHANGE) && o->op == EIK_OP_DBAR)
         return fail(EIK_EINVAL, "change tracking applies to the ablation operators only");

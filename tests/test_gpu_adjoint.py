@@ -62,14 +62,15 @@ def test_adjoint_matches_oracle(gpu, O, case):
     ref_grad, ref_mu = O.adjoint(t, par, f, h, g, return_mu=True)
     tiles = [(64, 16), (32, 32), (16, 16)] if f.shape[0] == 1 else [(32, 8, 4), (8, 8, 8), (64, 4, 4), (16, 8, 8)]
     for tile in tiles:
-        for delta, pk in ((0.0, False), (1.0, False), (0.0, True), (1.0, True)):
+        for delta, pk, la in ((0.0, False, 0), (1.0, False, 0), (0.0, True, 0), (1.0, True, 0), (0.25, True, 8),
+                              (0.1, False, 16)):
             mu = torch.empty(f.shape, dtype=torch.float64, device="cuda")
             grad = gpu.adjoint(to_gpu(f), h, to_gpu(t), to_gpu(par), to_gpu(g), tile=tile, delta=delta,
-                               mu_out=mu.view(to_gpu(f).shape), packed=pk)
+                               mu_out=mu.view(to_gpu(f).shape), packed=pk, lookahead=la)
             gr = grad.cpu().numpy().reshape(f.shape)
-            assert_close_or_equal(gr, ref_grad, f"{name} grad tile {tile} packed {pk}")
+            assert_close_or_equal(gr, ref_grad, f"{name} grad tile {tile} packed {pk} lookahead {la}")
             m = mu.cpu().numpy()
-            assert_close_or_equal(m, ref_mu, f"{name} mu tile {tile} packed {pk}")
+            assert_close_or_equal(m, ref_mu, f"{name} mu tile {tile} packed {pk} lookahead {la}")
 
 
 def test_adjoint_end_to_end_from_gpu_forward(gpu, O):
@@ -145,6 +146,9 @@ def test_batched_adjoint_equals_per_problem(gpu, O):
     gpu.adjoint_packed(b, t, par, gp, grad2, packed=True, tile=(8, 8, 8), delta=0.3)
     gpu.status()
     assert torch.equal(grad, grad2)
+    gpu.adjoint_packed(b, t, par, gp, grad2, packed=True, tile=(16, 8, 8), delta=0.05, lookahead=16)
+    gpu.status()
+    assert torch.equal(grad, grad2)
     for (f, s), g, gr in zip(shots, gs, b.views(grad)):
         tr = O.fmm(f, 1.0, s)
         ref = O.adjoint(tr, O.parents(tr, s), f, 1.0, g)
@@ -181,8 +185,8 @@ def test_graph_capture_with_different_forward_and_adjoint_tiles(gpu, O):
     fields = [to_gpu(1.0 / f) for f, _ in shots]
     srcs = [torch.as_tensor(s) for _, s in shots]
     recs = [torch.arange(0, f.size, 7, device="cuda") for f, _ in shots]
-    sb = ShotBatch(fields, 1.0, srcs, recs, kind="slowness", delta=0.3, tile=(16, 8, 8), packed=True,
-                   adj_delta=0.6, adj_tile=(8, 8, 8))
+    sb = ShotBatch(fields, 1.0, srcs, recs, kind="slowness", delta=0.1, tile=(16, 8, 8), packed=True,
+                   adj_delta=0.6, adj_tile=(8, 8, 8), lookahead=8, adj_lookahead=4)
     sb.capture()
     t_plain = torch.empty_like(sb.t)
     g_plain = torch.empty_like(sb.grad)

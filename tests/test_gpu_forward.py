@@ -90,7 +90,7 @@ def test_ragged_and_degenerate_shapes(gpu, O, case):
     tiles = TILES_2D if f.shape[0] == 1 else TILES_3D
     for tile in tiles:
         for delta, la, hz, pk in ((0.0, 0, 0, False), (0.5, 0, 0, True), (0.25, 3, 0, False), (0.25, 0, 1, True),
-                                  (0.5, 2, 2, False), (0.0, 1, 0, True)):
+                                  (0.5, 2, 2, False), (0.0, 1, 0, True), (0.125, 16, 1, False)):
             t = gpu_solve(gpu, f, h, src, t0, tile=tile, delta=delta, lookahead=la, horizon=hz, packed=pk)
             assert_bitwise(t, ref, f"{name} tile {tile} delta {delta} lookahead {la} horizon {hz} packed {pk}")
 
@@ -109,7 +109,7 @@ def test_layered_3d_scaled(gpu, O, layered_small, tile):
     p = layered_small
     ref = O.fmm(p.field, p.h, p.src)
     for delta, la, pk in ((0.0, 0, False), (0.02, 0, False), (0.02, 0, True), (0.02, 2, True), (0.2, 1, False),
-                          (0.005, 8, True)):
+                          (0.005, 8, True), (0.0025, 16, False)):
         t = gpu_solve(gpu, p.field, p.h, p.src, tile=tile, delta=delta, lookahead=la, packed=pk)
         assert_bitwise(t, ref, f"layered tile {tile} delta {delta} lookahead {la} packed {pk}")
 
@@ -118,7 +118,7 @@ def test_layered_3d_scaled(gpu, O, layered_small, tile):
 def test_blocky_2d_scaled(gpu, O, tile):
     p = W.blocky_2d(n=512, nsrc=16, seed=3, block=16)
     ref = O.fmm(p.field, p.h, p.src)
-    for delta, la, pk in ((0.0, 0, False), (4.0, 0, True), (4.0, 4, False), (64.0, 1, True)):
+    for delta, la, pk in ((0.0, 0, False), (4.0, 0, True), (4.0, 4, False), (64.0, 1, True), (1.0, 16, True)):
         t = gpu_solve(gpu, p.field, p.h, p.src, tile=tile, delta=delta, lookahead=la, packed=pk)
         assert_bitwise(t, ref, f"blocky tile {tile} delta {delta} lookahead {la} packed {pk}")
 
@@ -142,7 +142,8 @@ def bench_config(shape, kind="speed"):
     if not cfg:
         return {}
     return dict(tile=tuple(cfg["tile"]), delta=cfg["delta"], grid_blocks=int(cfg.get("grid_blocks", 0)),
-                horizon=int(cfg.get("horizon", 0)), packed=bool(cfg.get("packed", False)))
+                horizon=int(cfg.get("horizon", 0)), packed=bool(cfg.get("packed", False)),
+                lookahead=int(cfg.get("lookahead", 0)))
 
 
 def test_blocky_full_4096(gpu, O):
@@ -325,13 +326,18 @@ def test_autotune_candidates_agree(gpu, layered_small):
     f = torch.from_numpy(p.field).cuda()
     e = autotune.tune(f, p.h, torch.as_tensor(p.src), tiles=[(8, 8, 8), (16, 8, 8)],
                       delta_factors=(0.0, 1.0, 4.0), grid_blocks=(0, 64), horizons=(0, 1), packed=(False, True),
-                      reps=1, save=False, log=lambda s: None)
+                      lookaheads=(2, 5), lookahead_factors=(0.5,), reps=1, save=False, log=lambda s: None)
     # tiles x (bucket width 0: grid sizes + other widths: horizons x grid sizes) x pass structures
     grid = 2 * (1 * 2 + 2 * 2 * 2) * 2
+    # then each tile's best with every (lookahead, width) pair
+    window = e["candidates"][grid:grid + 2 * 2]
+    assert [c["lookahead"] for c in window] == [2, 5, 2, 5]
+    assert all(c["lookahead"] == 0 for c in e["candidates"][:grid])
     # the best bucket width is refined at 2^(+-1/2) of its factor unless it was 0
-    extra = e["candidates"][grid:]
-    assert len(e["candidates"]) in (grid, grid + 2)
-    assert all(c["delta_factor"] not in (0.0, 1.0, 4.0) for c in extra)
+    extra = e["candidates"][grid + 4:]
+    assert len(e["candidates"]) in (grid + 4, grid + 6)
+    assert all(c["delta_factor"] not in (0.0, 1.0, 4.0, 0.5) for c in extra)
+    assert e["lookahead"] in (0, 2, 5)
     assert tuple(e["tile"]) in ((8, 8, 8), (16, 8, 8))
 
 

@@ -43,10 +43,12 @@ def tuned(shape, kind, default_tile, default_delta, nshots=32):
     if not cfg:
         return dict(tile=default_tile, delta=default_delta, grid_blocks=0, horizon=0)
     out = dict(tile=tuple(cfg["tile"]), delta=cfg["delta"], grid_blocks=int(cfg.get("grid_blocks", 0)),
-               horizon=int(cfg.get("horizon", 0)), packed=bool(cfg.get("packed", False)))
+               horizon=int(cfg.get("horizon", 0)), packed=bool(cfg.get("packed", False)),
+               lookahead=int(cfg.get("lookahead", 0)))
     if "adj_delta" in cfg:
         out.update(adj_delta=cfg["adj_delta"], adj_tile=tuple(cfg["adj_tile"]),
-                   adj_grid_blocks=int(cfg.get("adj_grid_blocks", 0)), adj_packed=bool(cfg.get("adj_packed", False)))
+                   adj_grid_blocks=int(cfg.get("adj_grid_blocks", 0)), adj_packed=bool(cfg.get("adj_packed", False)),
+                   adj_lookahead=int(cfg.get("adj_lookahead", 0)))
     return out
 
 
@@ -112,7 +114,8 @@ def test_full_size_determinism(gpu, O):
     from paper_2103_05694_amd import autotune
     c = autotune.lookup(p.field.shape, "speed") or {}
     cfg = dict(tile=tuple(c.get("tile", (8, 8, 8))), delta=c.get("delta", 0.02), grid_blocks=int(c.get("grid_blocks", 0)),
-               horizon=int(c.get("horizon", 0)), packed=bool(c.get("packed", False)))
+               horizon=int(c.get("horizon", 0)), packed=bool(c.get("packed", False)),
+               lookahead=int(c.get("lookahead", 0)))
     f = torch.from_numpy(p.field).cuda()
     src = torch.as_tensor(p.src)
     t1 = gpu.solve(f, p.h, src, **cfg)
@@ -159,7 +162,7 @@ def test_uneven_full_batch(gpu, O):
     t = torch.empty(b.npts, dtype=torch.float64, device="cuda")
     par = torch.empty(b.npts, dtype=torch.uint8, device="cuda")
     gpu.solve_packed(b, t, par, cfg["delta"], cfg["tile"], grid_blocks=cfg["grid_blocks"],
-                     horizon=cfg["horizon"], packed=cfg["packed"])
+                     horizon=cfg["horizon"], packed=cfg["packed"], lookahead=cfg.get("lookahead", 0))
     gpu.status()
     rng = np.random.default_rng(12)
     small = [i for i, p in enumerate(shots) if p.npts == 128 ** 3][:2]
@@ -178,7 +181,7 @@ def test_uneven_full_batch(gpu, O):
     grad = torch.empty_like(t)
     gpu.adjoint_packed(b, t, par, g, grad, delta=cfg.get("adj_delta", cfg["delta"]),
                        tile=cfg.get("adj_tile", cfg["tile"]), grid_blocks=cfg.get("adj_grid_blocks", cfg["grid_blocks"]),
-                       packed=cfg.get("adj_packed", False))
+                       packed=cfg.get("adj_packed", False), lookahead=cfg.get("adj_lookahead", 0))
     gpu.status()
     tv, pv, grv = b.views(t), b.views(par), b.views(grad)
     for i in small:
@@ -213,7 +216,8 @@ def test_paper_scale_2d(gpu, O):
     cfg = autotune.lookup((11204, 54404), "speed") or {"tile": (32, 32), "delta": 32 * p.h / 3000.0}
     f = torch.from_numpy(p.field[0]).cuda()
     t = gpu.solve(f, p.h, torch.as_tensor(p.src), tile=tuple(cfg["tile"]), delta=cfg["delta"],
-                  grid_blocks=int(cfg.get("grid_blocks", 0)), horizon=int(cfg.get("horizon", 0)))
+                  grid_blocks=int(cfg.get("grid_blocks", 0)), horizon=int(cfg.get("horizon", 0)),
+                  lookahead=int(cfg.get("lookahead", 0)))
     del f
     th = t.cpu().numpy()
     del t
@@ -224,17 +228,18 @@ def test_paper_scale_2d(gpu, O):
 
 def test_rectilinear_full_size(gpu, O):
     """The benchmark's rectilinear leg at full size (512x512x256, depth
-    spacing stretched 5 -> 20 m, 8x8x4 tiles, delta 0.01 s): the oracle's
-    rectilinear residual on a host copy is zero at every point (the unique
-    fixed point), a second solve is bitwise equal, and a scaled-down grid of
-    the same recipe equals the oracle's fast marching bit for bit."""
+    spacing stretched 5 -> 20 m, 8x8x8 tiles, delta 0.0025 s, lookahead 16):
+    the oracle's rectilinear residual on a host copy is zero at every point
+    (the unique fixed point), a solve in another schedule (8x8x4 tiles, delta
+    0.01 s, no lookahead) is bitwise equal, and a scaled-down grid of the same
+    recipe equals the oracle's fast marching bit for bit."""
     small = W.layered_3d(96, 80, 48, h=10.0, seed=2)
     nz, ny, nx = small.field.shape
     zs = W.stretched_coords(nz, 5.0, 4.0 ** (1.0 / (nz - 2)))
     xs, ys = np.arange(nx) * small.h, np.arange(ny) * small.h
     ref = O.solve_rect(small.field, xs, ys, zs, small.src)
     t = gpu.solve_rect(torch.from_numpy(small.field).cuda(), xs, ys, zs, torch.as_tensor(small.src),
-                       tile=(8, 8, 4), delta=0.01)
+                       tile=(8, 8, 8), delta=0.0025, lookahead=16)
     assert np.array_equal(t.cpu().numpy(), ref), "scaled-down rectilinear grid"
     p = W.layered_3d()
     nz, ny, nx = p.field.shape
@@ -242,9 +247,9 @@ def test_rectilinear_full_size(gpu, O):
     xs, ys = np.arange(nx) * p.h, np.arange(ny) * p.h
     f = torch.from_numpy(p.field).cuda()
     src = torch.as_tensor(p.src)
-    t1 = gpu.solve_rect(f, xs, ys, zs, src, tile=(8, 8, 4), delta=0.01)
+    t1 = gpu.solve_rect(f, xs, ys, zs, src, tile=(8, 8, 8), delta=0.0025, lookahead=16)
     t2 = gpu.solve_rect(f, xs, ys, zs, src, tile=(8, 8, 4), delta=0.01)
-    assert torch.equal(t1, t2), "repeat full-size rectilinear solve"
+    assert torch.equal(t1, t2), "full-size rectilinear solve in two schedules"
     th = t1.cpu().numpy()
     del f, t1, t2
     assert np.all(np.isfinite(th))

@@ -125,7 +125,8 @@ def test_schedule_options_and_warm_start(gpu, O):
     xs, ys, zs = W.jittered_coords(48, 1.0, rng), W.jittered_coords(40, 0.7, rng), W.stretched_coords(24, 0.5, 1.05)
     src = np.array([W.flat_index(10, 30, 12, 48, 40)])
     ref = O.solve_rect(f, xs, ys, zs, src)
-    for kw in (dict(horizon=1, delta=0.5), dict(lookahead=3, delta=0.2), dict(grid_blocks=7)):
+    for kw in (dict(horizon=1, delta=0.5), dict(lookahead=3, delta=0.2), dict(grid_blocks=7),
+               dict(lookahead=16, delta=0.02, tile=(8, 8, 4))):
         assert_bitwise(gpu_rect(gpu, f, xs, ys, zs, src, **kw), ref, str(kw))
     # warm start from an upper bound (the sources are fixed again whatever the
     # start holds there) and from a solve stopped by the visit cap
