@@ -144,6 +144,12 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 25
     __shared__ unsigned long long s_face[6];
     __shared__ unsigned int s_done;
     __shared__ int s_next;  // tile handed on by the previous run's publish, or -1
+    // per-workgroup statistics, kept by thread 0 in LDS (not in registers) and
+    // flushed once at exit: [0..3] phase times on the 100 MHz wall clock, as in
+    // the forward solver (claim, stage, readiness passes, write + publish),
+    // [4] visits, [5] points done, [6] passes, [7] hand-offs, [8] the last
+    // phase mark
+    __shared__ unsigned long long s_stat[9];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -154,14 +160,11 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 25
     constexpr int PSTEP[3] = {1, TX, TX * TY};
     constexpr int LSTEP[3] = {1, C::SY, C::SZ};
     constexpr int NAX = C::D3 ? 3 : 2;
-    unsigned long long my_visits = 0, my_done = 0, my_cont = 0, my_passes = 0;
-    // phase times on the 100 MHz wall clock, as in the forward solver:
-    // [0] claim, [1] stage, [2] readiness passes, [3] write + publish
-    unsigned long long ph[4] = {0, 0, 0, 0};
-    unsigned long long tm = wall_clock64();
     if (tid == 0) {
         s_next = -1;
         s_bucket = 0;
+        for (int i = 0; i < 8; ++i) s_stat[i] = 0;
+        s_stat[8] = wall_clock64();
     }
 
     for (;;) {
@@ -169,13 +172,13 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 25
             int64_t bucket = s_bucket;
             int tile = s_next;
             if (tile < 0) tile = claim(S, &bucket);
-            else if (tid == 0) ++my_cont;
+            else if (tid == 0) ++s_stat[7];
             if (tid == 0) {
                 s_next = -1;
                 s_tile = tile;
                 s_bucket = bucket;
                 if (tile >= 0) {
-                    ++my_visits;
+                    ++s_stat[4];
                     uint32_t st = __hip_atomic_fetch_xor(S.tstate + tile, kQ | kR, __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_AGENT);
                     if ((st & (kQ | kR)) != kQ) set_flag(S, kFlagWatchdog);
@@ -191,8 +194,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 25
         const Prob P = prob_of_tile(A.pt, tile);
         if (tid == 0) {
             const unsigned long long now = wall_clock64();
-            ph[0] += now - tm;
-            tm = now;
+            s_stat[0] += now - s_stat[8];
+            s_stat[8] = now;
         }
         const int tl = tile - P.tile_off;
         const int tx = tl % P.ntx, ty = (tl / P.ntx) % P.nty, tz = tl / (P.ntx * P.nty);
@@ -324,8 +327,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 25
         __syncthreads();
         if (tid == 0) {
             const unsigned long long now = wall_clock64();
-            ph[1] += now - tm;
-            tm = now;
+            s_stat[1] += now - s_stat[8];
+            s_stat[8] = now;
         }
 
         // Evaluate points whose children are all done, until no point is left
@@ -557,11 +560,11 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 25
             }
         }
 
-        my_passes += (unsigned long long)passes;
         if (tid == 0) {
+            s_stat[6] += (unsigned long long)passes;
             const unsigned long long now = wall_clock64();
-            ph[2] += now - tm;
-            tm = now;
+            s_stat[2] += now - s_stat[8];
+            s_stat[8] = now;
         }
         // write back newly done points (first visit: every point, NaN = not done)
         unsigned int ndone = 0;
@@ -619,22 +622,22 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 25
             if (tid == 0) s_next = nxt;
         }
         if (tid == 0) {
-            my_done += s_done;
+            s_stat[5] += s_done;
             const unsigned long long now = wall_clock64();
-            ph[3] += now - tm;
-            tm = now;
+            s_stat[3] += now - s_stat[8];
+            s_stat[8] = now;
         }
         __syncthreads();
     }
     if (tid == 0) {
-        ph[0] += wall_clock64() - tm;
+        s_stat[0] += wall_clock64() - s_stat[8];
         for (int i = 0; i < 4; ++i)
-            __hip_atomic_fetch_add(S.counters + 5 + i, ph[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(S.counters + 2, my_passes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(S.counters + 5 + i, s_stat[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(S.counters + 2, s_stat[6], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(S.counters + 10, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(S.counters + 0, my_visits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(S.counters + 1, my_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(S.counters + 12, my_cont, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(S.counters + 0, s_stat[4], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(S.counters + 1, s_stat[5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(S.counters + 12, s_stat[7], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

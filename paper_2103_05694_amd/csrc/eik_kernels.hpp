@@ -331,20 +331,22 @@ __device__ __forceinline__ void st_flags(uint8_t* f, uint32_t v) {
 // Registers are capped for three waves per SIMD with blocks of up to 256
 // threads (three blocks per compute unit) and four with larger blocks (two
 // 512-thread blocks or one 1024-thread block per compute unit).  Compacted
-// passes on 3D tiles (the batched shots) also take four: a few registers
-// spill, but four 256-thread blocks per compute unit keep more tiles in flight
-// (2% more batch throughput); in 2D the spills cost more than that.  The
-// rectilinear operator on 3D tiles keeps two, its 512-thread blocks needing
-// about 160 registers.
+// passes on 3D tiles also take four (four 256-thread blocks per compute unit
+// keep more tiles in flight).  The rectilinear operator on 3D tiles takes four
+// with one point a thread and two with two points a thread on 512 threads
+// (16x8x8 and larger), where it would spill.  The per-workgroup statistics
+// sit in LDS, not in registers, so that these budgets hold without spills.
 template <int TX, int TY, int TZ, int NT, int OP = 0, bool COUNT = false, bool PACK = false>
 __global__ void __launch_bounds__(NT)
-    __attribute__((amdgpu_waves_per_eu(OP == 4 && TZ > 1 && NT == 512 ? 2 : ((NT > 256 || (PACK && TZ > 1)) ? 4 : 3)))) k_solve(SolveArgs A) {
+    __attribute__((amdgpu_waves_per_eu(OP == 4 && TZ > 1 && NT == 512 && TX * TY * TZ > NT ? 2 : ((NT > 256 || (PACK && TZ > 1)) ? 4 : 3)))) k_solve(SolveArgs A) {
     using C = TileCfg<TX, TY, TZ, NT>;
     constexpr int NPT = C::NPT;
     static_assert(NPT == 1 || NPT == 2 || NPT == 4, "1, 2 or 4 points per thread");
     constexpr uint32_t kAllDirty = NPT == 4 ? 0x01010101u : (NPT == 2 ? 0x0101u : 0x01u);
     __shared__ double sT[C::NLDS];
     __shared__ double sQ[PACK ? C::NP : 1];        // constants (PACK: any thread may relax a point)
+    __shared__ double sTin[PACK ? C::NP : 1];      // PACK: the values staged (not held in registers
+                                                   // through the passes)
     __shared__ uint16_t sList[PACK ? C::NP : 1];   // PACK: the pass's dirty points, compacted
     __shared__ int s_cnt[2];                       // PACK: list lengths
     // dirty flags, two buffers (read in one pass, marked for the next); the
@@ -364,23 +366,25 @@ __global__ void __launch_bounds__(NT)
     __shared__ unsigned int s_upd;
     __shared__ unsigned long long s_pend;  // smallest value left beyond the bucket (bits)
     __shared__ int s_next;  // tile handed on by the previous run's publish, or -1
+    // per-workgroup statistics, kept by thread 0 in LDS (not in registers
+    // through the passes) and flushed once at exit: [0..3] phase times on the
+    // 100 MHz wall clock (claim, stage, relax, write + publish), [4] visits,
+    // [5] point updates, [6] passes, [7] hand-offs, [8] the last phase mark
+    __shared__ unsigned long long s_stat[9];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const unsigned long long lanes_below = (1ull << lane) - 1ull;
     (void)lanes_below;
     const Sched& S = A.s;
-    // per-workgroup statistics, flushed once at exit; the phase times use the
-    // 100 MHz wall clock: [0] claim, [1] stage, [2] relax, [3] write + publish
-    unsigned long long my_visits = 0, my_updates = 0, my_passes = 0, my_cont = 0;
-    unsigned long long ph[4] = {0, 0, 0, 0};
     // per-wave work classification (with A.work_ref): operator evaluations,
     // those that lowered the value, those that set the final value
     unsigned long long w_eval = 0, w_imp = 0, w_good = 0;
-    unsigned long long tm = wall_clock64();
     if (tid == 0) {
         s_next = -1;
         s_bucket = 0;
+        for (int i = 0; i < 8; ++i) s_stat[i] = 0;
+        s_stat[8] = wall_clock64();
     }
 
     for (;;) {
@@ -389,7 +393,7 @@ __global__ void __launch_bounds__(NT)
             int64_t bucket = s_bucket;
             int tile = s_next;
             if (tile < 0) tile = claim(S, &bucket);
-            else if (tid == 0) ++my_cont;
+            else if (tid == 0) ++s_stat[7];
             if (tid == 0) {
                 s_next = -1;
                 s_tile = tile;
@@ -420,10 +424,10 @@ __global__ void __launch_bounds__(NT)
         const int tx = tl % P.ntx, ty = (tl / P.ntx) % P.nty, tz = tl / (P.ntx * P.nty);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
         if (tid == 0) {
-            ++my_visits;
+            ++s_stat[4];
             const unsigned long long now = wall_clock64();
-            ph[0] += now - tm;
-            tm = now;
+            s_stat[0] += now - s_stat[8];
+            s_stat[8] = now;
         }
 
         if (st & 0x80000000u) {  // visit cap reached: drop the tile
@@ -568,7 +572,10 @@ __global__ void __launch_bounds__(NT)
                 if (q > 0.0) live |= 1u << j;
                 sT[C::lds(lx, ly, lz)] = tvj;
                 q_own[j] = q;
-                if constexpr (PACK) sQ[p] = q;
+                if constexpr (PACK) {
+                    sQ[p] = q;
+                    sTin[p] = tvj;
+                }
                 t_in[j] = tvj;
                 t_own[j] = tvj;
             }
@@ -616,8 +623,8 @@ __global__ void __launch_bounds__(NT)
         }
         if (tid == 0) {
             const unsigned long long now = wall_clock64();
-            ph[1] += now - tm;
-            tm = now;
+            s_stat[1] += now - s_stat[8];
+            s_stat[8] = now;
         }
 
         // ---- relax until the tile is quiet --------------------------------
@@ -885,8 +892,8 @@ __global__ void __launch_bounds__(NT)
 
         if (tid == 0) {
             const unsigned long long now = wall_clock64();
-            ph[2] += now - tm;
-            tm = now;
+            s_stat[2] += now - s_stat[8];
+            s_stat[8] = now;
         }
         // ---- write back lowered points, gather lowered face minima ---------
         uint32_t chg = 0;  // bit j: point j was stored
@@ -901,8 +908,9 @@ __global__ void __launch_bounds__(NT)
             const double v = sT[L];
             const double nxm = sT[L - 1], nxp = sT[L + 1], nym = sT[L - C::SY], nyp = sT[L + C::SY];
             const double nzm = C::D3 ? sT[L - C::SZ] : inf64(), nzp = C::D3 ? sT[L + C::SZ] : inf64();
+            const double tin = PACK ? sTin[p] : t_in[j];
             if (x < P.nx && y < P.ny && z < P.nz) {
-                if (v < t_in[j]) {
+                if (v < tin) {
                     tstore(A.t + P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x, v);
                     chg |= 1u << j;
                     // a lowered face value matters to the neighbour only where
@@ -918,7 +926,7 @@ __global__ void __launch_bounds__(NT)
                         if (lz == 0 && (kAny || v < nzm)) fmin_[4] = nmin(fmin_[4], v);
                         if (lz == TZ - 1 && (kAny || v < nzp)) fmin_[5] = nmin(fmin_[5], v);
                     }
-                } else if (OP != 0 && OP != 4 && v != t_in[j]) {
+                } else if (OP != 0 && OP != 4 && v != tin) {
                     // an ablation operator raised the value: store it, and with
                     // change tracking activate the neighbours across its faces
                     tstore(A.t + P.pt_off + ((int64_t)z * P.ny + y) * P.nx + x, v);
@@ -966,11 +974,11 @@ __global__ void __launch_bounds__(NT)
             if (tid == 0) s_next = nxt;
         }
         if (tid == 0) {
-            my_updates += s_upd;
-            my_passes += (unsigned long long)passes;
+            s_stat[5] += s_upd;
+            s_stat[6] += (unsigned long long)passes;
             const unsigned long long now = wall_clock64();
-            ph[3] += now - tm;
-            tm = now;
+            s_stat[3] += now - s_stat[8];
+            s_stat[8] = now;
         }
         __syncthreads();
     }
@@ -980,17 +988,17 @@ __global__ void __launch_bounds__(NT)
         __hip_atomic_fetch_add(S.counters + 18, w_good, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (tid == 0) {
-        ph[0] += wall_clock64() - tm;
+        s_stat[0] += wall_clock64() - s_stat[8];
         for (int i = 0; i < 4; ++i)
-            __hip_atomic_fetch_add(S.counters + 5 + i, ph[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(S.counters + 5 + i, s_stat[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(S.counters + 10, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(S.counters + 12, my_cont, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(S.counters + 12, s_stat[7], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (S.timeline)
             __hip_atomic_fetch_max(S.timeline + 1, (unsigned long long)wall_clock64(), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(S.counters + 0, my_visits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(S.counters + 1, my_updates, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(S.counters + 2, my_passes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(S.counters + 0, s_stat[4], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(S.counters + 1, s_stat[5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(S.counters + 2, s_stat[6], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
