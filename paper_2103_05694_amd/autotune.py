@@ -232,7 +232,7 @@ def tune_batch(fields: Sequence[torch.Tensor], h: float, sources, receivers, kin
                     run_adj(tile, fac, gb, pk)
     ba = min(adj, key=lambda r: r["ms"])
     for la in lookaheads:
-        for fac in (0.5, 1.0, 2.0):
+        for fac in (0.5, 2.0 ** -0.5, 1.0, 2.0 ** 0.5, 2.0):
             run_adj(tuple(ba["tile"]), fac * max(ba["delta_factor"], 0.5), ba["grid_blocks"], ba["packed"], la)
     ba = min(adj, key=lambda r: r["ms"])
     if ba["delta_factor"] > 0:
