@@ -99,6 +99,11 @@ def test_solve_rejects_bad_counts_and_options(L):
     o = eik_opts()
     o.horizon = 5
     assert L.eik_solve(ctypes.byref(g), dummy, 1, dummy, None, dummy, None, ctypes.byref(o), None) == -1
+    for bad in (-1, 17, 32):                       # the window reads at most 16 buckets past the lowest
+        o = eik_opts()
+        o.lookahead = bad
+        assert L.eik_solve(ctypes.byref(g), dummy, 1, dummy, None, dummy, None, ctypes.byref(o), None) == -1
+        assert b"lookahead" in L.eik_last_error()
     o = eik_opts()
     o.op = 3                                       # Newton: 2D only
     assert L.eik_solve(ctypes.byref(g), dummy, 1, dummy, None, dummy, None, ctypes.byref(o), None) == -6
