@@ -107,14 +107,18 @@ def tune(field: torch.Tensor, h: float, sources, kind: str = "speed",
                 for gb in grid_blocks:
                     for pk in packed:
                         run(tile, fac, gb, hz, pk)
-    # a lookahead window with narrower buckets, on each tile's best of the first
-    # stage (the tile that wins without a window is often not the one that wins
-    # with it: smaller tiles gain more)
+    # a lookahead window with narrower buckets, on the first stage's best for
+    # each tile and pass structure (what wins without a window often does not
+    # win with it)
     for tile in tiles:
-        best = min((r for r in results if tuple(r["tile"]) == tuple(tile)), key=lambda r: r["ms"])
-        for la in lookaheads:
-            for fac in lookahead_factors:
-                run(tuple(tile), fac, best["grid_blocks"], best["horizon"], best["packed"], la)
+        for pk in packed:
+            rows = [r for r in results if tuple(r["tile"]) == tuple(tile) and r["packed"] == pk]
+            if not rows:
+                continue
+            best = min(rows, key=lambda r: r["ms"])
+            for la in lookaheads:
+                for fac in lookahead_factors:
+                    run(tuple(tile), fac, best["grid_blocks"], best["horizon"], pk, la)
     # refine the best bucket width between its neighbours on the doubling grid
     best = min(results, key=lambda r: r["ms"])
     if best["delta_factor"] > 0:
@@ -193,10 +197,14 @@ def tune_batch(fields: Sequence[torch.Tensor], h: float, sources, receivers, kin
                 for pk in packed:
                     run_fwd(tile, fac, gb, pk)
     for tile in tiles:
-        bt = min((r for r in fwd if tuple(r["tile"]) == tuple(tile)), key=lambda r: r["ms"])
-        for la in lookaheads:
-            for fac in lookahead_factors:
-                run_fwd(tuple(tile), fac, bt["grid_blocks"], bt["packed"], la)
+        for pk in packed:
+            rows = [r for r in fwd if tuple(r["tile"]) == tuple(tile) and r["packed"] == pk]
+            if not rows:
+                continue
+            bt = min(rows, key=lambda r: r["ms"])
+            for la in lookaheads:
+                for fac in lookahead_factors:
+                    run_fwd(tuple(tile), fac, bt["grid_blocks"], pk, la)
     bf = min(fwd, key=lambda r: r["ms"])
     if bf["delta_factor"] > 0:
         for step in (2.0 ** -0.5, 2.0 ** 0.5):

@@ -329,13 +329,14 @@ def test_autotune_candidates_agree(gpu, layered_small):
                       lookaheads=(2, 5), lookahead_factors=(0.5,), reps=1, save=False, log=lambda s: None)
     # tiles x (bucket width 0: grid sizes + other widths: horizons x grid sizes) x pass structures
     grid = 2 * (1 * 2 + 2 * 2 * 2) * 2
-    # then each tile's best with every (lookahead, width) pair
-    window = e["candidates"][grid:grid + 2 * 2]
-    assert [c["lookahead"] for c in window] == [2, 5, 2, 5]
+    # then the best of each tile and pass structure with every (lookahead, width) pair
+    window = e["candidates"][grid:grid + 2 * 2 * 2]
+    assert [c["lookahead"] for c in window] == [2, 5] * 4
+    assert [c["packed"] for c in window] == [False, False, True, True] * 2
     assert all(c["lookahead"] == 0 for c in e["candidates"][:grid])
     # the best bucket width is refined at 2^(+-1/2) of its factor unless it was 0
-    extra = e["candidates"][grid + 4:]
-    assert len(e["candidates"]) in (grid + 4, grid + 6)
+    extra = e["candidates"][grid + 8:]
+    assert len(e["candidates"]) in (grid + 8, grid + 10)
     assert all(c["delta_factor"] not in (0.0, 1.0, 4.0, 0.5) for c in extra)
     assert e["lookahead"] in (0, 2, 5)
     assert tuple(e["tile"]) in ((8, 8, 8), (16, 8, 8))
