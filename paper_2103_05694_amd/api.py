@@ -177,7 +177,11 @@ def solve(field: torch.Tensor, h: float, sources, t0: Optional[torch.Tensor] = N
           work_ref: Optional[torch.Tensor] = None, track_change: bool = False, warm_start: bool = False,
           packed: bool = False):
     """First-arrival times; returns t, or (t, parents) when parents=True.
-    `packed` selects the compacted relaxation passes (EIK_FLAG_PACKED).
+    `delta` (the priority bucket width), `lookahead` (0..16: how many buckets
+    past the lowest open one a claim may take work from), `horizon`, `tile`,
+    `grid_blocks` and `packed` (the compacted relaxation passes,
+    EIK_FLAG_PACKED) only schedule the work: the result is the same bits for
+    every choice (the d-bar operator is monotone and causal).
 
     With warm_start=True the solve resumes from the times in `out` (required):
     any upper bound of the solution, e.g. the output of a solve stopped by
