@@ -53,6 +53,26 @@ def test_noalloc_equals_solve_on_two_calls_the_second_smaller(gpu):
         assert torch.equal(par, par_ref), f"parents, call {i}"
 
 
+def test_noalloc_with_window_and_compacted_passes(gpu):
+    """The benchmark's kind of launch (16x8x8 tiles, compacted passes, a window
+    of 16 buckets) through the allocation-free entry point: the same bits as
+    eik_solve with the same options."""
+    from paper_2103_05694_amd import _lib
+    L = _lib.load()
+    p = W.layered_3d(96, 80, 48, h=10.0, seed=2)
+    print(f"[noalloc] window 16, compacted: {p.nx}x{p.ny}x{p.nz}", flush=True)
+    f = torch.from_numpy(p.field).cuda()
+    src = torch.as_tensor(p.src).cuda()
+    o = gpu.make_opts(0.005, (16, 8, 8), lookahead=16, packed=True)
+    t_ref = torch.empty_like(f)
+    rc, st = _call(L, "eik_solve", f, p.h, src, t_ref, None, o)
+    assert rc == 0 and L.eik_status(st, None) == 0
+    t = torch.full_like(f, -7.0)
+    rc, st = _call(L, "eik_solve_noalloc", f, p.h, src, t, None, o)
+    assert rc == 0 and L.eik_status(st, None) == 0
+    assert torch.equal(t, t_ref)
+
+
 def test_noalloc_resume_and_2d(gpu):
     from paper_2103_05694_amd import _lib
     L = _lib.load()
