@@ -167,11 +167,12 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT > 25
         s_stat[8] = wall_clock64();
     }
 
+    int32_t cur_hint = 0;  // wave 0: the window's lowest bucket as last seen
     for (;;) {
         if (tid < 64) {
             int64_t bucket = s_bucket;
             int tile = s_next;
-            if (tile < 0) tile = claim(S, &bucket);
+            if (tile < 0) tile = claim(S, &bucket, cur_hint);
             else if (tid == 0) ++s_stat[7];
             if (tid == 0) {
                 s_next = -1;

@@ -241,7 +241,13 @@ __device__ __forceinline__ void idle_sleep(int units) {
 // compared with the previous poll's, and any change restarts the count.  So it
 // fires only when nothing has moved for 2^19 polls (about 14 s with the
 // back-off below), however long a valid solve takes.
-__device__ __forceinline__ int claim(const Sched& s, int64_t* bucket) {
+//
+// `cur_hint` is the window's lowest bucket as this workgroup last saw it (0
+// before its first claim; `cur` never decreases).  A poll reads the window's
+// count words at the hint and `cur` itself together, one round trip, and uses
+// them only when `cur` still equals the hint; otherwise it reads again from the
+// new value (the cost of the former sequential read).
+__device__ __forceinline__ int claim(const Sched& s, int64_t* bucket, int32_t& cur_hint) {
     const int lane = threadIdx.x & 63;
     const int win = s.lookahead + 1;
     long long idle = 0;   // polls so far (sets the back-off)
@@ -249,10 +255,15 @@ __device__ __forceinline__ int claim(const Sched& s, int64_t* bucket) {
     unsigned long long seen_w = ~0ull;
     long long seen_cp = -1;
     for (;;) {
-        const int32_t c = ld_rlx(s.cur);
+        const int32_t c = cur_hint;
         const int r = (int)(((int64_t)c + lane) % s.nrings);
         unsigned long long w = kCountBias;  // nothing queued, nothing running
         if (lane < win) w = ld_cr(s, r);
+        const int32_t cnow = ld_rlx(s.cur);
+        if (cnow != c) {
+            cur_hint = cnow;
+            continue;
+        }
         const unsigned long long mask = __ballot(cr_count(w) > 0);
         if (mask) {
             // lowest bucket of the window with queued work
