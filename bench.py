@@ -6,7 +6,9 @@ Headline (the JSON `value`): grid points solved per second for the 3D
 (1 + 0.1 g), one source at the surface centre, FP64).  One step = one complete
 forward solve through the C ABI: per-solve reset, source placement, the
 persistent soft-priority tile kernel and finalisation, with the speed field
-already resident in HBM.  After the timed steps the output is checked: the
+already resident in HBM, in the launch configuration of the tuning cache (tile
+shape, bucket width, lookahead window, pass structure; the command line can
+override each).  After the timed steps the output is checked: the
 device status must be clean and the times' SHA-256 must equal the one the
 oracle's solve gives (tests/golden/layered_512x512x256_seed2.json).
 
