@@ -8,7 +8,7 @@ forward solve through the C ABI: per-solve reset, source placement, the
 persistent soft-priority tile kernel and finalisation, with the speed field
 already resident in HBM, in the launch configuration of the tuning cache (tile
 shape, bucket width, lookahead window, pass structure; the command line can
-override each).  After the timed steps the output is checked: the
+override all but the pass structure).  After the timed steps the output is checked: the
 device status must be clean and the times' SHA-256 must equal the one the
 oracle's solve gives (tests/golden/layered_512x512x256_seed2.json).
 
