@@ -443,12 +443,13 @@ def adjoint_packed(b: Batch, t_packed: torch.Tensor, par_packed: torch.Tensor, g
 
 def solve_batched(fields: Sequence[torch.Tensor], h, sources, kind: str = "speed", parents: bool = False,
                   delta: float = 0.0, tile=None, check_status: bool = True, grid_blocks: int = 0,
-                  horizon: int = 0, packed: bool = False):
+                  horizon: int = 0, packed: bool = False, lookahead: int = 0):
     """Solve independent problems (uneven sizes allowed) in one persistent launch."""
     b = pack(fields, h, sources, kind)
     t = torch.empty(b.npts, dtype=torch.float64, device=b.field.device)
     par = torch.empty(b.npts, dtype=torch.uint8, device=b.field.device) if parents else None
-    solve_packed(b, t, par, delta, tile, grid_blocks=grid_blocks, horizon=horizon, packed=packed)
+    solve_packed(b, t, par, delta, tile, grid_blocks=grid_blocks, horizon=horizon, packed=packed,
+                 lookahead=lookahead)
     if check_status:
         status()
     ts = b.views(t)

@@ -120,11 +120,12 @@ def test_batched_forward_equals_per_problem(gpu, O):
     shots = uneven_shots(9, 1)
     fields = [to_gpu(f) for f, _ in shots]
     srcs = [torch.as_tensor(s) for _, s in shots]
-    ts, pars = gpu.solve_batched(fields, 1.0, srcs, parents=True, delta=0.5)
-    for (f, s), t, p in zip(shots, ts, pars):
-        ref = O.fmm(f, 1.0, s)
-        assert np.array_equal(t.cpu().numpy(), ref)
-        assert np.array_equal(p.cpu().numpy(), O.parents(ref, s))
+    for kw in (dict(delta=0.5), dict(delta=0.1, tile=(16, 8, 8), packed=True, lookahead=16)):
+        ts, pars = gpu.solve_batched(fields, 1.0, srcs, parents=True, **kw)
+        for (f, s), t, p in zip(shots, ts, pars):
+            ref = O.fmm(f, 1.0, s)
+            assert np.array_equal(t.cpu().numpy(), ref), kw
+            assert np.array_equal(p.cpu().numpy(), O.parents(ref, s)), kw
 
 
 def test_batched_adjoint_equals_per_problem(gpu, O):

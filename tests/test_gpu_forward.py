@@ -406,18 +406,20 @@ def test_warm_start_resumes_to_the_same_bits(gpu, O, layered_small):
     ref = O.fmm(p.field, p.h, p.src)
     f = torch.from_numpy(p.field).cuda()
     src = torch.as_tensor(p.src)
-    for tile, delta in (((8, 8, 8), 0.02), ((16, 8, 8), 0.0), ((8, 4, 4), 0.005)):
-        for cap in (3, 60, 400):
-            t = gpu.solve(f, p.h, src, tile=tile, delta=delta, max_tile_visits=cap, check_status=False)
+    for tile, delta, la, pk in (((8, 8, 8), 0.02, 0, False), ((16, 8, 8), 0.0, 0, False), ((8, 4, 4), 0.005, 0, False),
+                                ((16, 8, 8), 0.004, 16, True)):
+        kw = dict(tile=tile, delta=delta, lookahead=la, packed=pk)
+        # caps below the tile count (360 tiles of 16x8x8) leave unvisited tiles at +inf
+        for cap in ((3, 60, 400) if la == 0 else (3, 60, 150)):
+            t = gpu.solve(f, p.h, src, max_tile_visits=cap, check_status=False, **kw)
             assert gpu.status(raise_on_error=False).status == -5
             part = t.cpu().numpy()
             assert np.all(part >= ref) and np.isinf(part).any()
             # stop once more, then finish
-            gpu.solve(f, p.h, src, tile=tile, delta=delta, max_tile_visits=cap, out=t, warm_start=True,
-                      check_status=False)
+            gpu.solve(f, p.h, src, max_tile_visits=cap, out=t, warm_start=True, check_status=False, **kw)
             gpu.status(raise_on_error=False)
-            gpu.solve(f, p.h, src, tile=tile, delta=delta, out=t, warm_start=True)
-            assert_bitwise(t.cpu().numpy(), ref, f"resume tile {tile} delta {delta} cap {cap}")
+            gpu.solve(f, p.h, src, out=t, warm_start=True, **kw)
+            assert_bitwise(t.cpu().numpy(), ref, f"resume {kw} cap {cap}")
     # from the oracle's own partial solve, from a raised exact solution, from +inf
     rng = np.random.default_rng(17)
     part, done = O.fmm_resume(p.field, p.h, p.src, np.full(p.field.shape, np.inf), max_pops=p.npts // 4)
