@@ -490,9 +490,11 @@ def bench_paper_scale(args, torch, eik, W) -> dict:
 def bench_rect(args, torch, eik, W) -> dict:
     """The benchmark's 512x512x256 layered model on a rectilinear grid:
     10 m in x and y, depth spacing stretched geometrically from 5 m to about
-    20 m (eik_solve_rect), same source; 8x8x8 tiles, a 0.0025 s bucket width
-    and a lookahead of 16 buckets, the best of a sweep over four tile shapes,
-    three widths and three lookaheads (0, 8, 16)."""
+    20 m (eik_solve_rect), same source, in the launch configuration of the
+    tuning cache (autotune.tune_rect: four tile shapes, four widths, lookahead
+    0, 8 or 16); without an entry, 8x8x8 tiles, a 0.0025 s bucket width and a
+    lookahead of 16."""
+    from paper_2103_05694_amd import autotune
     import numpy as np
     p = W.layered_3d()
     f = torch.from_numpy(p.field).cuda()
@@ -501,7 +503,9 @@ def bench_rect(args, torch, eik, W) -> dict:
     xs, ys = np.arange(nx) * p.h, np.arange(ny) * p.h
     zs = W.stretched_coords(nz, 5.0, 4.0 ** (1.0 / (nz - 2)))
     out = torch.empty_like(f)
-    kw = dict(tile=(8, 8, 8), delta=0.0025, lookahead=16, out=out, check_status=False)
+    cfg = autotune.lookup_rect(tuple(f.shape), "speed") or {"tile": [8, 8, 8], "delta": 0.0025, "lookahead": 16}
+    tile, delta, la = tuple(cfg["tile"]), float(cfg["delta"]), int(cfg["lookahead"])
+    kw = dict(tile=tile, delta=delta, lookahead=la, out=out, check_status=False)
     eik.solve_rect(f, xs, ys, zs, src, **kw)
     eik.status()
     reps = 5
@@ -514,8 +518,8 @@ def bench_rect(args, torch, eik, W) -> dict:
     st = eik.status()
     return {"workload": "3D 512x512x256 layered speed on a rectilinear grid (dx = dy = 10 m, dz 5 -> 20 m "
                         "geometric), one surface-centre source",
-            "points": p.npts, "ms_per_solve": ms, "points_per_s": p.npts / (ms * 1e-3), "tile": [8, 8, 8],
-            "delta": 0.0025, "lookahead": 16, "visits_per_tile": st.tile_visits / max(st.ntiles, 1), "max_time_s": float(out.max())}
+            "points": p.npts, "ms_per_solve": ms, "points_per_s": p.npts / (ms * 1e-3), "tile": list(tile),
+            "delta": delta, "lookahead": la, "visits_per_tile": st.tile_visits / max(st.ntiles, 1), "max_time_s": float(out.max())}
 
 
 def profile_mode(args, torch, eik, W) -> None:

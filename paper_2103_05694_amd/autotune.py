@@ -262,6 +262,72 @@ def tune_batch(fields: Sequence[torch.Tensor], h: float, sources, receivers, kin
     return entry
 
 
+RECT_TILES = {3: [(8, 8, 8), (8, 8, 4), (16, 8, 4), (16, 8, 8)], 2: [(32, 32), (16, 16), (64, 16)]}
+
+
+def _rect_key(shape: Sequence[int], kind: str) -> str:
+    return f"{ARCH}:rect:{len(shape)}d:{'x'.join(str(int(s)) for s in shape)}:{kind}"
+
+
+def lookup_rect(shape: Sequence[int], kind: str = "speed") -> Optional[dict]:
+    """Cached best configuration of the rectilinear solve for this shape."""
+    return _load().get(_rect_key(shape, kind))
+
+
+def tune_rect(field: torch.Tensor, xs, ys, zs, sources, kind: str = "speed",
+              tiles: Optional[Iterable[Tuple[int, ...]]] = None,
+              delta_factors: Sequence[float] = (0.0625, 0.125, 0.25, 0.5),
+              lookaheads: Sequence[int] = (0, 8, 16), reps: int = 3, save: bool = True, log=print) -> dict:
+    """Time every (tile, bucket width, lookahead) candidate of the rectilinear
+    solve (eik_solve_rect), refine the best width at 2^(+-1/2), and keep the
+    fastest; all candidates must agree bitwise.  The width scale is the median
+    slowness times the median grid spacing times the tile's shortest edge."""
+    import numpy as np
+    nd = field.dim()
+    tiles = list(tiles) if tiles is not None else RECT_TILES[nd]
+    f64 = field.to(torch.float64)
+    slow = (1.0 / f64) if kind == "speed" else f64
+    gaps = np.concatenate([np.diff(np.asarray(c, dtype=np.float64)) for c in (xs, ys, zs) if c is not None
+                           and len(c) > 1])
+    qmed = float(slow.median()) * float(np.median(gaps))
+    out = torch.empty_like(field)
+    ref = None
+    results: List[dict] = []
+
+    def run(tile, fac, la):
+        nonlocal ref
+        delta = fac * qmed * min(tile[:nd])
+        fn = lambda: api.solve_rect(field, xs, ys, zs, sources, kind=kind, delta=delta, tile=tile, out=out,
+                                    lookahead=la, check_status=False)
+        fn()
+        api.status()
+        if ref is None:
+            ref = out.clone()
+        elif not torch.equal(ref, out):
+            raise RuntimeError(f"rectilinear candidate tile={tile} delta={delta} lookahead={la} changed the result")
+        sec = _time(fn, reps)
+        api.status()
+        results.append({"tile": list(tile), "delta": delta, "delta_factor": fac, "lookahead": la, "ms": sec * 1e3})
+        log(f"  rect tile {tile} delta {delta:.4g} ({fac:.3g} x qmed x edge) lookahead {la}: {sec * 1e3:.3f} ms")
+
+    for tile in tiles:
+        for fac in delta_factors:
+            for la in lookaheads:
+                run(tile, fac, la)
+    best = min(results, key=lambda r: r["ms"])
+    for step in (2.0 ** -0.5, 2.0 ** 0.5):
+        run(tuple(best["tile"]), best["delta_factor"] * step, best["lookahead"])
+    best = min(results, key=lambda r: r["ms"])
+    entry = {"tile": best["tile"], "delta": best["delta"], "lookahead": best["lookahead"], "ms": best["ms"],
+             "qmed": qmed, "candidates": results}
+    if save:
+        cache = _load()
+        cache[_rect_key(field.shape, kind)] = entry
+        with open(CACHE, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+    return entry
+
+
 def _main(argv: List[str]) -> int:
     root = os.path.dirname(HERE)
     sys.path.insert(0, root)
@@ -279,6 +345,17 @@ def _main(argv: List[str]) -> int:
             e = tune(f, p.h, torch.as_tensor(p.src), tiles=[(32, 32), (16, 16)],
                      delta_factors=(0.5, 1.0, 2.0, 4.0), grid_blocks=(0,), horizons=(0,), reps=2,
                      log=lambda s: print(s, flush=True))
+            print(json.dumps({k: v for k, v in e.items() if k != "candidates"}), flush=True)
+            continue
+        elif name == "rect512":
+            import numpy as np
+            p = W.layered_3d()
+            nz, ny, nx = p.field.shape
+            xs, ys = np.arange(nx) * p.h, np.arange(ny) * p.h
+            zs = W.stretched_coords(nz, 5.0, 4.0 ** (1.0 / (nz - 2)))
+            f = torch.from_numpy(p.field).cuda()
+            print("tuning the rectilinear layered model (depth spacing 5 -> 20 m)", flush=True)
+            e = tune_rect(f, xs, ys, zs, torch.as_tensor(p.src), log=lambda s: print(s, flush=True))
             print(json.dumps({k: v for k, v in e.items() if k != "candidates"}), flush=True)
             continue
         elif name == "tomo256x32":

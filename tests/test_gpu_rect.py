@@ -164,3 +164,18 @@ def test_bad_coordinates_raise(gpu):
         gpu.solve_rect(f, [0.0, 1.0, 1.0, 2.0, 3.0], np.arange(4.0), sources=[0])
     with pytest.raises(ValueError):
         gpu.solve_rect(f, np.arange(4.0), np.arange(4.0), sources=[0])
+
+
+def test_rect_tuner_candidates_agree(gpu):
+    """The rectilinear tuner times each (tile, width, lookahead) candidate,
+    refines the best width, and refuses any candidate that changes the bits."""
+    from paper_2103_05694_amd import autotune
+    rng = np.random.default_rng(12)
+    f = W.random_field((28, 36, 40), rng, 1500.0, 6000.0, block=4)
+    xs, ys, zs = W.jittered_coords(40, 10.0, rng), W.jittered_coords(36, 10.0, rng), W.stretched_coords(28, 5.0, 1.05)
+    src = torch.tensor([W.flat_index(20, 18, 0, 40, 36)])
+    e = autotune.tune_rect(torch.from_numpy(f).cuda(), xs, ys, zs, src, tiles=[(8, 8, 8), (8, 8, 4)],
+                           delta_factors=(0.25, 1.0), lookaheads=(0, 8), reps=1, save=False, log=lambda s: None)
+    assert len(e["candidates"]) == 2 * 2 * 2 + 2
+    assert tuple(e["tile"]) in ((8, 8, 8), (8, 8, 4)) and e["lookahead"] in (0, 8)
+    assert e["ms"] == min(c["ms"] for c in e["candidates"])
